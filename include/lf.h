@@ -1,0 +1,214 @@
+/*
+ * lf.h -- C ABI of liblf, the MI355X (gfx950) implementation of the hot path of
+ * "Rapid Light Field Depth Estimation with Semi-Global Matching" (Anisimov,
+ * Wasenmueller, Stricker, 2019): Census / l2 matching costs over the views of a
+ * light field, restricted to per-pixel hypothesis bounds from an initial map,
+ * and semi-global matching over them.
+ *
+ * Conventions shared by every entry point
+ *  - Pointers are DEVICE pointers unless the comment says "host".  The caller
+ *    allocates every buffer, including the workspace; the library never
+ *    allocates or frees device memory inside a compute call.
+ *  - Calls are asynchronous on `stream` and never synchronise it; outputs are
+ *    valid once the stream's work has completed.  Concurrent calls on one stream
+ *    are ordered; calls on different streams must not share output or workspace
+ *    buffers.
+ *  - Arguments are validated on the host before anything is enqueued.  On a
+ *    failed check the call returns LF_EINVAL (or LF_ENOSPACE / LF_EUNSUPPORTED),
+ *    enqueues nothing and lf_last_error() describes the reason.  A failed kernel
+ *    launch returns LF_EDEVICE.  Nothing aborts the process.
+ *  - Light field, Sec. 3.1: views L(u,v,s,t) on an S x T angular grid (s
+ *    horizontal, t vertical), stored [T][S][H][pitch], each view row-major.  The
+ *    reference view is (s_hat, t_hat) = ((S-1)/2, (T-1)/2); S and T are odd.
+ *    Hypothesis d places the match of reference pixel (u,v) in view (s,t) at
+ *    (u + (s_hat-s) d, v + (t_hat-t) d), Eq. (1).
+ *  - Hypotheses: `hyp` is a device float32 array of N strictly increasing
+ *    disparities d_0 < ... < d_{N-1} (checked on the host copy by
+ *    lf_validate_hypotheses; a device array is not read back).  2 <= N <= 256.
+ *    Disparity indices are int16 in [0, N-1]; -1 marks an invalid pixel.
+ *  - Bounded volumes ("CSR" layout): pixel p = v*W + u owns the index range
+ *    [d_lo[p], d_hi[p]] and the cells offsets[p] .. offsets[p+1]-1, cell
+ *    offsets[p] + (k - d_lo[p]) holding hypothesis k.  offsets has H*W+1 int64
+ *    entries (an exclusive prefix sum of the range widths).
+ */
+#ifndef LF_H
+#define LF_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LF_ABI_VERSION 1
+#define LF_MAX_HYPOTHESES 256
+
+typedef enum {
+    LF_OK = 0,
+    LF_EINVAL = -1,        /* invalid argument (nothing enqueued) */
+    LF_ENOSPACE = -2,      /* a caller buffer or the workspace is too small */
+    LF_EDEVICE = -3,       /* a HIP call or kernel launch failed */
+    LF_EUNSUPPORTED = -4   /* valid, but outside what this build implements */
+} lf_status;
+
+typedef enum { LF_U8 = 0, LF_F32 = 1 } lf_dtype;
+
+/* Matching cost of the final (bounded) stage: l2, Eq. (12), or Census, Eq. (15). */
+typedef enum { LF_COST_L2 = 0, LF_COST_CENSUS = 1 } lf_cost_kind;
+
+/* A light field resident in device memory. */
+typedef struct {
+    const void* data;   /* [T][S][H][pitch] elements of `dtype` */
+    int32_t S, T, H, W;
+    int32_t pitch;      /* elements between rows, >= W; views are H*pitch apart */
+    int32_t dtype;      /* lf_dtype */
+} lf_view_set;
+
+/* Census window, Sec. 3.2 Eq. (2): win_h rows x win_w columns, both odd and at
+ * most 15, win_h*win_w - 1 <= 64 bits; bit n (LSB first) is the n-th neighbour in
+ * row-major order with the centre skipped, 1 iff centre > neighbour, Eq. (3);
+ * neighbours outside the image are clamped to the edge. */
+typedef struct { int32_t win_h, win_w; } lf_census_window;
+
+/* SGM penalties of Eq. (8) (0 <= P1 <= P2 <= 16383) and the number of path
+ * directions (8: the axis and diagonal directions). */
+typedef struct { int32_t P1, P2, npaths; } lf_sgm_params;
+
+/* Method parameters (Sec. 4.3 gives the paper's values). */
+typedef struct {
+    lf_census_window census;   /* window of the initial-stage Census */
+    lf_sgm_params sgm_init;    /* SGM of the initial map, Sec. 3.4 */
+    lf_sgm_params sgm_final;   /* SGM of the final map, Sec. 3.5 */
+    int32_t phi;               /* fusion confidence threshold, in index steps (>= 1) */
+    int32_t lambda;            /* border half-width of Eq. (11), in index steps (>= 0) */
+    int32_t fill_passes;       /* median hole-filling passes (0..8) */
+    float edge_tau;            /* Sobel |Gx|+|Gy| threshold in 8-bit units; +inf: off */
+    float alpha;               /* cost scale to 8-bit units; <= 0 selects 1 (U8) / 255 (F32) */
+    int32_t cost_kind;         /* lf_cost_kind of the final stage */
+    int32_t median;            /* 0: off, 3: 3x3 median of the final map */
+    int32_t sum_bits;          /* 16 or 32: width of the final aggregated cost */
+} lf_params;
+
+/* ------------------------------------------------------------ utilities */
+int lf_abi_version(void);
+
+/* Reason for the last non-LF_OK status returned on this host thread. */
+const char* lf_last_error(void);
+
+/* host_hyp: host array of N floats.  LF_OK iff 2 <= N <= LF_MAX_HYPOTHESES and the
+ * values are finite and strictly increasing. */
+lf_status lf_validate_hypotheses(const float* host_hyp, int32_t N);
+
+/* Cap applied when the final cost is quantised, C = min(rint(alpha*S), cap):
+ * cap + 2*P2 <= 65535 keeps 16-bit path costs exact beside the +inf sentinel, and
+ * with 16-bit sums npaths*(cap + P2) <= 65535 keeps the sum exact. */
+int32_t lf_cost_cap(int32_t P2_final, int32_t npaths, int32_t sum_bits);
+
+/* Number of cross-lying views |V| used by the initial stage (Sec. 3.4) and, in
+ * host `st` (may be NULL), their (s,t) pairs: (s_hat,0), (s_hat,T-1), (0,t_hat),
+ * (S-1,t_hat) with entries equal to the reference view or repeated dropped. */
+int32_t lf_cross_views(int32_t S, int32_t T, int32_t* st);
+
+/* --------------------------------------------------------------- stages */
+
+/* Census transform of one image, Sec. 3.2 Eq. (2)-(3).
+ * img: [H][pitch] elements of dtype.  out: [H][W] uint64 bit strings. */
+lf_status lf_census(const void* img, int32_t dtype, int32_t H, int32_t W, int32_t pitch,
+                    lf_census_window win, uint64_t* out, hipStream_t stream);
+
+/* Bytes of workspace lf_initial_disparity needs. */
+size_t lf_initial_workspace_size(int32_t S, int32_t T, int32_t H, int32_t W, int32_t N,
+                                 const lf_params* prm);
+
+/* Initial disparity map and borders, Sec. 3.4:
+ *  1. Census of the reference and cross views;
+ *  2. per cross view i, the Census cost of Eq. (7) over all N hypotheses (match
+ *     position of Eq. (1) rounded to the nearest pixel, half to even, clamped),
+ *     SGM over npaths directions, Eq. (8)-(9), WTA, Eq. (10), lowest index on
+ *     ties -> D_i;
+ *  3. fusion with threshold phi (running floored average, invalid is final),
+ *     `fill_passes` median hole-filling passes (lower median of the valid
+ *     8-neighbours), Sobel edge exclusion, borders of Eq. (11) saturated to
+ *     [0, N-1]; invalid and edge pixels get the full range.
+ * d_maps: [|V|][H][W] int16 or NULL; d_init, d_lo, d_hi: [H][W] int16.
+ * ws: at least lf_initial_workspace_size() bytes, 256-byte aligned. */
+lf_status lf_initial_disparity(const lf_view_set* views, const float* hyp, int32_t N,
+                               const lf_params* prm, int16_t* d_maps, int16_t* d_init,
+                               int16_t* d_lo, int16_t* d_hi, void* ws, size_t ws_bytes,
+                               hipStream_t stream);
+
+/* Bytes of workspace lf_cost_volume_bounded needs (prefix-sum scratch, and the
+ * Census strings of every view for LF_COST_CENSUS). */
+size_t lf_cost_workspace_size(int32_t S, int32_t T, int32_t H, int32_t W, int32_t N,
+                              const lf_params* prm);
+
+/* Bounded matching cost over all views, Sec. 3.5:
+ *  offsets <- exclusive prefix sum of the widths d_hi - d_lo + 1 ([H*W+1] int64);
+ *  for every cell (p, k), k in [d_lo[p], d_hi[p]]:
+ *   LF_COST_L2, Eq. (12): S = sum_t sum_s |L_ref(p) - B_{s,t}(p + shift)| in
+ *     float32, t outer, s inner, from +0; shift sh = (float)(s_hat-s)*d_k and
+ *     likewise for t, bilinear B with x0 = floor(sh), fx = sh - x0,
+ *     top = fma(fx,b-a,a), bot = fma(fx,e-c,c), val = fma(fy,bot-top,top), taps
+ *     clamped to the image (the reference view adds exactly 0 and is skipped);
+ *     cost = min(rint(alpha*S), cap) with alpha*S and rint in float32.
+ *   LF_COST_CENSUS, Eq. (15): S = sum over views of the Hamming distance at the
+ *     nearest shift; cost = min(S, cap).
+ *  cap = lf_cost_cap(prm->sgm_final.P2, prm->sgm_final.npaths, prm->sum_bits).
+ * cost: uint16 [cap_cells]; cost_f32: float [cap_cells] or NULL (raw S before
+ * quantisation, for checking).  cap_cells must be >= H*W*N (the count is only
+ * known on the device), else LF_ENOSPACE. */
+lf_status lf_cost_volume_bounded(const lf_view_set* views, const float* hyp, int32_t N,
+                                 const lf_params* prm, const int16_t* d_lo,
+                                 const int16_t* d_hi, int64_t* offsets, uint16_t* cost,
+                                 int64_t cap_cells, float* cost_f32, void* ws,
+                                 size_t ws_bytes, hipStream_t stream);
+
+/* SGM over a bounded volume, Eq. (8)-(9), on the per-pixel ranges (Sec. 3.5):
+ * path costs are computed in the normalised form L_r(p,k) = C(p,k) +
+ * min(L_r(p-r,k), L_r(p-r,k+-1) + P1, m + P2) - m with m = min_j L_r(p-r,j) over
+ * the range of p-r; terms whose index lies outside that range are omitted; the
+ * first pixel of a path takes L_r = C.  csum[cell] = sum over directions.
+ * cost: uint16 [cells], every value <= lf_cost_cap(sgm.P2, sgm.npaths, sum_bits)
+ * (the caller's contract; lf_cost_volume_bounded guarantees it).
+ * csum: uint16 (sum_bits 16) or uint32 (32) [cells], CSR layout of `cost`. */
+lf_status lf_sgm_aggregate(const uint16_t* cost, const int64_t* offsets, const int16_t* d_lo,
+                           const int16_t* d_hi, int32_t H, int32_t W, int32_t N,
+                           lf_sgm_params sgm, int32_t sum_bits, void* csum,
+                           hipStream_t stream);
+
+/* Bytes of workspace lf_wta_subpixel needs. */
+size_t lf_wta_workspace_size(int32_t H, int32_t W);
+
+/* WTA, sub-pixel refinement and median, Sec. 3.5-3.6:
+ *  d_index[p] = lowest k in [d_lo, d_hi] minimising csum (Eq. 10);
+ *  with c-, c0, c+ the sums at k*-1, k*, k*+1, if k*-1 >= d_lo, k*+1 <= d_hi and
+ *  d_hi - d_lo >= 4: o = (float)(c- - c+) / (2*(float)(c- + c+ - 2 c0)) (the
+ *  parabola vertex; Eq. (13) as printed has the sign of the denominator
+ *  reversed), disparity = o >= 0 ? fma(o, d[k*+1]-d[k*], d[k*])
+ *                                : fma(o, d[k*]-d[k*-1], d[k*]); else d[k*];
+ *  median = 3: the 3x3 median (clamp-to-edge) of that map.
+ * d_index: [H][W] int16; disparity: [H][W] float32. */
+lf_status lf_wta_subpixel(const void* csum, int32_t sum_bits, const int64_t* offsets,
+                          const int16_t* d_lo, const int16_t* d_hi, int32_t H, int32_t W,
+                          const float* hyp, int32_t N, int32_t median, int16_t* d_index,
+                          float* disparity, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Bytes of workspace lf_depth needs (every stage's buffers, including a
+ * worst-case H*W*N bounded volume). */
+size_t lf_depth_workspace_size(int32_t S, int32_t T, int32_t H, int32_t W, int32_t N,
+                               const lf_params* prm);
+
+/* The whole method on one light field: lf_initial_disparity ->
+ * lf_cost_volume_bounded -> lf_sgm_aggregate -> lf_wta_subpixel.
+ * disparity: [H][W] float32; d_index: [H][W] int16 (the WTA index of the final
+ * stage, before sub-pixel refinement) or NULL. */
+lf_status lf_depth(const lf_view_set* views, const float* hyp, int32_t N,
+                   const lf_params* prm, float* disparity, int16_t* d_index, void* ws,
+                   size_t ws_bytes, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

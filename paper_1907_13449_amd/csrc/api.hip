@@ -1,0 +1,477 @@
+// Host side of liblf: argument validation, workspace planning and the order of
+// launches for each C-ABI entry point declared in include/lf.h.
+#include "lf_internal.h"
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <string>
+
+namespace {
+
+thread_local std::string g_err;
+
+lf_status fail(lf_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+lf_status device_status(hipError_t e, const char* where) {
+    if (e == hipSuccess) return LF_OK;
+    return fail(LF_EDEVICE, "%s: %s", where, hipGetErrorString(e));
+}
+
+#define LF_CHECK(expr)                                  \
+    do {                                                \
+        lf_status _s = (expr);                          \
+        if (_s != LF_OK) return _s;                     \
+    } while (0)
+
+#define LF_HIP(expr, where)                             \
+    do {                                                \
+        hipError_t _e = (expr);                         \
+        if (_e != hipSuccess) return device_status(_e, where); \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Bump allocator over the caller's workspace: sizes first (base == nullptr),
+// then the same sequence of take() calls hands out the pointers.
+struct Carve {
+    char* base;
+    size_t used = 0;
+    explicit Carve(void* b) : base((char*)b) {}
+    void* take(size_t bytes) {
+        void* p = base ? base + used : nullptr;
+        used += align_up(bytes);
+        return p;
+    }
+};
+
+int cross_views(int S, int T, int* st) {
+    const int sh = (S - 1) / 2, th = (T - 1) / 2;
+    const int cand[4][2] = {{sh, 0}, {sh, T - 1}, {0, th}, {S - 1, th}};
+    int n = 0;
+    for (int i = 0; i < 4; ++i) {
+        const int s = cand[i][0], t = cand[i][1];
+        if (s == sh && t == th) continue;
+        bool dup = false;
+        for (int j = 0; j < n; ++j) dup |= st[2 * j] == s && st[2 * j + 1] == t;
+        if (dup) continue;
+        st[2 * n] = s;
+        st[2 * n + 1] = t;
+        ++n;
+    }
+    return n;
+}
+
+lf_status check_shape(int S, int T, int H, int W, int N) {
+    if (S < 1 || T < 1 || S % 2 == 0 || T % 2 == 0)
+        return fail(LF_EINVAL, "angular grid %dx%d: S and T must be odd and >= 1", S, T);
+    if (S * T < 2) return fail(LF_EINVAL, "a light field needs at least 2 views");
+    if (H < 1 || W < 1) return fail(LF_EINVAL, "image size %dx%d", H, W);
+    if ((int64_t)H * W > (1 << 30)) return fail(LF_EUNSUPPORTED, "image of %d x %d pixels", H, W);
+    if (N < 2) return fail(LF_EINVAL, "N = %d hypotheses (need >= 2)", N);
+    if (N > LF_MAX_HYPOTHESES)
+        return fail(LF_EUNSUPPORTED, "N = %d hypotheses (max %d)", N, LF_MAX_HYPOTHESES);
+    return LF_OK;
+}
+
+lf_status check_views(const lf_view_set* v) {
+    if (!v) return fail(LF_EINVAL, "views is NULL");
+    if (!v->data) return fail(LF_EINVAL, "views->data is NULL");
+    if (v->dtype != LF_U8 && v->dtype != LF_F32) return fail(LF_EINVAL, "dtype %d", v->dtype);
+    if (v->pitch < v->W) return fail(LF_EINVAL, "pitch %d < W %d", v->pitch, v->W);
+    return LF_OK;
+}
+
+lf_status check_window(lf_census_window w) {
+    if (w.win_h < 1 || w.win_w < 1 || w.win_h % 2 == 0 || w.win_w % 2 == 0)
+        return fail(LF_EINVAL, "Census window %dx%d must be odd", w.win_h, w.win_w);
+    if (w.win_h * w.win_w - 1 > 64)
+        return fail(LF_EINVAL, "Census window %dx%d has more than 64 bits", w.win_h, w.win_w);
+    if (w.win_h > 2 * lf::kMaxCensusRadius + 1 || w.win_w > 2 * lf::kMaxCensusRadius + 1)
+        return fail(LF_EUNSUPPORTED, "Census window %dx%d (max side %d)", w.win_h, w.win_w,
+                    2 * lf::kMaxCensusRadius + 1);
+    return LF_OK;
+}
+
+lf_status check_sgm(lf_sgm_params p, const char* which) {
+    if (p.P1 < 0 || p.P2 < p.P1 || p.P2 > 16383)
+        return fail(LF_EINVAL, "%s penalties P1=%d P2=%d (need 0 <= P1 <= P2 <= 16383)", which,
+                    p.P1, p.P2);
+    if (p.npaths != 8)
+        return fail(LF_EUNSUPPORTED, "%s npaths=%d (this build implements 8)", which, p.npaths);
+    return LF_OK;
+}
+
+float eff_alpha(const lf_params* p, int dtype) {
+    return p->alpha > 0.0f ? p->alpha : (dtype == LF_U8 ? 1.0f : 255.0f);
+}
+
+lf_status check_params(const lf_params* p) {
+    if (!p) return fail(LF_EINVAL, "params is NULL");
+    LF_CHECK(check_window(p->census));
+    LF_CHECK(check_sgm(p->sgm_init, "initial"));
+    LF_CHECK(check_sgm(p->sgm_final, "final"));
+    if (p->sgm_init.npaths * (64 + p->sgm_init.P2) > 65535)
+        return fail(LF_EINVAL, "initial P2=%d overflows the 16-bit aggregated Census cost",
+                    p->sgm_init.P2);
+    if (p->phi < 1) return fail(LF_EINVAL, "phi=%d (need >= 1)", p->phi);
+    if (p->lambda < 0) return fail(LF_EINVAL, "lambda=%d (need >= 0)", p->lambda);
+    if (p->fill_passes < 0 || p->fill_passes > 8)
+        return fail(LF_EINVAL, "fill_passes=%d (0..8)", p->fill_passes);
+    if (std::isnan(p->edge_tau)) return fail(LF_EINVAL, "edge_tau is NaN");
+    if (!(p->alpha <= 0.0f || std::isfinite(p->alpha))) return fail(LF_EINVAL, "alpha");
+    if (p->cost_kind != LF_COST_L2 && p->cost_kind != LF_COST_CENSUS)
+        return fail(LF_EINVAL, "cost_kind=%d", p->cost_kind);
+    if (p->median != 0 && p->median != 3) return fail(LF_EINVAL, "median=%d (0 or 3)", p->median);
+    if (p->sum_bits != 16 && p->sum_bits != 32)
+        return fail(LF_EINVAL, "sum_bits=%d (16 or 32)", p->sum_bits);
+    if (p->sum_bits == 16 && 65535 / p->sgm_final.npaths - p->sgm_final.P2 < 1)
+        return fail(LF_EINVAL, "final P2=%d leaves no room in 16-bit sums", p->sgm_final.P2);
+    return LF_OK;
+}
+
+const void* view_ptr(const lf_view_set* v, int s, int t) {
+    const size_t elem = v->dtype == LF_U8 ? 1 : 4;
+    return (const char*)v->data + ((size_t)t * v->S + s) * v->H * v->pitch * elem;
+}
+
+// Workspace plans -----------------------------------------------------------
+struct InitPlan {
+    uint64_t* census;     // [1 + nv][HW]
+    uint16_t* csum;       // [nv][HW][N]
+    int16_t* maps;        // [nv][HW]
+    int16_t* tmp;         // [HW]
+};
+
+size_t plan_initial(Carve& c, int S, int T, int H, int W, int N, InitPlan* p) {
+    int st[8];
+    const int nv = cross_views(S, T, st);
+    const size_t HW = (size_t)H * W;
+    InitPlan q;
+    q.census = (uint64_t*)c.take((1 + nv) * HW * sizeof(uint64_t));
+    q.csum = (uint16_t*)c.take(nv * HW * N * sizeof(uint16_t));
+    q.maps = (int16_t*)c.take(nv * HW * sizeof(int16_t));
+    q.tmp = (int16_t*)c.take(HW * sizeof(int16_t));
+    if (p) *p = q;
+    return c.used;
+}
+
+struct CostPlan {
+    void* scan;           // prefix-sum scratch
+    uint64_t* census_all; // [S*T][HW] (Census kind only)
+};
+
+size_t plan_cost(Carve& c, int S, int T, int H, int W, const lf_params* prm, CostPlan* p) {
+    const size_t HW = (size_t)H * W;
+    CostPlan q;
+    q.scan = c.take(lf::scan_scratch_bytes((int64_t)HW));
+    q.census_all = prm && prm->cost_kind == LF_COST_CENSUS
+                       ? (uint64_t*)c.take((size_t)S * T * HW * sizeof(uint64_t))
+                       : nullptr;
+    if (p) *p = q;
+    return c.used;
+}
+
+struct DepthPlan {
+    int16_t *dinit, *lo, *hi, *d_index;
+    int64_t* offsets;
+    uint16_t* cost;
+    void* csum;
+    float* pre_median;
+    void* init_ws;
+    size_t init_bytes;
+    void* cost_ws;
+    size_t cost_bytes;
+};
+
+size_t plan_depth(void* base, int S, int T, int H, int W, int N, const lf_params* prm,
+                  DepthPlan* p) {
+    Carve c(base);
+    const size_t HW = (size_t)H * W, cells = HW * N;
+    DepthPlan q;
+    q.dinit = (int16_t*)c.take(HW * 2);
+    q.lo = (int16_t*)c.take(HW * 2);
+    q.hi = (int16_t*)c.take(HW * 2);
+    q.d_index = (int16_t*)c.take(HW * 2);
+    q.offsets = (int64_t*)c.take((HW + 1) * 8);
+    q.cost = (uint16_t*)c.take(cells * 2);
+    q.csum = c.take(cells * (prm->sum_bits == 16 ? 2 : 4));
+    q.pre_median = (float*)c.take(lf_wta_workspace_size(H, W));
+    // the initial and the cost stage never run at once: they share one region
+    Carve ci(nullptr), cc(nullptr);
+    q.init_bytes = plan_initial(ci, S, T, H, W, N, nullptr);
+    q.cost_bytes = plan_cost(cc, S, T, H, W, prm, nullptr);
+    q.init_ws = c.take(q.init_bytes > q.cost_bytes ? q.init_bytes : q.cost_bytes);
+    q.cost_ws = q.init_ws;
+    if (p) *p = q;
+    return c.used;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lf_abi_version(void) { return LF_ABI_VERSION; }
+
+const char* lf_last_error(void) { return g_err.c_str(); }
+
+lf_status lf_validate_hypotheses(const float* host_hyp, int32_t N) {
+    if (!host_hyp) return fail(LF_EINVAL, "hypotheses pointer is NULL");
+    if (N < 2 || N > LF_MAX_HYPOTHESES)
+        return fail(N < 2 ? LF_EINVAL : LF_EUNSUPPORTED, "N = %d hypotheses", N);
+    for (int k = 0; k < N; ++k) {
+        if (!std::isfinite(host_hyp[k])) return fail(LF_EINVAL, "hypothesis %d is not finite", k);
+        if (k > 0 && !(host_hyp[k] > host_hyp[k - 1]))
+            return fail(LF_EINVAL, "hypotheses must increase strictly (index %d)", k);
+    }
+    return LF_OK;
+}
+
+int32_t lf_cost_cap(int32_t P2_final, int32_t npaths, int32_t sum_bits) {
+    int32_t cap = 65535 - 2 * P2_final;
+    if (sum_bits == 16 && npaths > 0 && 65535 / npaths - P2_final < cap)
+        cap = 65535 / npaths - P2_final;
+    return cap;
+}
+
+int32_t lf_cross_views(int32_t S, int32_t T, int32_t* st) {
+    int tmp[8];
+    const int n = cross_views(S, T, tmp);
+    if (st)
+        for (int i = 0; i < 2 * n; ++i) st[i] = tmp[i];
+    return n;
+}
+
+lf_status lf_census(const void* img, int32_t dtype, int32_t H, int32_t W, int32_t pitch,
+                    lf_census_window win, uint64_t* out, hipStream_t stream) {
+    if (!img || !out) return fail(LF_EINVAL, "NULL image or output");
+    if (dtype != LF_U8 && dtype != LF_F32) return fail(LF_EINVAL, "dtype %d", dtype);
+    if (H < 1 || W < 1 || pitch < W) return fail(LF_EINVAL, "image %dx%d pitch %d", H, W, pitch);
+    LF_CHECK(check_window(win));
+    lf::CensusBatch b{};
+    b.base = img;
+    b.off[0] = 0;
+    b.n = 1;
+    LF_HIP(lf::launch_census(b, dtype, H, W, pitch, win.win_h, win.win_w, out, stream),
+           "lf_census");
+    return LF_OK;
+}
+
+size_t lf_initial_workspace_size(int32_t S, int32_t T, int32_t H, int32_t W, int32_t N,
+                                 const lf_params* prm) {
+    (void)prm;
+    if (S < 1 || T < 1 || H < 1 || W < 1 || N < 1) return 0;
+    Carve c(nullptr);
+    return plan_initial(c, S, T, H, W, N, nullptr);
+}
+
+lf_status lf_initial_disparity(const lf_view_set* views, const float* hyp, int32_t N,
+                               const lf_params* prm, int16_t* d_maps, int16_t* d_init,
+                               int16_t* d_lo, int16_t* d_hi, void* ws, size_t ws_bytes,
+                               hipStream_t stream) {
+    LF_CHECK(check_views(views));
+    LF_CHECK(check_shape(views->S, views->T, views->H, views->W, N));
+    LF_CHECK(check_params(prm));
+    if (!hyp || !d_init || !d_lo || !d_hi || !ws) return fail(LF_EINVAL, "NULL argument");
+    const int S = views->S, T = views->T, H = views->H, W = views->W;
+    Carve sizer(nullptr);
+    const size_t need = plan_initial(sizer, S, T, H, W, N, nullptr);
+    if (ws_bytes < need) return fail(LF_ENOSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
+    if ((uintptr_t)ws % kAlign) return fail(LF_EINVAL, "workspace not 256-byte aligned");
+    Carve c(ws);
+    InitPlan pl;
+    plan_initial(c, S, T, H, W, N, &pl);
+
+    int st[8];
+    const int nv = cross_views(S, T, st);
+    const int sh = (S - 1) / 2, th = (T - 1) / 2;
+    const size_t HW = (size_t)H * W;
+    int16_t* maps = d_maps ? d_maps : pl.maps;
+
+    // 1. Census of the reference view and the cross views
+    lf::CensusBatch b{};
+    b.base = views->data;
+    b.n = 1 + nv;
+    const int64_t vs = (int64_t)H * views->pitch;
+    b.off[0] = ((int64_t)th * S + sh) * vs;
+    for (int i = 0; i < nv; ++i) b.off[1 + i] = ((int64_t)st[2 * i + 1] * S + st[2 * i]) * vs;
+    LF_HIP(lf::launch_census(b, views->dtype, H, W, views->pitch, prm->census.win_h,
+                             prm->census.win_w, pl.census, stream),
+           "census");
+
+    // 2. full-range Census cost + SGM + WTA per cross view
+    lf::SgmDense a{};
+    a.cref = pl.census;
+    a.cview = pl.census + HW;
+    a.csum = pl.csum;
+    a.dmap = maps;
+    a.nv = nv;
+    for (int i = 0; i < nv; ++i) {
+        a.cs[i] = sh - st[2 * i];
+        a.ct[i] = th - st[2 * i + 1];
+    }
+    LF_HIP(lf::launch_sgm_dense(a, hyp, H, W, N, prm->sgm_init.P1, prm->sgm_init.P2,
+                                prm->sgm_init.npaths, stream),
+           "initial SGM");
+
+    // 3. fusion, hole filling (ping-pong, ending in d_init), edges and borders
+    int16_t* buf[2] = {d_init, pl.tmp};
+    int cur = prm->fill_passes % 2;
+    LF_HIP(lf::launch_fuse(maps, nv, (int)HW, prm->phi, buf[cur], stream), "fusion");
+    for (int f = 0; f < prm->fill_passes; ++f, cur ^= 1)
+        LF_HIP(lf::launch_fill(buf[cur], buf[cur ^ 1], H, W, stream), "fill");
+    LF_HIP(lf::launch_borders(d_init, view_ptr(views, sh, th), views->dtype, views->pitch, H, W,
+                              N, prm->lambda, eff_alpha(prm, views->dtype), prm->edge_tau, d_lo,
+                              d_hi, stream),
+           "borders");
+    return LF_OK;
+}
+
+size_t lf_cost_workspace_size(int32_t S, int32_t T, int32_t H, int32_t W, int32_t N,
+                              const lf_params* prm) {
+    (void)N;
+    if (S < 1 || T < 1 || H < 1 || W < 1) return 0;
+    Carve c(nullptr);
+    return plan_cost(c, S, T, H, W, prm, nullptr);
+}
+
+lf_status lf_cost_volume_bounded(const lf_view_set* views, const float* hyp, int32_t N,
+                                 const lf_params* prm, const int16_t* d_lo,
+                                 const int16_t* d_hi, int64_t* offsets, uint16_t* cost,
+                                 int64_t cap_cells, float* cost_f32, void* ws,
+                                 size_t ws_bytes, hipStream_t stream) {
+    LF_CHECK(check_views(views));
+    LF_CHECK(check_shape(views->S, views->T, views->H, views->W, N));
+    LF_CHECK(check_params(prm));
+    if (!hyp || !d_lo || !d_hi || !offsets || !cost || !ws)
+        return fail(LF_EINVAL, "NULL argument");
+    const int S = views->S, T = views->T, H = views->H, W = views->W;
+    const int64_t HW = (int64_t)H * W;
+    if (cap_cells < HW * N)
+        return fail(LF_ENOSPACE, "cap_cells %lld < H*W*N = %lld", (long long)cap_cells,
+                    (long long)(HW * N));
+    Carve sizer(nullptr);
+    const size_t need = plan_cost(sizer, S, T, H, W, prm, nullptr);
+    if (ws_bytes < need) return fail(LF_ENOSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
+    if ((uintptr_t)ws % kAlign) return fail(LF_EINVAL, "workspace not 256-byte aligned");
+    Carve c(ws);
+    CostPlan pl;
+    plan_cost(c, S, T, H, W, prm, &pl);
+
+    LF_HIP(lf::launch_offsets(d_lo, d_hi, HW, offsets, pl.scan, stream), "offsets");
+    const int32_t cap = lf_cost_cap(prm->sgm_final.P2, prm->sgm_final.npaths, prm->sum_bits);
+    if (prm->cost_kind == LF_COST_L2) {
+        LF_HIP(lf::launch_cost_l2(views->data, views->dtype, S, T, H, W, views->pitch, hyp, N,
+                                  d_lo, d_hi, offsets, eff_alpha(prm, views->dtype), cap, cost,
+                                  cost_f32, cap_cells, stream),
+               "l2 cost");
+    } else {
+        lf::CensusBatch b{};
+        b.base = views->data;
+        b.n = S * T;
+        b.stride = (int64_t)H * views->pitch;
+        if (b.n <= lf::kMaxBatchImages)
+            for (int z = 0; z < b.n; ++z) b.off[z] = z * b.stride;
+        LF_HIP(lf::launch_census(b, views->dtype, H, W, views->pitch, prm->census.win_h,
+                                 prm->census.win_w, pl.census_all, stream),
+               "census (all views)");
+        LF_HIP(lf::launch_cost_census_all(pl.census_all, S, T, H, W, hyp, N, d_lo, d_hi, offsets,
+                                          cap, cost, cost_f32, cap_cells, stream),
+               "census cost");
+    }
+    return LF_OK;
+}
+
+lf_status lf_sgm_aggregate(const uint16_t* cost, const int64_t* offsets, const int16_t* d_lo,
+                           const int16_t* d_hi, int32_t H, int32_t W, int32_t N,
+                           lf_sgm_params sgm, int32_t sum_bits, void* csum,
+                           hipStream_t stream) {
+    if (!cost || !offsets || !d_lo || !d_hi || !csum) return fail(LF_EINVAL, "NULL argument");
+    if (H < 1 || W < 1) return fail(LF_EINVAL, "image %dx%d", H, W);
+    if (N < 2 || N > LF_MAX_HYPOTHESES)
+        return fail(N < 2 ? LF_EINVAL : LF_EUNSUPPORTED, "N = %d", N);
+    LF_CHECK(check_sgm(sgm, "aggregate"));
+    if (sum_bits != 16 && sum_bits != 32) return fail(LF_EINVAL, "sum_bits=%d", sum_bits);
+    if (lf_cost_cap(sgm.P2, sgm.npaths, sum_bits) < 1)
+        return fail(LF_EINVAL, "P2=%d leaves no room for costs in %d-bit sums", sgm.P2, sum_bits);
+    lf::SgmBounded a{cost, offsets, d_lo, d_hi, csum, sum_bits};
+    LF_HIP(lf::launch_sgm_bounded(a, H, W, N, sgm.P1, sgm.P2, sgm.npaths, stream),
+           "bounded SGM");
+    return LF_OK;
+}
+
+size_t lf_wta_workspace_size(int32_t H, int32_t W) {
+    if (H < 1 || W < 1) return 0;
+    return align_up((size_t)H * W * sizeof(float));
+}
+
+lf_status lf_wta_subpixel(const void* csum, int32_t sum_bits, const int64_t* offsets,
+                          const int16_t* d_lo, const int16_t* d_hi, int32_t H, int32_t W,
+                          const float* hyp, int32_t N, int32_t median, int16_t* d_index,
+                          float* disparity, void* ws, size_t ws_bytes, hipStream_t stream) {
+    if (!csum || !offsets || !d_lo || !d_hi || !hyp || !d_index || !disparity)
+        return fail(LF_EINVAL, "NULL argument");
+    if (H < 1 || W < 1) return fail(LF_EINVAL, "image %dx%d", H, W);
+    if (N < 2 || N > LF_MAX_HYPOTHESES)
+        return fail(N < 2 ? LF_EINVAL : LF_EUNSUPPORTED, "N = %d", N);
+    if (sum_bits != 16 && sum_bits != 32) return fail(LF_EINVAL, "sum_bits=%d", sum_bits);
+    if (median != 0 && median != 3) return fail(LF_EINVAL, "median=%d", median);
+    if (median == 3) {
+        if (!ws || ws_bytes < lf_wta_workspace_size(H, W))
+            return fail(LF_ENOSPACE, "workspace %zu < %zu bytes", ws_bytes,
+                        lf_wta_workspace_size(H, W));
+        float* pre = (float*)ws;
+        LF_HIP(lf::launch_wta_subpixel(csum, sum_bits, offsets, d_lo, d_hi, H, W, hyp, d_index,
+                                       pre, stream),
+               "wta/subpixel");
+        LF_HIP(lf::launch_median3(pre, disparity, H, W, stream), "median");
+    } else {
+        LF_HIP(lf::launch_wta_subpixel(csum, sum_bits, offsets, d_lo, d_hi, H, W, hyp, d_index,
+                                       disparity, stream),
+               "wta/subpixel");
+    }
+    return LF_OK;
+}
+
+size_t lf_depth_workspace_size(int32_t S, int32_t T, int32_t H, int32_t W, int32_t N,
+                               const lf_params* prm) {
+    if (!prm || S < 1 || T < 1 || H < 1 || W < 1 || N < 1) return 0;
+    return plan_depth(nullptr, S, T, H, W, N, prm, nullptr);
+}
+
+lf_status lf_depth(const lf_view_set* views, const float* hyp, int32_t N, const lf_params* prm,
+                   float* disparity, int16_t* d_index, void* ws, size_t ws_bytes,
+                   hipStream_t stream) {
+    LF_CHECK(check_views(views));
+    LF_CHECK(check_shape(views->S, views->T, views->H, views->W, N));
+    LF_CHECK(check_params(prm));
+    if (!hyp || !disparity || !ws) return fail(LF_EINVAL, "NULL argument");
+    const int S = views->S, T = views->T, H = views->H, W = views->W;
+    const size_t need = plan_depth(nullptr, S, T, H, W, N, prm, nullptr);
+    if (ws_bytes < need) return fail(LF_ENOSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
+    if ((uintptr_t)ws % kAlign) return fail(LF_EINVAL, "workspace not 256-byte aligned");
+    DepthPlan pl;
+    plan_depth(ws, S, T, H, W, N, prm, &pl);
+    const int64_t cells = (int64_t)H * W * N;
+    LF_CHECK(lf_initial_disparity(views, hyp, N, prm, nullptr, pl.dinit, pl.lo, pl.hi,
+                                  pl.init_ws, pl.init_bytes, stream));
+    LF_CHECK(lf_cost_volume_bounded(views, hyp, N, prm, pl.lo, pl.hi, pl.offsets, pl.cost, cells,
+                                    nullptr, pl.cost_ws, pl.cost_bytes, stream));
+    LF_CHECK(lf_sgm_aggregate(pl.cost, pl.offsets, pl.lo, pl.hi, H, W, N, prm->sgm_final,
+                              prm->sum_bits, pl.csum, stream));
+    LF_CHECK(lf_wta_subpixel(pl.csum, prm->sum_bits, pl.offsets, pl.lo, pl.hi, H, W, hyp, N,
+                             prm->median, d_index ? d_index : pl.d_index, disparity,
+                             pl.pre_median, lf_wta_workspace_size(H, W), stream));
+    return LF_OK;
+}
+
+}  // extern "C"

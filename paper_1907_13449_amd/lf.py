@@ -1,0 +1,261 @@
+"""ctypes binding of liblf (include/lf.h): the same entry points, taking torch
+tensors that live on the GPU.
+
+This module only marshals arguments -- shapes, dtypes, data pointers and the
+current HIP stream -- and raises on a non-zero status.  Every step of the method
+runs in the HIP kernels of liblf.so; there is no fallback: if the library is
+missing or fails to load, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblf.so")
+
+LF_OK, LF_EINVAL, LF_ENOSPACE, LF_EDEVICE, LF_EUNSUPPORTED = 0, -1, -2, -3, -4
+LF_U8, LF_F32 = 0, 1
+LF_COST_L2, LF_COST_CENSUS = 0, 1
+
+EXPORTS = (
+    "lf_abi_version", "lf_last_error", "lf_validate_hypotheses", "lf_cost_cap",
+    "lf_cross_views", "lf_census", "lf_initial_workspace_size", "lf_initial_disparity",
+    "lf_cost_workspace_size", "lf_cost_volume_bounded", "lf_sgm_aggregate",
+    "lf_wta_workspace_size", "lf_wta_subpixel", "lf_depth_workspace_size", "lf_depth",
+)
+
+
+class LFError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"liblf status {status}: {msg}")
+        self.status = status
+
+
+class ViewSet(C.Structure):
+    _fields_ = [("data", C.c_void_p), ("S", C.c_int32), ("T", C.c_int32), ("H", C.c_int32),
+                ("W", C.c_int32), ("pitch", C.c_int32), ("dtype", C.c_int32)]
+
+
+class CensusWindow(C.Structure):
+    _fields_ = [("win_h", C.c_int32), ("win_w", C.c_int32)]
+
+
+class SgmParams(C.Structure):
+    _fields_ = [("P1", C.c_int32), ("P2", C.c_int32), ("npaths", C.c_int32)]
+
+
+class Params(C.Structure):
+    _fields_ = [("census", CensusWindow), ("sgm_init", SgmParams), ("sgm_final", SgmParams),
+                ("phi", C.c_int32), ("lambda_", C.c_int32), ("fill_passes", C.c_int32),
+                ("edge_tau", C.c_float), ("alpha", C.c_float), ("cost_kind", C.c_int32),
+                ("median", C.c_int32), ("sum_bits", C.c_int32)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"liblf.so not built ({LIB_PATH}); run python -m paper_1907_13449_amd.build")
+    lib = C.CDLL(LIB_PATH)
+    lib.lf_last_error.restype = C.c_char_p
+    for name in ("lf_initial_workspace_size", "lf_cost_workspace_size", "lf_wta_workspace_size",
+                 "lf_depth_workspace_size"):
+        getattr(lib, name).restype = C.c_size_t
+    P, i32, i64, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
+    lib.lf_census.argtypes = [P, i32, i32, i32, i32, CensusWindow, P, P]
+    lib.lf_initial_workspace_size.argtypes = [i32, i32, i32, i32, i32, P]
+    lib.lf_initial_disparity.argtypes = [P, P, i32, P, P, P, P, P, P, sz, P]
+    lib.lf_cost_workspace_size.argtypes = [i32, i32, i32, i32, i32, P]
+    lib.lf_cost_volume_bounded.argtypes = [P, P, i32, P, P, P, P, P, i64, P, P, sz, P]
+    lib.lf_sgm_aggregate.argtypes = [P, P, P, P, i32, i32, i32, SgmParams, i32, P, P]
+    lib.lf_wta_workspace_size.argtypes = [i32, i32]
+    lib.lf_wta_subpixel.argtypes = [P, i32, P, P, P, i32, i32, P, i32, i32, P, P, P, sz, P]
+    lib.lf_depth_workspace_size.argtypes = [i32, i32, i32, i32, i32, P]
+    lib.lf_depth.argtypes = [P, P, i32, P, P, P, P, sz, P]
+    lib.lf_validate_hypotheses.argtypes = [P, i32]
+    lib.lf_cost_cap.argtypes = [i32, i32, i32]
+    lib.lf_cross_views.argtypes = [i32, i32, P]
+    return lib
+
+
+lib = _load()
+
+
+# ------------------------------------------------------------------ helpers
+def _check(status):
+    if status != LF_OK:
+        raise LFError(status, lib.lf_last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dev(t, dtype, name):
+    if not (t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise ValueError(f"{name}: expected a contiguous {dtype} CUDA tensor")
+    return t
+
+
+def make_params(p: dict) -> Params:
+    """lf_params from a dict of method parameters (the keys of lfsynth workloads)."""
+    return Params(CensusWindow(p["win_h"], p["win_w"]),
+                  SgmParams(p["P1_init"], p["P2_init"], p["npaths"]),
+                  SgmParams(p["P1_final"], p["P2_final"], p["npaths"]),
+                  p["phi"], p["lam"], p["fill_passes"], float(p["edge_tau"]), float(p["alpha"]),
+                  p["cost_kind"], p["median"], p["sum_bits"])
+
+
+def view_set(views: torch.Tensor) -> ViewSet:
+    """lf_view_set of a [T][S][H][W] uint8/float32 tensor on the GPU."""
+    if views.dim() != 4 or not views.is_cuda or not views.is_contiguous():
+        raise ValueError("views: expected a contiguous [T][S][H][W] CUDA tensor")
+    if views.dtype == torch.uint8:
+        dt = LF_U8
+    elif views.dtype == torch.float32:
+        dt = LF_F32
+    else:
+        raise ValueError("views: uint8 or float32")
+    T, S, H, W = views.shape
+    return ViewSet(views.data_ptr(), S, T, H, W, W, dt)
+
+
+def workspace(nbytes: int, device) -> torch.Tensor:
+    ws = torch.empty(max(int(nbytes), 256) + 256, dtype=torch.uint8, device=device)
+    off = (-ws.data_ptr()) % 256
+    return ws[off:off + max(int(nbytes), 256)]
+
+
+def cross_views(S, T):
+    buf = (C.c_int32 * 8)()
+    n = lib.lf_cross_views(S, T, buf)
+    return [(buf[2 * i], buf[2 * i + 1]) for i in range(n)]
+
+
+def cost_cap(P2_final, npaths, sum_bits):
+    return lib.lf_cost_cap(P2_final, npaths, sum_bits)
+
+
+def validate_hypotheses(hyp_host) -> None:
+    import numpy as np
+    h = np.ascontiguousarray(hyp_host, dtype=np.float32)
+    _check(lib.lf_validate_hypotheses(h.ctypes.data_as(C.c_void_p), h.shape[0]))
+
+
+# ------------------------------------------------------------- entry points
+def lf_census(img: torch.Tensor, win_h: int, win_w: int, out=None, stream=None):
+    if img.dim() != 2 or not img.is_cuda or not img.is_contiguous():
+        raise ValueError("img: contiguous [H][W] CUDA tensor")
+    dt = LF_U8 if img.dtype == torch.uint8 else LF_F32
+    if img.dtype not in (torch.uint8, torch.float32):
+        raise ValueError("img: uint8 or float32")
+    H, W = img.shape
+    if out is None:
+        out = torch.empty((H, W), dtype=torch.int64, device=img.device)
+    _check(lib.lf_census(_ptr(img), dt, H, W, W, CensusWindow(win_h, win_w), _ptr(out),
+                         _stream(stream)))
+    return out
+
+
+def lf_initial_disparity(views: torch.Tensor, hyp: torch.Tensor, params: dict, want_maps=True,
+                         ws=None, stream=None):
+    vs = view_set(views)
+    prm = make_params(params)
+    _dev(hyp, torch.float32, "hyp")
+    N = hyp.shape[0]
+    dev = views.device
+    H, W = vs.H, vs.W
+    nv = len(cross_views(vs.S, vs.T))
+    maps = torch.empty((nv, H, W), dtype=torch.int16, device=dev) if want_maps else None
+    d_init = torch.empty((H, W), dtype=torch.int16, device=dev)
+    d_lo = torch.empty((H, W), dtype=torch.int16, device=dev)
+    d_hi = torch.empty((H, W), dtype=torch.int16, device=dev)
+    need = lib.lf_initial_workspace_size(vs.S, vs.T, H, W, N, C.byref(prm))
+    if ws is None:
+        ws = workspace(need, dev)
+    _check(lib.lf_initial_disparity(C.byref(vs), _ptr(hyp), N, C.byref(prm), _ptr(maps),
+                                    _ptr(d_init), _ptr(d_lo), _ptr(d_hi), _ptr(ws), ws.numel(),
+                                    _stream(stream)))
+    return dict(maps=maps, d_init=d_init, d_lo=d_lo, d_hi=d_hi)
+
+
+def lf_cost_volume_bounded(views: torch.Tensor, hyp: torch.Tensor, params: dict,
+                           d_lo: torch.Tensor, d_hi: torch.Tensor, want_f32=False, ws=None,
+                           stream=None, cap_cells=None):
+    vs = view_set(views)
+    prm = make_params(params)
+    _dev(hyp, torch.float32, "hyp")
+    _dev(d_lo, torch.int16, "d_lo")
+    _dev(d_hi, torch.int16, "d_hi")
+    N = hyp.shape[0]
+    dev = views.device
+    HW = vs.H * vs.W
+    cells = HW * N if cap_cells is None else int(cap_cells)
+    offsets = torch.empty(HW + 1, dtype=torch.int64, device=dev)
+    cost = torch.empty(cells, dtype=torch.int16, device=dev)        # uint16 bits
+    cost_f32 = torch.empty(cells, dtype=torch.float32, device=dev) if want_f32 else None
+    need = lib.lf_cost_workspace_size(vs.S, vs.T, vs.H, vs.W, N, C.byref(prm))
+    if ws is None:
+        ws = workspace(need, dev)
+    _check(lib.lf_cost_volume_bounded(C.byref(vs), _ptr(hyp), N, C.byref(prm), _ptr(d_lo),
+                                      _ptr(d_hi), _ptr(offsets), _ptr(cost), cells,
+                                      _ptr(cost_f32), _ptr(ws), ws.numel(), _stream(stream)))
+    return dict(offsets=offsets, cost=cost, cost_f32=cost_f32)
+
+
+def lf_sgm_aggregate(cost: torch.Tensor, offsets: torch.Tensor, d_lo: torch.Tensor,
+                     d_hi: torch.Tensor, N: int, P1: int, P2: int, npaths: int = 8,
+                     sum_bits: int = 32, csum=None, stream=None):
+    _dev(cost, torch.int16, "cost")
+    _dev(offsets, torch.int64, "offsets")
+    _dev(d_lo, torch.int16, "d_lo")
+    _dev(d_hi, torch.int16, "d_hi")
+    H, W = d_lo.shape
+    if csum is None:
+        csum = torch.empty(cost.numel(), dtype=torch.int16 if sum_bits == 16 else torch.int32,
+                           device=cost.device)
+    _check(lib.lf_sgm_aggregate(_ptr(cost), _ptr(offsets), _ptr(d_lo), _ptr(d_hi), H, W, N,
+                                SgmParams(P1, P2, npaths), sum_bits, _ptr(csum),
+                                _stream(stream)))
+    return csum
+
+
+def lf_wta_subpixel(csum: torch.Tensor, sum_bits: int, offsets: torch.Tensor, d_lo: torch.Tensor,
+                    d_hi: torch.Tensor, hyp: torch.Tensor, median: int = 3, ws=None, stream=None):
+    H, W = d_lo.shape
+    dev = csum.device
+    d_index = torch.empty((H, W), dtype=torch.int16, device=dev)
+    disp = torch.empty((H, W), dtype=torch.float32, device=dev)
+    if ws is None:
+        ws = workspace(lib.lf_wta_workspace_size(H, W), dev)
+    _check(lib.lf_wta_subpixel(_ptr(csum), sum_bits, _ptr(offsets), _ptr(d_lo), _ptr(d_hi), H,
+                               W, _ptr(hyp), hyp.shape[0], median, _ptr(d_index), _ptr(disp),
+                               _ptr(ws), ws.numel(), _stream(stream)))
+    return dict(d_index=d_index, disparity=disp)
+
+
+def depth_workspace_bytes(S, T, H, W, N, params: dict) -> int:
+    prm = make_params(params)
+    return lib.lf_depth_workspace_size(S, T, H, W, N, C.byref(prm))
+
+
+def lf_depth(views: torch.Tensor, hyp: torch.Tensor, params: dict, ws=None, out=None,
+             d_index=None, stream=None):
+    vs = view_set(views)
+    prm = make_params(params)
+    _dev(hyp, torch.float32, "hyp")
+    N = hyp.shape[0]
+    dev = views.device
+    if out is None:
+        out = torch.empty((vs.H, vs.W), dtype=torch.float32, device=dev)
+    if ws is None:
+        ws = workspace(lib.lf_depth_workspace_size(vs.S, vs.T, vs.H, vs.W, N, C.byref(prm)), dev)
+    _check(lib.lf_depth(C.byref(vs), _ptr(hyp), N, C.byref(prm), _ptr(out), _ptr(d_index),
+                        _ptr(ws), ws.numel(), _stream(stream)))
+    return out

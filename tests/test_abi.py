@@ -1,0 +1,124 @@
+"""The C-ABI library loads, exports every entry point include/lf.h declares, and
+rejects invalid arguments on the host before touching the GPU (no compute call
+runs here: every call below fails validation or is a pure host utility)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lf.h")
+
+
+@pytest.fixture(scope="module")
+def lf():
+    from paper_1907_13449_amd import lf as binding
+    return binding
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lf_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_six_calls_and_helpers():
+    names = declared_functions()
+    for n in ("lf_census", "lf_initial_disparity", "lf_cost_volume_bounded", "lf_sgm_aggregate",
+              "lf_wta_subpixel", "lf_depth"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(lf):
+    for name in declared_functions():
+        assert hasattr(lf.lib, name), name
+    assert set(declared_functions()) == set(lf.EXPORTS)
+    assert lf.lib.lf_abi_version() == 1
+
+
+def test_struct_layouts_match_header(lf):
+    # lf_view_set: pointer + 6 int32; lf_params: 2 + 3 + 3 + 3 int32 + 2 float + 3 int32
+    assert C.sizeof(lf.ViewSet) == 8 + 6 * 4
+    assert C.sizeof(lf.Params) == (2 + 3 + 3 + 3) * 4 + 2 * 4 + 3 * 4
+
+
+def test_validate_hypotheses(lf):
+    lf.validate_hypotheses(np.linspace(-4, 4, 100, dtype=np.float32))
+    with pytest.raises(lf.LFError):
+        lf.validate_hypotheses(np.array([0.0, 0.0, 1.0], np.float32))
+    with pytest.raises(lf.LFError):
+        lf.validate_hypotheses(np.array([0.0], np.float32))
+    with pytest.raises(lf.LFError):
+        lf.validate_hypotheses(np.array([0.0, np.nan], np.float32))
+    with pytest.raises(lf.LFError):
+        lf.validate_hypotheses(np.linspace(0, 1, 257, dtype=np.float32))
+
+
+def test_cross_views_and_cost_cap(lf):
+    assert lf.cross_views(9, 9) == [(4, 0), (4, 8), (0, 4), (8, 4)]
+    assert lf.cross_views(11, 1) == [(0, 0), (10, 0)]
+    assert lf.cost_cap(35, 8, 32) == 65535 - 70
+    assert lf.cost_cap(120, 8, 16) == 65535 // 8 - 120
+
+
+def _params(lf, **kw):
+    import lfsynth
+    p = lfsynth._params()
+    p.update(kw)
+    return lf.make_params(p)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(S=4, T=5), dict(S=1, T=1), dict(N=1), dict(N=300), dict(H=0),
+])
+def test_initial_disparity_rejects_bad_shapes(lf, bad):
+    shape = dict(S=5, T=5, H=16, W=16, N=8)
+    shape.update(bad)
+    vs = lf.ViewSet(0x1000, shape["S"], shape["T"], shape["H"], shape["W"], shape["W"], lf.LF_U8)
+    prm = _params(lf)
+    st = lf.lib.lf_initial_disparity(C.byref(vs), C.c_void_p(0x1000), shape["N"], C.byref(prm),
+                                     None, C.c_void_p(0x1000), C.c_void_p(0x1000),
+                                     C.c_void_p(0x1000), C.c_void_p(0x1000), 1 << 30, None)
+    assert st in (lf.LF_EINVAL, lf.LF_EUNSUPPORTED)
+    assert lf.lib.lf_last_error()
+
+
+@pytest.mark.parametrize("bad", [
+    dict(win_h=4), dict(win_h=9, win_w=9), dict(win_h=17, win_w=3), dict(P1_init=50, P2_init=40),
+    dict(npaths=4), dict(phi=0), dict(lam=-1), dict(median=5), dict(sum_bits=8),
+    dict(cost_kind=7), dict(P2_init=9000),
+])
+def test_params_rejected(lf, bad):
+    vs = lf.ViewSet(0x1000, 5, 5, 16, 16, 16, lf.LF_U8)
+    prm = _params(lf, **bad)
+    st = lf.lib.lf_depth(C.byref(vs), C.c_void_p(0x1000), 8, C.byref(prm), C.c_void_p(0x1000),
+                         None, C.c_void_p(0x1000), 1 << 40, None)
+    assert st in (lf.LF_EINVAL, lf.LF_EUNSUPPORTED)
+
+
+def test_workspace_too_small_is_enospace(lf):
+    vs = lf.ViewSet(0x1000, 5, 5, 16, 16, 16, lf.LF_U8)
+    prm = _params(lf)
+    st = lf.lib.lf_depth(C.byref(vs), C.c_void_p(0x1000), 8, C.byref(prm), C.c_void_p(0x1000),
+                         None, C.c_void_p(0x1000), 1024, None)
+    assert st == lf.LF_ENOSPACE
+
+
+def test_cost_volume_capacity_is_checked(lf):
+    vs = lf.ViewSet(0x1000, 5, 5, 16, 16, 16, lf.LF_U8)
+    prm = _params(lf)
+    p = C.c_void_p(0x1000)
+    st = lf.lib.lf_cost_volume_bounded(C.byref(vs), p, 8, C.byref(prm), p, p, p, p,
+                                       16 * 16 * 8 - 1, None, p, 1 << 30, None)
+    assert st == lf.LF_ENOSPACE
+
+
+def test_workspace_sizes_are_positive_and_monotone(lf):
+    prm = _params(lf)
+    a = lf.lib.lf_depth_workspace_size(5, 5, 96, 96, 32, C.byref(prm))
+    b = lf.lib.lf_depth_workspace_size(9, 9, 512, 512, 100, C.byref(prm))
+    assert 0 < a < b
+    # 9x9x512^2, N=100: dominated by the four 16-bit initial volumes (4*512*512*100*2 B)
+    assert b > 4 * 512 * 512 * 100 * 2
