@@ -111,6 +111,18 @@ int32_t lf_cost_cap(int32_t P2_final, int32_t npaths, int32_t sum_bits);
  * (S-1,t_hat) with entries equal to the reference view or repeated dropped. */
 int32_t lf_cross_views(int32_t S, int32_t T, int32_t* st);
 
+/* Stage timing for measurement.  lf_profile_enable(1) makes every later call
+ * record a HIP event pair on its stream around each group of launches (stages:
+ * 0 census, 1 initial SGM, 2 fusion/fill/borders, 3 offsets, 4 bounded cost,
+ * 5 bounded SGM, 6 WTA/sub-pixel/median); returns the previous setting.
+ * lf_profile_read waits for the recorded events, writes per-stage milliseconds
+ * and launch counts (host arrays of n entries, either may be NULL), forgets the
+ * records and returns the number of stages.  Event objects are created on first
+ * use and reused; no device memory is allocated. */
+int32_t lf_profile_enable(int32_t on);
+int32_t lf_profile_read(double* ms, int64_t* launches, int32_t n);
+const char* lf_profile_stage_name(int32_t i);
+
 /* --------------------------------------------------------------- stages */
 
 /* Census transform of one image, Sec. 3.2 Eq. (2)-(3).
@@ -165,6 +177,10 @@ lf_status lf_cost_volume_bounded(const lf_view_set* views, const float* hyp, int
                                  int64_t cap_cells, float* cost_f32, void* ws,
                                  size_t ws_bytes, hipStream_t stream);
 
+/* Bytes of workspace lf_sgm_aggregate needs: npaths * H*W*N 16-bit path costs
+ * (every direction keeps its own path costs; they are summed at the end). */
+size_t lf_sgm_workspace_size(int32_t H, int32_t W, int32_t N, int32_t npaths);
+
 /* SGM over a bounded volume, Eq. (8)-(9), on the per-pixel ranges (Sec. 3.5):
  * path costs are computed in the normalised form L_r(p,k) = C(p,k) +
  * min(L_r(p-r,k), L_r(p-r,k+-1) + P1, m + P2) - m with m = min_j L_r(p-r,j) over
@@ -172,11 +188,12 @@ lf_status lf_cost_volume_bounded(const lf_view_set* views, const float* hyp, int
  * first pixel of a path takes L_r = C.  csum[cell] = sum over directions.
  * cost: uint16 [cells], every value <= lf_cost_cap(sgm.P2, sgm.npaths, sum_bits)
  * (the caller's contract; lf_cost_volume_bounded guarantees it).
- * csum: uint16 (sum_bits 16) or uint32 (32) [cells], CSR layout of `cost`. */
+ * csum: uint16 (sum_bits 16) or uint32 (32) [cells], CSR layout of `cost`.
+ * ws: at least lf_sgm_workspace_size() bytes. */
 lf_status lf_sgm_aggregate(const uint16_t* cost, const int64_t* offsets, const int16_t* d_lo,
                            const int16_t* d_hi, int32_t H, int32_t W, int32_t N,
-                           lf_sgm_params sgm, int32_t sum_bits, void* csum,
-                           hipStream_t stream);
+                           lf_sgm_params sgm, int32_t sum_bits, void* csum, void* ws,
+                           size_t ws_bytes, hipStream_t stream);
 
 /* Bytes of workspace lf_wta_subpixel needs. */
 size_t lf_wta_workspace_size(int32_t H, int32_t W);

@@ -5,7 +5,9 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <mutex>
 #include <string>
+#include <vector>
 
 namespace {
 
@@ -37,6 +39,60 @@ lf_status device_status(hipError_t e, const char* where) {
         hipError_t _e = (expr);                         \
         if (_e != hipSuccess) return device_status(_e, where); \
     } while (0)
+
+// Opt-in stage timing: a HIP event pair recorded on the call's stream around
+// each group of launches.  Off by default; when off nothing is recorded.
+namespace prof {
+enum Stage { kCensus, kSgmInit, kBorders, kOffsets, kCost, kSgmFinal, kWta, kNumStages };
+const char* const kNames[kNumStages] = {"census", "sgm_initial", "fuse_fill_borders",
+                                        "offsets", "cost_bounded", "sgm_bounded",
+                                        "wta_subpixel_median"};
+struct Rec {
+    int stage, launches;
+    hipEvent_t a, b;
+};
+std::mutex mu;
+bool on = false;
+std::vector<Rec> pending;
+std::vector<hipEvent_t> pool;
+
+hipEvent_t get_event() {
+    if (!pool.empty()) {
+        hipEvent_t e = pool.back();
+        pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+struct Scope {
+    int stage, launches;
+    hipStream_t st;
+    hipEvent_t a = nullptr;
+    Scope(int stage_, hipStream_t st_, int launches_) : stage(stage_), launches(launches_), st(st_) {
+        std::lock_guard<std::mutex> g(mu);
+        if (!on) return;
+        a = get_event();
+        if (a && hipEventRecord(a, st) != hipSuccess) {
+            pool.push_back(a);
+            a = nullptr;
+        }
+    }
+    ~Scope() {
+        if (!a) return;
+        std::lock_guard<std::mutex> g(mu);
+        hipEvent_t b = get_event();
+        if (b && hipEventRecord(b, st) == hipSuccess) {
+            pending.push_back(Rec{stage, launches, a, b});
+        } else {
+            pool.push_back(a);
+            if (b) pool.push_back(b);
+        }
+    }
+};
+}  // namespace prof
 
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -147,18 +203,21 @@ const void* view_ptr(const lf_view_set* v, int s, int t) {
 // Workspace plans -----------------------------------------------------------
 struct InitPlan {
     uint64_t* census;     // [1 + nv][HW]
-    uint16_t* csum;       // [nv][HW][N]
+    void* paths;          // per-direction path costs of the SGM
     int16_t* maps;        // [nv][HW]
     int16_t* tmp;         // [HW]
 };
 
-size_t plan_initial(Carve& c, int S, int T, int H, int W, int N, InitPlan* p) {
+size_t plan_initial(Carve& c, int S, int T, int H, int W, int N, const lf_params* prm,
+                    InitPlan* p) {
     int st[8];
     const int nv = cross_views(S, T, st);
     const size_t HW = (size_t)H * W;
     InitPlan q;
     q.census = (uint64_t*)c.take((1 + nv) * HW * sizeof(uint64_t));
-    q.csum = (uint16_t*)c.take(nv * HW * N * sizeof(uint16_t));
+    q.paths = c.take(lf::sgm_dense_scratch_bytes(nv, H, W, N, prm->sgm_init.npaths,
+                                                 prm->census.win_h * prm->census.win_w - 1,
+                                                 prm->sgm_init.P2));
     q.maps = (int16_t*)c.take(nv * HW * sizeof(int16_t));
     q.tmp = (int16_t*)c.take(HW * sizeof(int16_t));
     if (p) *p = q;
@@ -191,6 +250,8 @@ struct DepthPlan {
     size_t init_bytes;
     void* cost_ws;
     size_t cost_bytes;
+    void* sgm_ws;
+    size_t sgm_bytes;
 };
 
 size_t plan_depth(void* base, int S, int T, int H, int W, int N, const lf_params* prm,
@@ -208,10 +269,14 @@ size_t plan_depth(void* base, int S, int T, int H, int W, int N, const lf_params
     q.pre_median = (float*)c.take(lf_wta_workspace_size(H, W));
     // the initial and the cost stage never run at once: they share one region
     Carve ci(nullptr), cc(nullptr);
-    q.init_bytes = plan_initial(ci, S, T, H, W, N, nullptr);
+    q.init_bytes = plan_initial(ci, S, T, H, W, N, prm, nullptr);
     q.cost_bytes = plan_cost(cc, S, T, H, W, prm, nullptr);
-    q.init_ws = c.take(q.init_bytes > q.cost_bytes ? q.init_bytes : q.cost_bytes);
+    q.sgm_bytes = lf_sgm_workspace_size(H, W, N, prm->sgm_final.npaths);
+    size_t shared = q.init_bytes > q.cost_bytes ? q.init_bytes : q.cost_bytes;
+    if (q.sgm_bytes > shared) shared = q.sgm_bytes;
+    q.init_ws = c.take(shared);
     q.cost_ws = q.init_ws;
+    q.sgm_ws = q.init_ws;
     if (p) *p = q;
     return c.used;
 }
@@ -221,6 +286,43 @@ size_t plan_depth(void* base, int S, int T, int H, int W, int N, const lf_params
 extern "C" {
 
 int lf_abi_version(void) { return LF_ABI_VERSION; }
+
+int32_t lf_profile_enable(int32_t on) {
+    std::lock_guard<std::mutex> g(prof::mu);
+    const int32_t was = prof::on;
+    prof::on = on != 0;
+    return was;
+}
+
+int32_t lf_profile_read(double* ms, int64_t* launches, int32_t n) {
+    std::vector<prof::Rec> recs;
+    {
+        std::lock_guard<std::mutex> g(prof::mu);
+        recs.swap(prof::pending);
+    }
+    for (int i = 0; i < n && i < prof::kNumStages; ++i) {
+        if (ms) ms[i] = 0.0;
+        if (launches) launches[i] = 0;
+    }
+    for (const prof::Rec& r : recs) {
+        float t = 0.0f;
+        if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&t, r.a, r.b) == hipSuccess &&
+            r.stage < n) {
+            if (ms) ms[r.stage] += t;
+            if (launches) launches[r.stage] += r.launches;
+        }
+    }
+    std::lock_guard<std::mutex> g(prof::mu);
+    for (const prof::Rec& r : recs) {
+        prof::pool.push_back(r.a);
+        prof::pool.push_back(r.b);
+    }
+    return prof::kNumStages;
+}
+
+const char* lf_profile_stage_name(int32_t i) {
+    return i >= 0 && i < prof::kNumStages ? prof::kNames[i] : "";
+}
 
 const char* lf_last_error(void) { return g_err.c_str(); }
 
@@ -270,8 +372,9 @@ size_t lf_initial_workspace_size(int32_t S, int32_t T, int32_t H, int32_t W, int
                                  const lf_params* prm) {
     (void)prm;
     if (S < 1 || T < 1 || H < 1 || W < 1 || N < 1) return 0;
+    if (!prm) return 0;
     Carve c(nullptr);
-    return plan_initial(c, S, T, H, W, N, nullptr);
+    return plan_initial(c, S, T, H, W, N, prm, nullptr);
 }
 
 lf_status lf_initial_disparity(const lf_view_set* views, const float* hyp, int32_t N,
@@ -284,12 +387,12 @@ lf_status lf_initial_disparity(const lf_view_set* views, const float* hyp, int32
     if (!hyp || !d_init || !d_lo || !d_hi || !ws) return fail(LF_EINVAL, "NULL argument");
     const int S = views->S, T = views->T, H = views->H, W = views->W;
     Carve sizer(nullptr);
-    const size_t need = plan_initial(sizer, S, T, H, W, N, nullptr);
+    const size_t need = plan_initial(sizer, S, T, H, W, N, prm, nullptr);
     if (ws_bytes < need) return fail(LF_ENOSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
     if ((uintptr_t)ws % kAlign) return fail(LF_EINVAL, "workspace not 256-byte aligned");
     Carve c(ws);
     InitPlan pl;
-    plan_initial(c, S, T, H, W, N, &pl);
+    plan_initial(c, S, T, H, W, N, prm, &pl);
 
     int st[8];
     const int nv = cross_views(S, T, st);
@@ -304,26 +407,33 @@ lf_status lf_initial_disparity(const lf_view_set* views, const float* hyp, int32
     const int64_t vs = (int64_t)H * views->pitch;
     b.off[0] = ((int64_t)th * S + sh) * vs;
     for (int i = 0; i < nv; ++i) b.off[1 + i] = ((int64_t)st[2 * i + 1] * S + st[2 * i]) * vs;
+    {
+        prof::Scope _ps(prof::kCensus, stream, 1);
     LF_HIP(lf::launch_census(b, views->dtype, H, W, views->pitch, prm->census.win_h,
-                             prm->census.win_w, pl.census, stream),
-           "census");
+                                 prm->census.win_w, pl.census, stream),
+               "census");
+    }
 
     // 2. full-range Census cost + SGM + WTA per cross view
     lf::SgmDense a{};
     a.cref = pl.census;
     a.cview = pl.census + HW;
-    a.csum = pl.csum;
     a.dmap = maps;
     a.nv = nv;
     for (int i = 0; i < nv; ++i) {
         a.cs[i] = sh - st[2 * i];
         a.ct[i] = th - st[2 * i + 1];
     }
+    {
+        prof::Scope _ps(prof::kSgmInit, stream, 2);
     LF_HIP(lf::launch_sgm_dense(a, hyp, H, W, N, prm->sgm_init.P1, prm->sgm_init.P2,
-                                prm->sgm_init.npaths, stream),
-           "initial SGM");
+                                    prm->sgm_init.npaths,
+                                    prm->census.win_h * prm->census.win_w - 1, pl.paths, stream),
+               "initial SGM");
+    }
 
     // 3. fusion, hole filling (ping-pong, ending in d_init), edges and borders
+    prof::Scope _ps(prof::kBorders, stream, 2 + prm->fill_passes);
     int16_t* buf[2] = {d_init, pl.tmp};
     int cur = prm->fill_passes % 2;
     LF_HIP(lf::launch_fuse(maps, nv, (int)HW, prm->phi, buf[cur], stream), "fusion");
@@ -367,8 +477,12 @@ lf_status lf_cost_volume_bounded(const lf_view_set* views, const float* hyp, int
     CostPlan pl;
     plan_cost(c, S, T, H, W, prm, &pl);
 
+    {
+        prof::Scope _ps(prof::kOffsets, stream, 3);
     LF_HIP(lf::launch_offsets(d_lo, d_hi, HW, offsets, pl.scan, stream), "offsets");
+    }
     const int32_t cap = lf_cost_cap(prm->sgm_final.P2, prm->sgm_final.npaths, prm->sum_bits);
+    prof::Scope _ps(prof::kCost, stream, prm->cost_kind == LF_COST_L2 ? 1 : 2);
     if (prm->cost_kind == LF_COST_L2) {
         LF_HIP(lf::launch_cost_l2(views->data, views->dtype, S, T, H, W, views->pitch, hyp, N,
                                   d_lo, d_hi, offsets, eff_alpha(prm, views->dtype), cap, cost,
@@ -391,21 +505,33 @@ lf_status lf_cost_volume_bounded(const lf_view_set* views, const float* hyp, int
     return LF_OK;
 }
 
+size_t lf_sgm_workspace_size(int32_t H, int32_t W, int32_t N, int32_t npaths) {
+    if (H < 1 || W < 1 || N < 1 || npaths < 1) return 0;
+    return align_up(lf::sgm_bounded_scratch_bytes(H, W, N, npaths));
+}
+
 lf_status lf_sgm_aggregate(const uint16_t* cost, const int64_t* offsets, const int16_t* d_lo,
                            const int16_t* d_hi, int32_t H, int32_t W, int32_t N,
-                           lf_sgm_params sgm, int32_t sum_bits, void* csum,
-                           hipStream_t stream) {
-    if (!cost || !offsets || !d_lo || !d_hi || !csum) return fail(LF_EINVAL, "NULL argument");
+                           lf_sgm_params sgm, int32_t sum_bits, void* csum, void* ws,
+                           size_t ws_bytes, hipStream_t stream) {
+    if (!cost || !offsets || !d_lo || !d_hi || !csum || !ws)
+        return fail(LF_EINVAL, "NULL argument");
     if (H < 1 || W < 1) return fail(LF_EINVAL, "image %dx%d", H, W);
+    if ((int64_t)H * W > (1 << 30)) return fail(LF_EUNSUPPORTED, "image of %d x %d pixels", H, W);
     if (N < 2 || N > LF_MAX_HYPOTHESES)
         return fail(N < 2 ? LF_EINVAL : LF_EUNSUPPORTED, "N = %d", N);
     LF_CHECK(check_sgm(sgm, "aggregate"));
     if (sum_bits != 16 && sum_bits != 32) return fail(LF_EINVAL, "sum_bits=%d", sum_bits);
     if (lf_cost_cap(sgm.P2, sgm.npaths, sum_bits) < 1)
         return fail(LF_EINVAL, "P2=%d leaves no room for costs in %d-bit sums", sgm.P2, sum_bits);
+    const size_t need = lf_sgm_workspace_size(H, W, N, sgm.npaths);
+    if (ws_bytes < need) return fail(LF_ENOSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
     lf::SgmBounded a{cost, offsets, d_lo, d_hi, csum, sum_bits};
-    LF_HIP(lf::launch_sgm_bounded(a, H, W, N, sgm.P1, sgm.P2, sgm.npaths, stream),
-           "bounded SGM");
+    {
+        prof::Scope _ps(prof::kSgmFinal, stream, 2);
+        LF_HIP(lf::launch_sgm_bounded(a, H, W, N, sgm.P1, sgm.P2, sgm.npaths, ws, stream),
+               "bounded SGM");
+    }
     return LF_OK;
 }
 
@@ -425,6 +551,10 @@ lf_status lf_wta_subpixel(const void* csum, int32_t sum_bits, const int64_t* off
         return fail(N < 2 ? LF_EINVAL : LF_EUNSUPPORTED, "N = %d", N);
     if (sum_bits != 16 && sum_bits != 32) return fail(LF_EINVAL, "sum_bits=%d", sum_bits);
     if (median != 0 && median != 3) return fail(LF_EINVAL, "median=%d", median);
+    if (median == 3 && (!ws || ws_bytes < lf_wta_workspace_size(H, W)))
+        return fail(LF_ENOSPACE, "workspace %zu < %zu bytes", ws_bytes,
+                    lf_wta_workspace_size(H, W));
+    prof::Scope _ps(prof::kWta, stream, median == 3 ? 2 : 1);
     if (median == 3) {
         if (!ws || ws_bytes < lf_wta_workspace_size(H, W))
             return fail(LF_ENOSPACE, "workspace %zu < %zu bytes", ws_bytes,
@@ -467,7 +597,7 @@ lf_status lf_depth(const lf_view_set* views, const float* hyp, int32_t N, const 
     LF_CHECK(lf_cost_volume_bounded(views, hyp, N, prm, pl.lo, pl.hi, pl.offsets, pl.cost, cells,
                                     nullptr, pl.cost_ws, pl.cost_bytes, stream));
     LF_CHECK(lf_sgm_aggregate(pl.cost, pl.offsets, pl.lo, pl.hi, H, W, N, prm->sgm_final,
-                              prm->sum_bits, pl.csum, stream));
+                              prm->sum_bits, pl.csum, pl.sgm_ws, pl.sgm_bytes, stream));
     LF_CHECK(lf_wta_subpixel(pl.csum, prm->sum_bits, pl.offsets, pl.lo, pl.hi, H, W, hyp, N,
                              prm->median, d_index ? d_index : pl.d_index, disparity,
                              pl.pre_median, lf_wta_workspace_size(H, W), stream));

@@ -36,25 +36,29 @@ hipError_t launch_census(const CensusBatch& b, int dtype, int H, int W, int pitc
 struct SgmDense {                // initial stage: Census cost on the fly, all N hypotheses
     const uint64_t* cref;        // [H*W]
     const uint64_t* cview;       // [nv][H*W]
-    uint16_t* csum;              // [nv][H*W][N]
-    int16_t* dmap;               // [nv][H*W]
+    int16_t* dmap;               // [nv][H*W] WTA result
     int cs[4], ct[4];            // s_hat - s, t_hat - t of each cross view
     int nv;
 };
 
 struct SgmBounded {              // final stage: CSR volume over per-pixel ranges
     const uint16_t* cost;
-    const int64_t* off;
+    const int64_t* off;          // [H*W+1]; off[H*W] is the cell count
     const int16_t* lo;
     const int16_t* hi;
     void* csum;                  // uint16 or uint32 [cells]
     int sum_bits;
 };
 
+// Scratch for the per-direction path costs (bytes).
+size_t sgm_dense_scratch_bytes(int nv, int H, int W, int N, int npaths, int bits, int P2);
+size_t sgm_bounded_scratch_bytes(int H, int W, int N, int npaths);
+
+// bits: Census string length (bounds the initial cost); scratch: see above.
 hipError_t launch_sgm_dense(const SgmDense& a, const float* hyp, int H, int W, int N, int P1,
-                            int P2, int npaths, hipStream_t st);
+                            int P2, int npaths, int bits, void* scratch, hipStream_t st);
 hipError_t launch_sgm_bounded(const SgmBounded& a, int H, int W, int N, int P1, int P2,
-                              int npaths, hipStream_t st);
+                              int npaths, void* scratch, hipStream_t st);
 
 // --- per-pixel stages ------------------------------------------------------
 hipError_t launch_fuse(const int16_t* maps, int nv, int HW, int phi, int16_t* dinit,

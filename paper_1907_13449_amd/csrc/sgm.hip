@@ -1,25 +1,30 @@
 // Semi-global matching, Eq. (8)-(10), on gfx950.
 //
-// Schedule: one wavefront per path line; lane l holds the hypotheses
-// k = K*l .. K*l+K-1 (K = ceil(N/64)), so the path state of one pixel lives in
-// the registers of one wave.  Per step along the line:
+// Schedule.  All path directions of all views run in ONE launch: a wavefront
+// owns one path line of one direction of one view, and writes that direction's
+// path costs L_r to a buffer of its own (no read-modify-write, no atomics); a
+// second kernel sums the directions, Eq. (9), and for the initial stage takes
+// the WTA of Eq. (10) in the same pass.  With 8 directions x |V| views the launch
+// has enough independent waves to keep every SIMD busy while each wave walks its
+// line step by step.
+//
+// Inside a wave, lane l holds hypotheses k = K*l .. K*l+K-1 (K = ceil(N/64)), so
+// the state of one pixel lives in the registers of one wave.  Per step:
 //   - the matching cost of the K hypotheses (initial stage: Hamming distance of
 //     the reference Census string and the view's string at the rounded shift,
-//     computed on the fly with popcount; final stage: read from the CSR volume);
-//   - the neighbours k-1 / k+1 of the previous pixel's state come from the own
+//     computed on the fly with popcount; final stage: read from the CSR volume),
+//     with the next step's loads issued before this step's arithmetic;
+//   - the neighbours k-1 / k+1 of the previous pixel come from the lane's own
 //     registers or, at the lane boundary, from lane l-1 / l+1 by a DPP wave
 //     shift (wave_shr:1 / wave_shl:1);
-//   - m = min_k L_r(p-r, k) is a DPP reduction (quad perms, half/row mirror,
-//     row broadcasts) followed by a readlane, so it is wave-uniform in an SGPR;
-//   - the path cost is added into the aggregated volume C_s.
-// Path costs use the normalised recurrence (L - m), which stays in [0, C + P2];
-// hypotheses outside a pixel's range hold +inf (kInf) so they never win a min
-// and the min over the range of p-r is the min over the whole wave.
-// The directions run as separate launches (each line of one direction touches
-// distinct pixels, so the read-modify-write of C_s needs no atomics); the last
-// launch of the initial stage fuses the WTA of Eq. (10).
+//   - m = min_k L_r(p-r, k) is a DPP reduction (quad perms, half/row mirror, row
+//     broadcasts) and a readlane, so it is wave-uniform in an SGPR.
+// Path costs use the normalised recurrence (subtract m), which keeps them in
+// [0, C + P2]: 8 bits suffice for the Census stage when bits + P2 <= 255.
+// Hypotheses outside a pixel's range hold +inf (kInf) so they never win a min.
 #include "lf_internal.h"
 
+#include <algorithm>
 #include <climits>
 
 namespace lf {
@@ -41,247 +46,433 @@ __device__ __forceinline__ uint32_t wave_min(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
 }
 
-// Start pixel and length of path line `line` of direction (du, dv).
-__device__ __forceinline__ void line_start(int H, int W, int du, int dv, int line, int& u0,
-                                           int& v0, int& len) {
-    if (dv == 0) {                       // horizontal: one line per row
-        u0 = du > 0 ? 0 : W - 1;
-        v0 = line;
-        len = W;
-    } else if (du == 0) {                // vertical: one line per column
-        u0 = line;
-        v0 = dv > 0 ? 0 : H - 1;
-        len = H;
-    } else {                             // diagonal: entries on a row, then on a column
-        if (line < W) {
-            u0 = line;
-            v0 = dv > 0 ? 0 : H - 1;
-        } else {
-            const int j = line - W + 1;
-            u0 = du > 0 ? 0 : W - 1;
-            v0 = dv > 0 ? j : H - 1 - j;
-        }
-        const int lu = du > 0 ? W - u0 : u0 + 1;
-        const int lv = dv > 0 ? H - v0 : v0 + 1;
-        len = min(lu, lv);
-    }
-}
+const int kDirs[8][2] = {{1, 0}, {-1, 0}, {0, 1}, {0, -1}, {1, 1}, {-1, -1}, {1, -1}, {-1, 1}};
 
 __host__ __device__ inline int num_lines(int H, int W, int du, int dv) {
     return dv == 0 ? H : (du == 0 ? W : W + H - 1);
 }
 
-enum { kFirst = 0, kMid = 1, kLastWta = 2 };
-constexpr int kWavesPerBlock = 4;
+// Lines of every direction, numbered consecutively: direction r owns global
+// lines [base[r], base[r+1]).
+struct Lines {
+    int base[9];
+    int du[8], dv[8];
+    int npaths;
+};
 
-// One step of the normalised recurrence for K consecutive hypotheses.
+Lines make_lines(int H, int W, int npaths) {
+    Lines L{};
+    L.npaths = npaths;
+    L.base[0] = 0;
+    for (int r = 0; r < npaths; ++r) {
+        L.du[r] = kDirs[r][0];
+        L.dv[r] = kDirs[r][1];
+        L.base[r + 1] = L.base[r] + num_lines(H, W, L.du[r], L.dv[r]);
+    }
+    return L;
+}
+
+struct LineInfo {
+    int r, u0, v0, du, dv, len;
+};
+
+__device__ __forceinline__ LineInfo locate(const Lines& L, int H, int W, int g) {
+    LineInfo li;
+    int r = 0;
+#pragma unroll
+    for (int i = 1; i < 8; ++i) r += (i < L.npaths && g >= L.base[i]) ? 1 : 0;
+    const int line = g - L.base[r];
+    const int du = L.du[r], dv = L.dv[r];
+    li.r = r;
+    li.du = du;
+    li.dv = dv;
+    if (dv == 0) {                       // horizontal: one line per row
+        li.u0 = du > 0 ? 0 : W - 1;
+        li.v0 = line;
+        li.len = W;
+    } else if (du == 0) {                // vertical: one line per column
+        li.u0 = line;
+        li.v0 = dv > 0 ? 0 : H - 1;
+        li.len = H;
+    } else {                             // diagonal: entries on a row, then on a column
+        if (line < W) {
+            li.u0 = line;
+            li.v0 = dv > 0 ? 0 : H - 1;
+        } else {
+            const int j = line - W + 1;
+            li.u0 = du > 0 ? 0 : W - 1;
+            li.v0 = dv > 0 ? j : H - 1 - j;
+        }
+        const int lu = du > 0 ? W - li.u0 : li.u0 + 1;
+        const int lv = dv > 0 ? H - li.v0 : li.v0 + 1;
+        li.len = min(lu, lv);
+    }
+    return li;
+}
+
+constexpr int kWavesPerBlock = 4;
+constexpr int kDepth = 8;          // steps of input prefetched ahead of the recurrence
+
+// Copies a wave-uniform value into a VGPR that the compiler treats as divergent.
+// Loads addressed through it stay vector-memory loads, which complete in order,
+// so a wave can keep several steps of them in flight and wait for the oldest
+// only (scalar loads can only be awaited all at once).
+__device__ __forceinline__ uint32_t in_vgpr(uint32_t x) {
+    asm volatile("" : "=v"(x) : "0"(x));
+    return x;
+}
+
+// One step of the normalised recurrence for K consecutive hypotheses.  Lanes
+// whose hypotheses do not exist carry costs >= kInf and so path costs >= kInf,
+// which never win a min; the neighbour shift brings UINT_MAX (the identity of
+// umin) in at the wave edges.
 template <int K>
 __device__ __forceinline__ void sgm_step(const uint32_t (&Lp)[K], uint32_t m, uint32_t P1,
-                                         uint32_t P2, const uint32_t (&C)[K],
-                                         const bool (&valid)[K], uint32_t (&L)[K]) {
-    const uint32_t left = dpp<0x138>(kInf, Lp[K - 1]);   // wave_shr:1 -> from lane l-1
-    const uint32_t right = dpp<0x130>(kInf, Lp[0]);      // wave_shl:1 -> from lane l+1
+                                         uint32_t P2, const uint32_t (&C)[K], uint32_t (&L)[K]) {
+    const uint32_t left = dpp<0x138>(UINT_MAX, Lp[K - 1]);   // wave_shr:1 -> from lane l-1
+    const uint32_t right = dpp<0x130>(UINT_MAX, Lp[0]);      // wave_shl:1 -> from lane l+1
     const uint32_t mP2 = m + P2;
 #pragma unroll
     for (int j = 0; j < K; ++j) {
         const uint32_t lm = j == 0 ? left : Lp[j - 1];
         const uint32_t lp = j == K - 1 ? right : Lp[j + 1];
         const uint32_t t = min(min(Lp[j], mP2), min(lm, lp) + P1);
-        L[j] = valid[j] ? C[j] + (t - m) : kInf;
+        L[j] = C[j] + (t - m);
     }
 }
 
-// Initial stage: Census cost on the fly, every hypothesis, views on blockIdx.y.
-template <int K, int PHASE>
-__global__ __launch_bounds__(64 * kWavesPerBlock) void sgm_dense_kernel(
-    SgmDense a, const float* __restrict__ hyp, int H, int W, int N, uint32_t P1, uint32_t P2,
-    int du, int dv) {
+template <int K>
+__device__ __forceinline__ uint32_t lane_min(const uint32_t (&L)[K]) {
+    uint32_t mn = L[0];
+#pragma unroll
+    for (int j = 1; j < K; ++j) mn = min(mn, L[j]);
+    return mn;
+}
+
+// ---------------------------------------------------------------------------
+// Initial stage: Census cost on the fly over all N hypotheses; blockIdx.y = view.
+// Output: Lbuf[r][z][p][NP] (NP = N rounded up to 4), storage type LT.
+template <int K, typename LT>
+__global__ __launch_bounds__(64 * kWavesPerBlock) void sgm_dense_paths_kernel(
+    SgmDense a, Lines lines, const float* __restrict__ hyp, int H, int W, int N, int NP,
+    uint32_t P1, uint32_t P2, LT* __restrict__ Lbuf) {
     const int lane = threadIdx.x & 63;
-    const int line = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-    if (line >= num_lines(H, W, du, dv)) return;       // wave-uniform exit
+    const int g = __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6));
+    if (g >= lines.base[lines.npaths]) return;         // wave-uniform exit
     const int z = blockIdx.y;
-    int u0, v0, len;
-    line_start(H, W, du, dv, line, u0, v0, len);
-    const size_t HW = (size_t)H * W;
+    const LineInfo li = locate(lines, H, W, g);
+    const uint32_t HW = (uint32_t)H * W;
     const uint64_t* __restrict__ cref = a.cref;
     const uint64_t* __restrict__ cv = a.cview + (size_t)z * HW;
-    uint16_t* __restrict__ csum = a.csum + (size_t)z * HW * N;
+    LT* __restrict__ out = Lbuf + ((size_t)li.r * a.nv + z) * HW * NP;
 
-    int ku[K], kv[K];
-    bool valid[K];
+    // Each cross view is shifted along one axis only: along u (t = t_hat) or v.
+    // With a = the coordinate on that axis and b the other one, the sample of
+    // hypothesis k is at clamp(a + sh_k) * mul_a + b * mul_b: no branches in the
+    // address arithmetic, so the loads of kDepth steps can stay in flight.
+    const bool along_u = a.ct[z] == 0;
+    const int cs = along_u ? a.cs[z] : a.ct[z];
+    const int amax = along_u ? W - 1 : H - 1;
+    const uint32_t mul_a = along_u ? 1u : (uint32_t)W, mul_b = along_u ? (uint32_t)W : 1u;
+    const int da = along_u ? li.du : li.dv, db = along_u ? li.dv : li.du;
+    const int a0 = along_u ? li.u0 : li.v0, b0 = along_u ? li.v0 : li.u0;
+    int sh[K];
+    uint32_t cinit[K];                 // popcount accumulator: 0, or kInf past N
 #pragma unroll
     for (int j = 0; j < K; ++j) {
         const int k = lane * K + j;
-        valid[j] = k < N;
-        const float d = hyp[min(k, N - 1)];
-        ku[j] = (int)rintf((float)a.cs[z] * d);
-        kv[j] = (int)rintf((float)a.ct[z] * d);
+        sh[j] = (int)rintf((float)cs * hyp[min(k, N - 1)]);
+        cinit[j] = k < N ? 0u : kInf;
     }
-    uint32_t Lp[K], m = 0;
-    for (int step = 0; step < len; ++step) {
-        const int u = u0 + step * du, v = v0 + step * dv;
-        const size_t p = (size_t)v * W + u;
-        const uint64_t cr = cref[p];
-        uint32_t C[K];
+    const int last = li.len - 1;
+    auto load = [&](int step, uint64_t& r, uint64_t (&x)[K]) {
+        step = min(step, last);
+        const int av = a0 + step * da, bv = b0 + step * db;
+        const uint32_t bterm = (uint32_t)bv * mul_b;
+        r = cref[in_vgpr((uint32_t)av * mul_a + bterm)];
 #pragma unroll
-        for (int j = 0; j < K; ++j) {
-            const int x = clampi(u + ku[j], 0, W - 1), y = clampi(v + kv[j], 0, H - 1);
-            C[j] = (uint32_t)__popcll(cr ^ cv[(size_t)y * W + x]);
-        }
-        uint32_t L[K];
-        if (step == 0) {
+        for (int j = 0; j < K; ++j)
+            x[j] = cv[(uint32_t)clampi(av + sh[j], 0, amax) * mul_a + bterm];
+    };
+    uint64_t rb[kDepth], xb[kDepth][K];
 #pragma unroll
-            for (int j = 0; j < K; ++j) L[j] = valid[j] ? C[j] : kInf;
-        } else {
-            sgm_step<K>(Lp, m, P1, P2, C, valid, L);
-        }
-        uint32_t mn = L[0];
-#pragma unroll
-        for (int j = 1; j < K; ++j) mn = min(mn, L[j]);
-        m = wave_min(mn);
+    for (int i = 0; i < kDepth; ++i) load(i, rb[i], xb[i]);
 
-        uint16_t* row = csum + p * N + lane * K;
-        if (PHASE == kFirst) {
+    uint32_t Lp[K], m = 0;
+#pragma unroll
+    for (int j = 0; j < K; ++j) Lp[j] = kInf;
+    for (int base = 0; base < li.len; base += kDepth) {
+#pragma unroll
+        for (int i = 0; i < kDepth; ++i) {
+            const int step = base + i;           // steps past the line end are computed
+            uint32_t C[K];                       // and not stored
 #pragma unroll
             for (int j = 0; j < K; ++j)
-                if (valid[j]) row[j] = (uint16_t)L[j];
-        } else if (PHASE == kMid) {
+                C[j] = __popc((uint32_t)(rb[i] ^ xb[i][j])) +
+                       __popc((uint32_t)((rb[i] ^ xb[i][j]) >> 32)) + cinit[j];
+            load(step + kDepth, rb[i], xb[i]);   // refill the slot just consumed
+            uint32_t L[K];
+            if (step == 0) {
 #pragma unroll
-            for (int j = 0; j < K; ++j)
-                if (valid[j]) row[j] = (uint16_t)(row[j] + L[j]);
-        } else {
-            uint32_t key = UINT_MAX;
+                for (int j = 0; j < K; ++j) L[j] = C[j];
+            } else {
+                sgm_step<K>(Lp, m, P1, P2, C, L);
+            }
+            m = wave_min(lane_min(L));
+
+            const int u = li.u0 + step * li.du, v = li.v0 + step * li.dv;
+            LT* row = out + (size_t)(v * W + u) * NP + lane * K;
+            const bool live = step < li.len;
+            if constexpr (K == 2) {
+                if (live && lane * 2 < N) {        // a pair: one 16- or 32-bit store
+                    if constexpr (sizeof(LT) == 1)
+                        *(uint16_t*)row = (uint16_t)((L[0] & 0xFF) | (L[1] << 8));
+                    else
+                        *(uint32_t*)row = (L[0] & 0xFFFF) | (L[1] << 16);
+                }
+            } else {
 #pragma unroll
-            for (int j = 0; j < K; ++j)
-                if (valid[j]) key = min(key, ((row[j] + L[j]) << 8) | (uint32_t)(lane * K + j));
-            key = wave_min(key);
-            if (lane == 0) a.dmap[(size_t)z * HW + p] = (int16_t)(key & 0xFF);
+                for (int j = 0; j < K; ++j)
+                    if (live && lane * K + j < N) row[j] = (LT)L[j];
+            }
+#pragma unroll
+            for (int j = 0; j < K; ++j) Lp[j] = L[j];
         }
-#pragma unroll
-        for (int j = 0; j < K; ++j) Lp[j] = L[j];
     }
 }
 
-// Final stage: CSR volume over per-pixel ranges [lo, hi].
-template <int K, int PHASE, typename SumT>
-__global__ __launch_bounds__(64 * kWavesPerBlock) void sgm_bounded_kernel(
-    SgmBounded a, int H, int W, uint32_t P1, uint32_t P2, int du, int dv) {
+// Sum over directions + WTA (Eq. 9-10) of the initial stage: one wave per pixel,
+// lane l holds hypotheses 2l and 2l+1 (+128 per round); lowest index on ties.
+template <typename LT>
+__global__ __launch_bounds__(256) void dense_sum_wta_kernel(const LT* __restrict__ Lbuf,
+                                                            int npaths, int nv, int64_t HW,
+                                                            int N, int NP,
+                                                            int16_t* __restrict__ dmap) {
     const int lane = threadIdx.x & 63;
-    const int line = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-    if (line >= num_lines(H, W, du, dv)) return;
-    int u0, v0, len;
-    line_start(H, W, du, dv, line, u0, v0, len);
-    const uint16_t* __restrict__ cost = a.cost;
-    SumT* __restrict__ csum = reinterpret_cast<SumT*>(a.csum);
-
-    uint32_t Lp[K], m = 0;
-    for (int step = 0; step < len; ++step) {
-        const int u = u0 + step * du, v = v0 + step * dv;
-        const size_t p = (size_t)v * W + u;
-        const int lo = a.lo[p], hi = a.hi[p];
-        const int64_t base = a.off[p] - lo;
-        uint32_t C[K];
-        bool valid[K];
-#pragma unroll
-        for (int j = 0; j < K; ++j) {
-            const int k = lane * K + j;
-            valid[j] = k >= lo && k <= hi;
-            C[j] = valid[j] ? (uint32_t)cost[base + k] : 0u;
+    const int64_t nwaves = (int64_t)gridDim.x * 4;
+    const size_t dir_stride = (size_t)nv * HW * NP;
+    for (int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); q < nv * HW; q += nwaves) {
+        const LT* base = Lbuf + (size_t)q * NP;        // q = z*HW + p
+        uint32_t key = UINT_MAX;
+        for (int k = 2 * lane; k < N; k += 128) {
+            uint32_t t0 = 0, t1 = 0;
+#pragma unroll 8
+            for (int r = 0; r < npaths; ++r) {
+                const LT* e = base + (size_t)r * dir_stride + k;
+                if constexpr (sizeof(LT) == 1) {
+                    const uint32_t x = *(const uint16_t*)e;
+                    t0 += x & 0xFF;
+                    t1 += x >> 8;
+                } else {
+                    const uint32_t x = *(const uint32_t*)e;
+                    t0 += x & 0xFFFF;
+                    t1 += x >> 16;
+                }
+            }
+            key = min(key, (t0 << 8) | (uint32_t)k);
+            if (k + 1 < N) key = min(key, (t1 << 8) | (uint32_t)(k + 1));
         }
-        uint32_t L[K];
-        if (step == 0) {
-#pragma unroll
-            for (int j = 0; j < K; ++j) L[j] = valid[j] ? C[j] : kInf;
-        } else {
-            sgm_step<K>(Lp, m, P1, P2, C, valid, L);
-        }
-        uint32_t mn = L[0];
-#pragma unroll
-        for (int j = 1; j < K; ++j) mn = min(mn, L[j]);
-        m = wave_min(mn);
-#pragma unroll
-        for (int j = 0; j < K; ++j) {
-            if (!valid[j]) continue;
-            SumT* c = csum + base + lane * K + j;
-            *c = PHASE == kFirst ? (SumT)L[j] : (SumT)(*c + L[j]);
-        }
-#pragma unroll
-        for (int j = 0; j < K; ++j) Lp[j] = L[j];
+        key = wave_min(key);
+        if (lane == 0) dmap[q] = (int16_t)(key & 0xFF);
     }
 }
 
-const int kDirs[8][2] = {{1, 0}, {-1, 0}, {0, 1}, {0, -1}, {1, 1}, {-1, -1}, {1, -1}, {-1, 1}};
+// ---------------------------------------------------------------------------
+// Final stage: CSR volume over per-pixel ranges [lo, hi].  Output Lbuf[r][cell].
+// meta[p] = {off[p] - lo[p] (int64), lo | hi << 16}: one 16-byte load per step.
+struct alignas(16) PixMeta {
+    int64_t base;
+    int32_t lohi;
+    int32_t pad;
+};
+
+__global__ __launch_bounds__(256) void pix_meta_kernel(const int64_t* __restrict__ off,
+                                                       const int16_t* __restrict__ lo,
+                                                       const int16_t* __restrict__ hi, int HW,
+                                                       PixMeta* __restrict__ meta) {
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= HW) return;
+    PixMeta m;
+    m.base = off[p] - lo[p];
+    m.lohi = (int32_t)((uint16_t)lo[p] | ((uint32_t)(uint16_t)hi[p] << 16));
+    m.pad = 0;
+    meta[p] = m;
+}
 
 template <int K>
-hipError_t dense_passes(const SgmDense& a, const float* hyp, int H, int W, int N, int P1,
-                        int P2, int npaths, hipStream_t st) {
-    for (int r = 0; r < npaths; ++r) {
-        const int du = kDirs[r][0], dv = kDirs[r][1];
-        dim3 grid((num_lines(H, W, du, dv) + kWavesPerBlock - 1) / kWavesPerBlock, a.nv);
-        dim3 block(64 * kWavesPerBlock);
-        if (r == 0)
-            hipLaunchKernelGGL((sgm_dense_kernel<K, kFirst>), grid, block, 0, st, a, hyp, H, W,
-                               N, (uint32_t)P1, (uint32_t)P2, du, dv);
-        else if (r + 1 < npaths)
-            hipLaunchKernelGGL((sgm_dense_kernel<K, kMid>), grid, block, 0, st, a, hyp, H, W, N,
-                               (uint32_t)P1, (uint32_t)P2, du, dv);
-        else
-            hipLaunchKernelGGL((sgm_dense_kernel<K, kLastWta>), grid, block, 0, st, a, hyp, H,
-                               W, N, (uint32_t)P1, (uint32_t)P2, du, dv);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
+__global__ __launch_bounds__(64 * kWavesPerBlock) void sgm_bounded_paths_kernel(
+    SgmBounded a, const PixMeta* __restrict__ meta, Lines lines, int H, int W, uint32_t P1,
+    uint32_t P2, size_t dir_stride, uint16_t* __restrict__ Lbuf) {
+    constexpr int kMeta = kDepth, kCost = kDepth / 2;   // two-stage prefetch
+    const int lane = threadIdx.x & 63;
+    const int g = __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6));
+    if (g >= lines.base[lines.npaths]) return;
+    const LineInfo li = locate(lines, H, W, g);
+    const uint16_t* __restrict__ cost = a.cost;
+    uint16_t* __restrict__ out = Lbuf + (size_t)li.r * dir_stride;
+
+    auto load_meta = [&](int step) {
+        const int u = li.u0 + step * li.du, v = li.v0 + step * li.dv;
+        return meta[in_vgpr((uint32_t)(v * W + u))];
+    };
+    // gather of the K costs of a pixel; hypotheses outside [lo, hi] read the
+    // pixel's first cell and are replaced by kInf when used
+    auto load_cost = [&](const PixMeta& pm, uint32_t (&c)[K]) {
+        const int lo = pm.lohi & 0xFFFF, hi = pm.lohi >> 16;
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const int k = min(max(lane * K + j, lo), hi);
+            c[j] = cost[pm.base + k];
+        }
+    };
+    PixMeta mb[kMeta];
+    uint32_t cb[kCost][K];
+#pragma unroll
+    for (int i = 0; i < kMeta; ++i) mb[i] = load_meta(min(i, li.len - 1));
+#pragma unroll
+    for (int i = 0; i < kCost; ++i) load_cost(mb[i], cb[i]);
+
+    uint32_t Lp[K], m = 0;
+#pragma unroll
+    for (int j = 0; j < K; ++j) Lp[j] = kInf;
+    for (int base = 0; base < li.len; base += kMeta) {
+#pragma unroll
+        for (int i = 0; i < kMeta; ++i) {
+            const int step = base + i;           // steps past the line end are computed
+            const PixMeta pm = mb[i];            // and not stored
+            const int lo = pm.lohi & 0xFFFF, hi = pm.lohi >> 16;
+            uint32_t C[K];
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                const int k = lane * K + j;
+                C[j] = (k >= lo && k <= hi) ? cb[i % kCost][j] : kInf;
+            }
+            // refill: costs for step + kCost (its meta arrived kMeta - kCost steps
+            // ago), then the meta slot for step + kMeta
+            load_cost(mb[(i + kCost) % kMeta], cb[i % kCost]);
+            mb[i] = load_meta(min(step + kMeta, li.len - 1));
+            uint32_t L[K];
+            if (step == 0) {
+#pragma unroll
+                for (int j = 0; j < K; ++j) L[j] = C[j];
+            } else {
+                sgm_step<K>(Lp, m, P1, P2, C, L);
+            }
+            m = wave_min(lane_min(L));
+            const bool live = step < li.len;
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                const int k = lane * K + j;
+                if (live && k >= lo && k <= hi) out[pm.base + k] = (uint16_t)L[j];
+            }
+#pragma unroll
+            for (int j = 0; j < K; ++j) Lp[j] = L[j];
+        }
     }
-    return hipSuccess;
 }
 
-template <int K, typename SumT>
-hipError_t bounded_passes(const SgmBounded& a, int H, int W, int P1, int P2, int npaths,
-                          hipStream_t st) {
-    for (int r = 0; r < npaths; ++r) {
-        const int du = kDirs[r][0], dv = kDirs[r][1];
-        dim3 grid((num_lines(H, W, du, dv) + kWavesPerBlock - 1) / kWavesPerBlock);
-        dim3 block(64 * kWavesPerBlock);
-        if (r == 0)
-            hipLaunchKernelGGL((sgm_bounded_kernel<K, kFirst, SumT>), grid, block, 0, st, a, H,
-                               W, (uint32_t)P1, (uint32_t)P2, du, dv);
-        else
-            hipLaunchKernelGGL((sgm_bounded_kernel<K, kMid, SumT>), grid, block, 0, st, a, H, W,
-                               (uint32_t)P1, (uint32_t)P2, du, dv);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
+// csum[c] = sum_r Lbuf[r][c] over the cells of the CSR volume.
+template <typename SumT>
+__global__ __launch_bounds__(256) void bounded_sum_kernel(const uint16_t* __restrict__ Lbuf,
+                                                          int npaths, size_t dir_stride,
+                                                          const int64_t* __restrict__ total,
+                                                          SumT* __restrict__ csum) {
+    const int64_t n = *total;
+    for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < n;
+         c += (int64_t)gridDim.x * 256) {
+        uint32_t s = 0;
+        for (int r = 0; r < npaths; ++r) s += Lbuf[(size_t)r * dir_stride + c];
+        csum[c] = (SumT)s;
     }
-    return hipSuccess;
+}
+
+template <int K, typename LT>
+hipError_t dense_launch(const SgmDense& a, const Lines& lines, const float* hyp, int H, int W,
+                        int N, int NP, int P1, int P2, void* Lbuf, hipStream_t st) {
+    dim3 grid((lines.base[lines.npaths] + kWavesPerBlock - 1) / kWavesPerBlock, a.nv);
+    hipLaunchKernelGGL((sgm_dense_paths_kernel<K, LT>), grid, dim3(64 * kWavesPerBlock), 0, st, a,
+                       lines, hyp, H, W, N, NP, (uint32_t)P1, (uint32_t)P2, (LT*)Lbuf);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t HW = (int64_t)H * W;
+    const int64_t waves = a.nv * HW;
+    const int blocks = (int)std::min<int64_t>((waves + 3) / 4, 8192);
+    hipLaunchKernelGGL((dense_sum_wta_kernel<LT>), dim3(blocks), dim3(256), 0, st,
+                       (const LT*)Lbuf, lines.npaths, a.nv, HW, N, NP, a.dmap);
+    return hipGetLastError();
+}
+
+template <typename LT>
+hipError_t dense_dispatch(const SgmDense& a, const Lines& lines, const float* hyp, int H, int W,
+                          int N, int NP, int P1, int P2, void* Lbuf, hipStream_t st) {
+    switch ((N + 63) / 64) {
+        case 1: return dense_launch<1, LT>(a, lines, hyp, H, W, N, NP, P1, P2, Lbuf, st);
+        case 2: return dense_launch<2, LT>(a, lines, hyp, H, W, N, NP, P1, P2, Lbuf, st);
+        case 3: return dense_launch<3, LT>(a, lines, hyp, H, W, N, NP, P1, P2, Lbuf, st);
+        default: return dense_launch<4, LT>(a, lines, hyp, H, W, N, NP, P1, P2, Lbuf, st);
+    }
+}
+
+template <int K>
+hipError_t bounded_launch(const SgmBounded& a, const PixMeta* meta, const Lines& lines, int H,
+                          int W, int P1, int P2, size_t dir_stride, uint16_t* Lbuf,
+                          hipStream_t st) {
+    dim3 grid((lines.base[lines.npaths] + kWavesPerBlock - 1) / kWavesPerBlock);
+    hipLaunchKernelGGL((sgm_bounded_paths_kernel<K>), grid, dim3(64 * kWavesPerBlock), 0, st, a,
+                       meta, lines, H, W, (uint32_t)P1, (uint32_t)P2, dir_stride, Lbuf);
+    return hipGetLastError();
 }
 
 }  // namespace
 
+int dense_np(int N) { return (N + 3) / 4 * 4; }
+
+size_t sgm_dense_scratch_bytes(int nv, int H, int W, int N, int npaths, int bits, int P2) {
+    const size_t lt = bits + P2 <= 255 ? 1 : 2;
+    return (size_t)npaths * nv * H * W * dense_np(N) * lt;
+}
+
+size_t sgm_bounded_scratch_bytes(int H, int W, int N, int npaths) {
+    const size_t meta = ((size_t)H * W * sizeof(PixMeta) + 255) / 256 * 256;
+    return meta + (size_t)npaths * H * W * N * sizeof(uint16_t);
+}
+
 hipError_t launch_sgm_dense(const SgmDense& a, const float* hyp, int H, int W, int N, int P1,
-                            int P2, int npaths, hipStream_t st) {
-    switch ((N + 63) / 64) {
-        case 1: return dense_passes<1>(a, hyp, H, W, N, P1, P2, npaths, st);
-        case 2: return dense_passes<2>(a, hyp, H, W, N, P1, P2, npaths, st);
-        case 3: return dense_passes<3>(a, hyp, H, W, N, P1, P2, npaths, st);
-        default: return dense_passes<4>(a, hyp, H, W, N, P1, P2, npaths, st);
-    }
+                            int P2, int npaths, int bits, void* scratch, hipStream_t st) {
+    const Lines lines = make_lines(H, W, npaths);
+    const int NP = dense_np(N);
+    if (bits + P2 <= 255)
+        return dense_dispatch<uint8_t>(a, lines, hyp, H, W, N, NP, P1, P2, scratch, st);
+    return dense_dispatch<uint16_t>(a, lines, hyp, H, W, N, NP, P1, P2, scratch, st);
 }
 
 hipError_t launch_sgm_bounded(const SgmBounded& a, int H, int W, int N, int P1, int P2,
-                              int npaths, hipStream_t st) {
-    const int K = (N + 63) / 64;
-    if (a.sum_bits == 16) {
-        switch (K) {
-            case 1: return bounded_passes<1, uint16_t>(a, H, W, P1, P2, npaths, st);
-            case 2: return bounded_passes<2, uint16_t>(a, H, W, P1, P2, npaths, st);
-            case 3: return bounded_passes<3, uint16_t>(a, H, W, P1, P2, npaths, st);
-            default: return bounded_passes<4, uint16_t>(a, H, W, P1, P2, npaths, st);
-        }
+                              int npaths, void* scratch, hipStream_t st) {
+    const Lines lines = make_lines(H, W, npaths);
+    const size_t dir_stride = (size_t)H * W * N;     // worst-case cells per direction
+    const int HW = H * W;
+    PixMeta* meta = (PixMeta*)scratch;
+    uint16_t* Lbuf = (uint16_t*)((char*)scratch + ((size_t)HW * sizeof(PixMeta) + 255) / 256 * 256);
+    hipLaunchKernelGGL(pix_meta_kernel, dim3((HW + 255) / 256), dim3(256), 0, st, a.off, a.lo, a.hi,
+                       HW, meta);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    switch ((N + 63) / 64) {
+        case 1: e = bounded_launch<1>(a, meta, lines, H, W, P1, P2, dir_stride, Lbuf, st); break;
+        case 2: e = bounded_launch<2>(a, meta, lines, H, W, P1, P2, dir_stride, Lbuf, st); break;
+        case 3: e = bounded_launch<3>(a, meta, lines, H, W, P1, P2, dir_stride, Lbuf, st); break;
+        default: e = bounded_launch<4>(a, meta, lines, H, W, P1, P2, dir_stride, Lbuf, st); break;
     }
-    switch (K) {
-        case 1: return bounded_passes<1, uint32_t>(a, H, W, P1, P2, npaths, st);
-        case 2: return bounded_passes<2, uint32_t>(a, H, W, P1, P2, npaths, st);
-        case 3: return bounded_passes<3, uint32_t>(a, H, W, P1, P2, npaths, st);
-        default: return bounded_passes<4, uint32_t>(a, H, W, P1, P2, npaths, st);
-    }
+    if (e != hipSuccess) return e;
+    const int blocks = 2048;
+    const int64_t* total = a.off + (int64_t)H * W;
+    if (a.sum_bits == 16)
+        hipLaunchKernelGGL(bounded_sum_kernel<uint16_t>, dim3(blocks), dim3(256), 0, st, Lbuf,
+                           npaths, dir_stride, total, (uint16_t*)a.csum);
+    else
+        hipLaunchKernelGGL(bounded_sum_kernel<uint32_t>, dim3(blocks), dim3(256), 0, st, Lbuf,
+                           npaths, dir_stride, total, (uint32_t*)a.csum);
+    return hipGetLastError();
 }
 
 }  // namespace lf

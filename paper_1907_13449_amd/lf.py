@@ -23,8 +23,10 @@ LF_COST_L2, LF_COST_CENSUS = 0, 1
 EXPORTS = (
     "lf_abi_version", "lf_last_error", "lf_validate_hypotheses", "lf_cost_cap",
     "lf_cross_views", "lf_census", "lf_initial_workspace_size", "lf_initial_disparity",
-    "lf_cost_workspace_size", "lf_cost_volume_bounded", "lf_sgm_aggregate",
+    "lf_cost_workspace_size", "lf_cost_volume_bounded", "lf_sgm_workspace_size",
+    "lf_sgm_aggregate",
     "lf_wta_workspace_size", "lf_wta_subpixel", "lf_depth_workspace_size", "lf_depth",
+    "lf_profile_enable", "lf_profile_read", "lf_profile_stage_name",
 )
 
 
@@ -60,7 +62,7 @@ def _load():
     lib = C.CDLL(LIB_PATH)
     lib.lf_last_error.restype = C.c_char_p
     for name in ("lf_initial_workspace_size", "lf_cost_workspace_size", "lf_wta_workspace_size",
-                 "lf_depth_workspace_size"):
+                 "lf_depth_workspace_size", "lf_sgm_workspace_size"):
         getattr(lib, name).restype = C.c_size_t
     P, i32, i64, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
     lib.lf_census.argtypes = [P, i32, i32, i32, i32, CensusWindow, P, P]
@@ -68,7 +70,8 @@ def _load():
     lib.lf_initial_disparity.argtypes = [P, P, i32, P, P, P, P, P, P, sz, P]
     lib.lf_cost_workspace_size.argtypes = [i32, i32, i32, i32, i32, P]
     lib.lf_cost_volume_bounded.argtypes = [P, P, i32, P, P, P, P, P, i64, P, P, sz, P]
-    lib.lf_sgm_aggregate.argtypes = [P, P, P, P, i32, i32, i32, SgmParams, i32, P, P]
+    lib.lf_sgm_workspace_size.argtypes = [i32, i32, i32, i32]
+    lib.lf_sgm_aggregate.argtypes = [P, P, P, P, i32, i32, i32, SgmParams, i32, P, P, sz, P]
     lib.lf_wta_workspace_size.argtypes = [i32, i32]
     lib.lf_wta_subpixel.argtypes = [P, i32, P, P, P, i32, i32, P, i32, i32, P, P, P, sz, P]
     lib.lf_depth_workspace_size.argtypes = [i32, i32, i32, i32, i32, P]
@@ -76,6 +79,10 @@ def _load():
     lib.lf_validate_hypotheses.argtypes = [P, i32]
     lib.lf_cost_cap.argtypes = [i32, i32, i32]
     lib.lf_cross_views.argtypes = [i32, i32, P]
+    lib.lf_profile_enable.argtypes = [i32]
+    lib.lf_profile_read.argtypes = [P, P, i32]
+    lib.lf_profile_stage_name.argtypes = [i32]
+    lib.lf_profile_stage_name.restype = C.c_char_p
     return lib
 
 
@@ -211,7 +218,7 @@ def lf_cost_volume_bounded(views: torch.Tensor, hyp: torch.Tensor, params: dict,
 
 def lf_sgm_aggregate(cost: torch.Tensor, offsets: torch.Tensor, d_lo: torch.Tensor,
                      d_hi: torch.Tensor, N: int, P1: int, P2: int, npaths: int = 8,
-                     sum_bits: int = 32, csum=None, stream=None):
+                     sum_bits: int = 32, csum=None, ws=None, stream=None):
     _dev(cost, torch.int16, "cost")
     _dev(offsets, torch.int64, "offsets")
     _dev(d_lo, torch.int16, "d_lo")
@@ -220,9 +227,11 @@ def lf_sgm_aggregate(cost: torch.Tensor, offsets: torch.Tensor, d_lo: torch.Tens
     if csum is None:
         csum = torch.empty(cost.numel(), dtype=torch.int16 if sum_bits == 16 else torch.int32,
                            device=cost.device)
+    if ws is None:
+        ws = workspace(lib.lf_sgm_workspace_size(H, W, N, npaths), cost.device)
     _check(lib.lf_sgm_aggregate(_ptr(cost), _ptr(offsets), _ptr(d_lo), _ptr(d_hi), H, W, N,
-                                SgmParams(P1, P2, npaths), sum_bits, _ptr(csum),
-                                _stream(stream)))
+                                SgmParams(P1, P2, npaths), sum_bits, _ptr(csum), _ptr(ws),
+                                ws.numel(), _stream(stream)))
     return csum
 
 
@@ -238,6 +247,20 @@ def lf_wta_subpixel(csum: torch.Tensor, sum_bits: int, offsets: torch.Tensor, d_
                                W, _ptr(hyp), hyp.shape[0], median, _ptr(d_index), _ptr(disp),
                                _ptr(ws), ws.numel(), _stream(stream)))
     return dict(d_index=d_index, disparity=disp)
+
+
+def profile_enable(on: bool = True) -> bool:
+    """Turn per-stage HIP-event timing on/off; returns the previous setting."""
+    return bool(lib.lf_profile_enable(int(on)))
+
+
+def profile_read():
+    """{stage name: (milliseconds, launches)} accumulated since the last read."""
+    n = 16
+    ms = (C.c_double * n)()
+    la = (C.c_int64 * n)()
+    k = lib.lf_profile_read(ms, la, n)
+    return {lib.lf_profile_stage_name(i).decode(): (ms[i], la[i]) for i in range(k)}
 
 
 def depth_workspace_bytes(S, T, H, W, N, params: dict) -> int:
