@@ -386,6 +386,9 @@ lf_status lf_initial_disparity(const lf_view_set* views, const float* hyp, int32
     LF_CHECK(check_params(prm));
     if (!hyp || !d_init || !d_lo || !d_hi || !ws) return fail(LF_EINVAL, "NULL argument");
     const int S = views->S, T = views->T, H = views->H, W = views->W;
+    if ((int64_t)H * W * ((N + 3) / 4 * 4) * 2 >= ((int64_t)1 << 31))
+        return fail(LF_EUNSUPPORTED, "H*W*N = %lld cells per view (max 2^30)",
+                    (long long)H * W * N);
     Carve sizer(nullptr);
     const size_t need = plan_initial(sizer, S, T, H, W, N, prm, nullptr);
     if (ws_bytes < need) return fail(LF_ENOSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
@@ -466,6 +469,9 @@ lf_status lf_cost_volume_bounded(const lf_view_set* views, const float* hyp, int
         return fail(LF_EINVAL, "NULL argument");
     const int S = views->S, T = views->T, H = views->H, W = views->W;
     const int64_t HW = (int64_t)H * W;
+    if ((int64_t)S * T * H * views->pitch * (views->dtype == LF_U8 ? 1 : 4) >= ((int64_t)1 << 31))
+        return fail(LF_EUNSUPPORTED, "light field of %lld bytes (max 2 GiB)",
+                    (long long)S * T * H * views->pitch * (views->dtype == LF_U8 ? 1 : 4));
     if (cap_cells < HW * N)
         return fail(LF_ENOSPACE, "cap_cells %lld < H*W*N = %lld", (long long)cap_cells,
                     (long long)(HW * N));

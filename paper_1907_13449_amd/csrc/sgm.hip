@@ -10,10 +10,10 @@
 //
 // Inside a wave, lane l holds hypotheses k = K*l .. K*l+K-1 (K = ceil(N/64)), so
 // the state of one pixel lives in the registers of one wave.  Per step:
-//   - the matching cost of the K hypotheses (initial stage: Hamming distance of
-//     the reference Census string and the view's string at the rounded shift,
-//     computed on the fly with popcount; final stage: read from the CSR volume),
-//     with the next step's loads issued before this step's arithmetic;
+//   - the matching cost of the K hypotheses, read from a cost volume whose row of
+//     the pixel is contiguous (initial stage: the 8-bit Census cost volume, built
+//     once by a popcount kernel; final stage: the CSR volume), with the loads of
+//     the next kDepth steps in flight;
 //   - the neighbours k-1 / k+1 of the previous pixel come from the lane's own
 //     registers or, at the lane boundary, from lane l-1 / l+1 by a DPP wave
 //     shift (wave_shr:1 / wave_shl:1);
@@ -36,13 +36,15 @@ __device__ __forceinline__ uint32_t dpp(uint32_t old, uint32_t v) {
 }
 
 // Minimum over the 64 lanes, returned wave-uniform.
+// The DPP source operand "old" is UINT_MAX, the identity of umin, so that each
+// move fuses into the v_min_u32 that consumes it (one v_min_u32_dpp per stage).
 __device__ __forceinline__ uint32_t wave_min(uint32_t v) {
-    v = min(v, dpp<0xB1>(v, v));        // quad_perm [1,0,3,2]
-    v = min(v, dpp<0x4E>(v, v));        // quad_perm [2,3,0,1]
-    v = min(v, dpp<0x141>(v, v));       // row_half_mirror
-    v = min(v, dpp<0x140>(v, v));       // row_mirror: every lane holds its row's min
-    v = min(v, dpp<0x142, 0xA>(v, v));  // row_bcast:15 into rows 1, 3
-    v = min(v, dpp<0x143, 0xC>(v, v));  // row_bcast:31 into rows 2, 3
+    v = min(v, dpp<0xB1>(UINT_MAX, v));        // quad_perm [1,0,3,2]
+    v = min(v, dpp<0x4E>(UINT_MAX, v));        // quad_perm [2,3,0,1]
+    v = min(v, dpp<0x141>(UINT_MAX, v));       // row_half_mirror
+    v = min(v, dpp<0x140>(UINT_MAX, v));       // row_mirror: every lane holds its row's min
+    v = min(v, dpp<0x142, 0xA>(UINT_MAX, v));  // row_bcast:15 into rows 1, 3
+    v = min(v, dpp<0x143, 0xC>(UINT_MAX, v));  // row_bcast:31 into rows 2, 3
     return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
 }
 
@@ -150,11 +152,44 @@ __device__ __forceinline__ uint32_t lane_min(const uint32_t (&L)[K]) {
 }
 
 // ---------------------------------------------------------------------------
-// Initial stage: Census cost on the fly over all N hypotheses; blockIdx.y = view.
-// Output: Lbuf[r][z][p][NP] (NP = N rounded up to 4), storage type LT.
+// Initial stage, Eq. (7): the Census cost volume C[z][p][NP] (8-bit, NP = N
+// rounded up to 4) of every cross view, computed once and read by all path
+// directions.  A thread fills 4 hypotheses of one pixel (one 32-bit store);
+// consecutive threads walk the hypotheses of a pixel, then the next pixel.
+__global__ __launch_bounds__(256) void census_cost_volume_kernel(SgmDense a,
+                                                                 const float* __restrict__ hyp,
+                                                                 int H, int W, int N, int NP,
+                                                                 uint8_t* __restrict__ cvol) {
+    const int z = blockIdx.y;
+    const int groups = NP / 4;
+    const uint32_t HW = (uint32_t)H * W;
+    const uint32_t t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= HW * (uint32_t)groups) return;
+    const uint32_t p = t / groups;
+    const int k0 = (int)(t - p * groups) * 4;
+    const int v = (int)(p / W), u = (int)(p - (uint32_t)v * W);
+    const bool along_u = a.ct[z] == 0;
+    const int cs = along_u ? a.cs[z] : a.ct[z];
+    const uint64_t r = a.cref[p];
+    const uint64_t* __restrict__ cv = a.cview + (size_t)z * HW;
+    uint32_t packed = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int k = k0 + j;
+        const int sh = (int)rintf((float)cs * hyp[min(k, N - 1)]);
+        const uint32_t q = along_u ? (uint32_t)(v * W + clampi(u + sh, 0, W - 1))
+                                   : (uint32_t)(clampi(v + sh, 0, H - 1) * W + u);
+        const uint32_t c = k < N ? (uint32_t)__popcll(r ^ cv[q]) : 0u;
+        packed |= c << (8 * j);
+    }
+    *(uint32_t*)(cvol + ((size_t)z * HW + p) * NP + k0) = packed;
+}
+
+// SGM over the Census cost volume, every direction of every view in one launch;
+// blockIdx.y = view.  Output: Lbuf[r][z][p][NP], storage type LT.
 template <int K, typename LT>
 __global__ __launch_bounds__(64 * kWavesPerBlock) void sgm_dense_paths_kernel(
-    SgmDense a, Lines lines, const float* __restrict__ hyp, int H, int W, int N, int NP,
+    const uint8_t* __restrict__ cvol, int nv, Lines lines, int H, int W, int N, int NP,
     uint32_t P1, uint32_t P2, LT* __restrict__ Lbuf) {
     const int lane = threadIdx.x & 63;
     const int g = __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6));
@@ -162,41 +197,27 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void sgm_dense_paths_kernel(
     const int z = blockIdx.y;
     const LineInfo li = locate(lines, H, W, g);
     const uint32_t HW = (uint32_t)H * W;
-    const uint64_t* __restrict__ cref = a.cref;
-    const uint64_t* __restrict__ cv = a.cview + (size_t)z * HW;
-    LT* __restrict__ out = Lbuf + ((size_t)li.r * a.nv + z) * HW * NP;
+    const uint8_t* __restrict__ cz = cvol + (size_t)z * HW * NP;
+    LT* __restrict__ out = Lbuf + ((size_t)li.r * nv + z) * HW * NP;
 
-    // Each cross view is shifted along one axis only: along u (t = t_hat) or v.
-    // With a = the coordinate on that axis and b the other one, the sample of
-    // hypothesis k is at clamp(a + sh_k) * mul_a + b * mul_b: no branches in the
-    // address arithmetic, so the loads of kDepth steps can stay in flight.
-    const bool along_u = a.ct[z] == 0;
-    const int cs = along_u ? a.cs[z] : a.ct[z];
-    const int amax = along_u ? W - 1 : H - 1;
-    const uint32_t mul_a = along_u ? 1u : (uint32_t)W, mul_b = along_u ? (uint32_t)W : 1u;
-    const int da = along_u ? li.du : li.dv, db = along_u ? li.dv : li.du;
-    const int a0 = along_u ? li.u0 : li.v0, b0 = along_u ? li.v0 : li.u0;
-    int sh[K];
-    uint32_t cinit[K];                 // popcount accumulator: 0, or kInf past N
+    // the lane's K bytes of a pixel row; lanes past N read in-row bytes and add kInf
+    const uint32_t lofs = (uint32_t)min(lane * K, NP - K);
+    uint32_t cinit[K];
 #pragma unroll
-    for (int j = 0; j < K; ++j) {
-        const int k = lane * K + j;
-        sh[j] = (int)rintf((float)cs * hyp[min(k, N - 1)]);
-        cinit[j] = k < N ? 0u : kInf;
-    }
+    for (int j = 0; j < K; ++j) cinit[j] = lane * K + j < N ? 0u : kInf;
     const int last = li.len - 1;
-    auto load = [&](int step, uint64_t& r, uint64_t (&x)[K]) {
+    auto load = [&](int step) -> uint32_t {
         step = min(step, last);
-        const int av = a0 + step * da, bv = b0 + step * db;
-        const uint32_t bterm = (uint32_t)bv * mul_b;
-        r = cref[in_vgpr((uint32_t)av * mul_a + bterm)];
-#pragma unroll
-        for (int j = 0; j < K; ++j)
-            x[j] = cv[(uint32_t)clampi(av + sh[j], 0, amax) * mul_a + bterm];
+        const uint32_t p = (uint32_t)((li.v0 + step * li.dv) * W + li.u0 + step * li.du);
+        const uint32_t o = p * (uint32_t)NP + lofs;      // 32-bit offset off a scalar base
+        if constexpr (K == 1) return cz[o];
+        else if constexpr (K == 2) return *(const uint16_t*)(cz + o);
+        else if constexpr (K == 4) return *(const uint32_t*)(cz + o);
+        else return (uint32_t)cz[o] | ((uint32_t)cz[o + 1] << 8) | ((uint32_t)cz[o + 2] << 16);
     };
-    uint64_t rb[kDepth], xb[kDepth][K];
+    uint32_t cb[kDepth];
 #pragma unroll
-    for (int i = 0; i < kDepth; ++i) load(i, rb[i], xb[i]);
+    for (int i = 0; i < kDepth; ++i) cb[i] = load(i);
 
     uint32_t Lp[K], m = 0;
 #pragma unroll
@@ -207,10 +228,8 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void sgm_dense_paths_kernel(
             const int step = base + i;           // steps past the line end are computed
             uint32_t C[K];                       // and not stored
 #pragma unroll
-            for (int j = 0; j < K; ++j)
-                C[j] = __popc((uint32_t)(rb[i] ^ xb[i][j])) +
-                       __popc((uint32_t)((rb[i] ^ xb[i][j]) >> 32)) + cinit[j];
-            load(step + kDepth, rb[i], xb[i]);   // refill the slot just consumed
+            for (int j = 0; j < K; ++j) C[j] = ((cb[i] >> (8 * j)) & 0xFFu) + cinit[j];
+            cb[i] = load(step + kDepth);         // refill the slot just consumed
             uint32_t L[K];
             if (step == 0) {
 #pragma unroll
@@ -220,20 +239,21 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void sgm_dense_paths_kernel(
             }
             m = wave_min(lane_min(L));
 
-            const int u = li.u0 + step * li.du, v = li.v0 + step * li.dv;
-            LT* row = out + (size_t)(v * W + u) * NP + lane * K;
-            const bool live = step < li.len;
-            if constexpr (K == 2) {
-                if (live && lane * 2 < N) {        // a pair: one 16- or 32-bit store
-                    if constexpr (sizeof(LT) == 1)
-                        *(uint16_t*)row = (uint16_t)((L[0] & 0xFF) | (L[1] << 8));
-                    else
-                        *(uint32_t*)row = (L[0] & 0xFFFF) | (L[1] << 16);
-                }
-            } else {
+            const uint32_t p = (uint32_t)((li.v0 + step * li.dv) * W + li.u0 + step * li.du);
+            const uint32_t e0 = p * (uint32_t)NP + (uint32_t)(lane * K);   // element offset
+            if (step < li.len) {
+                if constexpr (K == 2) {
+                    if (lane * 2 < N) {          // a pair: one 16- or 32-bit store
+                        if constexpr (sizeof(LT) == 1)
+                            *(uint16_t*)(out + e0) = (uint16_t)((L[0] & 0xFF) | (L[1] << 8));
+                        else
+                            *(uint32_t*)(out + e0) = (L[0] & 0xFFFF) | (L[1] << 16);
+                    }
+                } else {
 #pragma unroll
-                for (int j = 0; j < K; ++j)
-                    if (live && lane * K + j < N) row[j] = (LT)L[j];
+                    for (int j = 0; j < K; ++j)
+                        if (lane * K + j < N) out[e0 + j] = (LT)L[j];
+                }
             }
 #pragma unroll
             for (int j = 0; j < K; ++j) Lp[j] = L[j];
@@ -387,11 +407,11 @@ __global__ __launch_bounds__(256) void bounded_sum_kernel(const uint16_t* __rest
 }
 
 template <int K, typename LT>
-hipError_t dense_launch(const SgmDense& a, const Lines& lines, const float* hyp, int H, int W,
-                        int N, int NP, int P1, int P2, void* Lbuf, hipStream_t st) {
+hipError_t dense_launch(const SgmDense& a, const Lines& lines, int H, int W, int N, int NP, int P1,
+                        int P2, const uint8_t* cvol, void* Lbuf, hipStream_t st) {
     dim3 grid((lines.base[lines.npaths] + kWavesPerBlock - 1) / kWavesPerBlock, a.nv);
-    hipLaunchKernelGGL((sgm_dense_paths_kernel<K, LT>), grid, dim3(64 * kWavesPerBlock), 0, st, a,
-                       lines, hyp, H, W, N, NP, (uint32_t)P1, (uint32_t)P2, (LT*)Lbuf);
+    hipLaunchKernelGGL((sgm_dense_paths_kernel<K, LT>), grid, dim3(64 * kWavesPerBlock), 0, st,
+                       cvol, a.nv, lines, H, W, N, NP, (uint32_t)P1, (uint32_t)P2, (LT*)Lbuf);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t HW = (int64_t)H * W;
@@ -403,13 +423,13 @@ hipError_t dense_launch(const SgmDense& a, const Lines& lines, const float* hyp,
 }
 
 template <typename LT>
-hipError_t dense_dispatch(const SgmDense& a, const Lines& lines, const float* hyp, int H, int W,
-                          int N, int NP, int P1, int P2, void* Lbuf, hipStream_t st) {
+hipError_t dense_dispatch(const SgmDense& a, const Lines& lines, int H, int W, int N, int NP,
+                          int P1, int P2, const uint8_t* cvol, void* Lbuf, hipStream_t st) {
     switch ((N + 63) / 64) {
-        case 1: return dense_launch<1, LT>(a, lines, hyp, H, W, N, NP, P1, P2, Lbuf, st);
-        case 2: return dense_launch<2, LT>(a, lines, hyp, H, W, N, NP, P1, P2, Lbuf, st);
-        case 3: return dense_launch<3, LT>(a, lines, hyp, H, W, N, NP, P1, P2, Lbuf, st);
-        default: return dense_launch<4, LT>(a, lines, hyp, H, W, N, NP, P1, P2, Lbuf, st);
+        case 1: return dense_launch<1, LT>(a, lines, H, W, N, NP, P1, P2, cvol, Lbuf, st);
+        case 2: return dense_launch<2, LT>(a, lines, H, W, N, NP, P1, P2, cvol, Lbuf, st);
+        case 3: return dense_launch<3, LT>(a, lines, H, W, N, NP, P1, P2, cvol, Lbuf, st);
+        default: return dense_launch<4, LT>(a, lines, H, W, N, NP, P1, P2, cvol, Lbuf, st);
     }
 }
 
@@ -427,9 +447,12 @@ hipError_t bounded_launch(const SgmBounded& a, const PixMeta* meta, const Lines&
 
 int dense_np(int N) { return (N + 3) / 4 * 4; }
 
+static size_t round256(size_t x) { return (x + 255) / 256 * 256; }
+
 size_t sgm_dense_scratch_bytes(int nv, int H, int W, int N, int npaths, int bits, int P2) {
     const size_t lt = bits + P2 <= 255 ? 1 : 2;
-    return (size_t)npaths * nv * H * W * dense_np(N) * lt;
+    const size_t cv = round256((size_t)nv * H * W * dense_np(N));
+    return cv + (size_t)npaths * nv * H * W * dense_np(N) * lt;
 }
 
 size_t sgm_bounded_scratch_bytes(int H, int W, int N, int npaths) {
@@ -441,9 +464,16 @@ hipError_t launch_sgm_dense(const SgmDense& a, const float* hyp, int H, int W, i
                             int P2, int npaths, int bits, void* scratch, hipStream_t st) {
     const Lines lines = make_lines(H, W, npaths);
     const int NP = dense_np(N);
+    uint8_t* cvol = (uint8_t*)scratch;
+    void* Lbuf = (char*)scratch + round256((size_t)a.nv * H * W * NP);
+    const uint32_t threads = (uint32_t)H * W * (NP / 4);
+    hipLaunchKernelGGL(census_cost_volume_kernel, dim3((threads + 255) / 256, a.nv), dim3(256), 0,
+                       st, a, hyp, H, W, N, NP, cvol);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
     if (bits + P2 <= 255)
-        return dense_dispatch<uint8_t>(a, lines, hyp, H, W, N, NP, P1, P2, scratch, st);
-    return dense_dispatch<uint16_t>(a, lines, hyp, H, W, N, NP, P1, P2, scratch, st);
+        return dense_dispatch<uint8_t>(a, lines, H, W, N, NP, P1, P2, cvol, Lbuf, st);
+    return dense_dispatch<uint16_t>(a, lines, H, W, N, NP, P1, P2, cvol, Lbuf, st);
 }
 
 hipError_t launch_sgm_bounded(const SgmBounded& a, int H, int W, int N, int P1, int P2,
