@@ -27,21 +27,11 @@ struct CellMap {
     int p0;                     // first pixel
 };
 
-// Blocks are dealt to the 8 XCDs round-robin by block id; remap them so that
-// each XCD (and its L2) works on one contiguous band of image rows, whose view
-// rows overlap, instead of every XCD touching every row of every view.
-__device__ __forceinline__ int xcd_band_block(int nblocks) {
-    const int per = (nblocks + 7) / 8;
-    return (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
-}
-
-inline int xcd_band_grid(int nblocks) { return (nblocks + 7) / 8 * 8; }
-
 // Stages offsets/lo of the workgroup's pixels; returns its cell span.
-__device__ __forceinline__ CellMap stage_cells(int blk, const int64_t* __restrict__ off,
+__device__ __forceinline__ CellMap stage_cells(const int64_t* __restrict__ off,
                                                const int16_t* __restrict__ lo, int HW,
                                                int64_t* s_off, int* s_lo) {
-    const int p0 = blk * kPix;
+    const int p0 = blockIdx.x * kPix;
     const int np = min(kPix, HW - p0);
     for (int i = threadIdx.x; i <= np; i += kThreads) {
         s_off[i] = off[p0 + i];
@@ -61,42 +51,18 @@ __device__ __forceinline__ int find_pixel(const int64_t* s_off, int np, int64_t 
     return a;
 }
 
-// Bilinear sample shift of one view axis for hypothesis d: integer part and
-// weight of sh = c*d (rounded once), the two taps clamped to [0, n-1].
-struct AxisTap {
-    int a, b;
-    float f;
-};
-
-__device__ __forceinline__ AxisTap axis_tap(int c, float d, int pos, int n) {
-    const float sh = (float)c * d;
-    const float i0 = floorf(sh);
-    AxisTap t;
-    t.f = sh - i0;
-    t.a = clampi(pos + (int)i0, 0, n - 1);
-    t.b = clampi(pos + (int)i0 + 1, 0, n - 1);
-    return t;
-}
-
-// S_ and T_ > 0: the angular grid is known at compile time and the per-view
-// shift terms of a cell live in registers; 0: runtime loops.
-template <typename T, int S_, int T_>
+template <typename T>
 __global__ __launch_bounds__(kThreads) void cost_l2_kernel(
-    const T* __restrict__ views, int S_rt, int T_rt, int H, int W, int pitch,
+    const T* __restrict__ views, int S, int T_, int H, int W, int pitch,
     const float* __restrict__ hyp, int N, const int16_t* __restrict__ lo,
     const int64_t* __restrict__ off, float alpha, float cap, uint16_t* __restrict__ cost,
     float* __restrict__ cost_f32, int64_t cap_cells) {
     __shared__ int64_t s_off[kPix + 1];
     __shared__ int s_lo[kPix];
-    const int S = S_ > 0 ? S_ : S_rt;
-    const int TT = T_ > 0 ? T_ : T_rt;
     const int HW = H * W;
-    const int nblocks = (HW + kPix - 1) / kPix;
-    const int blk = xcd_band_block(nblocks);
-    if (blk >= nblocks) return;
-    const CellMap cm = stage_cells(blk, off, lo, HW, s_off, s_lo);
+    const CellMap cm = stage_cells(off, lo, HW, s_off, s_lo);
     const int np = min(kPix, HW - cm.p0);
-    const int sh = (S - 1) / 2, th = (TT - 1) / 2;
+    const int sh = (S - 1) / 2, th = (T_ - 1) / 2;
     const size_t vstride = (size_t)H * pitch;
     const T* __restrict__ refv = views + ((size_t)th * S + sh) * vstride;
 
@@ -110,56 +76,25 @@ __global__ __launch_bounds__(kThreads) void cost_l2_kernel(
         const float d = hyp[k];
         const float ref = ld(refv + (size_t)v * pitch + u);
         float acc = 0.0f;
-        if constexpr (S_ > 0 && T_ > 0) {
-            // byte offsets from `views`: x taps carry s*vstride, y taps t*S*vstride,
-            // so a tap address is one add and no per-view base is kept
-            const char* __restrict__ vb = (const char*)views;
-            const uint32_t vbytes = (uint32_t)(vstride * sizeof(T));
-            AxisTap xs[S_], ys[T_];
-#pragma unroll
-            for (int s = 0; s < S_; ++s) {
-                xs[s] = axis_tap(sh - s, d, u, W);
-                xs[s].a = xs[s].a * (int)sizeof(T) + s * (int)vbytes;
-                xs[s].b = xs[s].b * (int)sizeof(T) + s * (int)vbytes;
-            }
-#pragma unroll
-            for (int t = 0; t < T_; ++t) {
-                ys[t] = axis_tap(th - t, d, v, H);
-                ys[t].a = ys[t].a * pitch * (int)sizeof(T) + t * S_ * (int)vbytes;
-                ys[t].b = ys[t].b * pitch * (int)sizeof(T) + t * S_ * (int)vbytes;
-            }
-#pragma unroll
-            for (int t = 0; t < T_; ++t) {
-#pragma unroll
-                for (int s = 0; s < S_; ++s) {
-                    if (s == sh && t == th) continue;        // adds exactly +0
-                    const float a = ld((const T*)(vb + (uint32_t)(ys[t].a + xs[s].a)));
-                    const float b = ld((const T*)(vb + (uint32_t)(ys[t].a + xs[s].b)));
-                    const float cc = ld((const T*)(vb + (uint32_t)(ys[t].b + xs[s].a)));
-                    const float e = ld((const T*)(vb + (uint32_t)(ys[t].b + xs[s].b)));
-                    const float top = fmaf(xs[s].f, b - a, a);
-                    const float bot = fmaf(xs[s].f, e - cc, cc);
-                    const float val = fmaf(ys[t].f, bot - top, top);
-                    acc = acc + fabsf(ref - val);
-                }
-            }
-        } else {
-            for (int t = 0; t < TT; ++t) {
-                const AxisTap y = axis_tap(th - t, d, v, H);
-                const T* __restrict__ vt = views + (size_t)t * S * vstride;
-                for (int s = 0; s < S; ++s) {
-                    if (s == sh && t == th) continue;
-                    const AxisTap x = axis_tap(sh - s, d, u, W);
-                    const T* __restrict__ vs = vt + (size_t)s * vstride;
-                    const float a = ld(vs + (size_t)y.a * pitch + x.a);
-                    const float b = ld(vs + (size_t)y.a * pitch + x.b);
-                    const float cc = ld(vs + (size_t)y.b * pitch + x.a);
-                    const float e = ld(vs + (size_t)y.b * pitch + x.b);
-                    const float top = fmaf(x.f, b - a, a);
-                    const float bot = fmaf(x.f, e - cc, cc);
-                    const float val = fmaf(y.f, bot - top, top);
-                    acc = acc + fabsf(ref - val);
-                }
+        for (int t = 0; t < T_; ++t) {
+            const float shy = (float)(th - t) * d;
+            const float y0 = floorf(shy);
+            const float fy = shy - y0;
+            const int ya = clampi(v + (int)y0, 0, H - 1), yb = clampi(v + (int)y0 + 1, 0, H - 1);
+            const T* __restrict__ vt = views + (size_t)t * S * vstride;
+            for (int s = 0; s < S; ++s) {
+                if (s == sh && t == th) continue;
+                const float shx = (float)(sh - s) * d;
+                const float x0 = floorf(shx);
+                const float fx = shx - x0;
+                const int xa = clampi(u + (int)x0, 0, W - 1), xb = clampi(u + (int)x0 + 1, 0, W - 1);
+                const T* __restrict__ vs = vt + (size_t)s * vstride;
+                const float a = ld(vs + (size_t)ya * pitch + xa), b = ld(vs + (size_t)ya * pitch + xb);
+                const float cc = ld(vs + (size_t)yb * pitch + xa), e = ld(vs + (size_t)yb * pitch + xb);
+                const float top = fmaf(fx, b - a, a);
+                const float bot = fmaf(fx, e - cc, cc);
+                const float val = fmaf(fy, bot - top, top);
+                acc = acc + fabsf(ref - val);
             }
         }
         const float q = rintf(alpha * acc);
@@ -176,10 +111,7 @@ __global__ __launch_bounds__(kThreads) void cost_census_all_kernel(
     __shared__ int64_t s_off[kPix + 1];
     __shared__ int s_lo[kPix];
     const int HW = H * W;
-    const int nblocks = (HW + kPix - 1) / kPix;
-    const int blk = xcd_band_block(nblocks);
-    if (blk >= nblocks) return;
-    const CellMap cm = stage_cells(blk, off, lo, HW, s_off, s_lo);
+    const CellMap cm = stage_cells(off, lo, HW, s_off, s_lo);
     const int np = min(kPix, HW - cm.p0);
     const int sh = (S - 1) / 2, th = (T_ - 1) / 2;
     const uint64_t* __restrict__ cref = census + ((size_t)th * S + sh) * HW;
@@ -207,36 +139,21 @@ __global__ __launch_bounds__(kThreads) void cost_census_all_kernel(
 
 }  // namespace
 
-template <typename T>
-void launch_l2_typed(dim3 grid, hipStream_t st, const T* views, int S, int T_, int H, int W,
-                     int pitch, const float* hyp, int N, const int16_t* lo, const int64_t* off,
-                     float alpha, float cap, uint16_t* cost, float* cost_f32, int64_t cap_cells) {
-#define LF_L2(SS, TTT)                                                                          \
-    hipLaunchKernelGGL((cost_l2_kernel<T, SS, TTT>), grid, dim3(kThreads), 0, st, views, S, T_, \
-                       H, W, pitch, hyp, N, lo, off, alpha, cap, cost, cost_f32, cap_cells)
-    if (S == 9 && T_ == 9) LF_L2(9, 9);
-    else if (S == 7 && T_ == 7) LF_L2(7, 7);
-    else if (S == 5 && T_ == 5) LF_L2(5, 5);
-    else if (S == 3 && T_ == 3) LF_L2(3, 3);
-    else if (S == 15 && T_ == 15) LF_L2(15, 15);
-    else if (S == 11 && T_ == 1) LF_L2(11, 1);
-    else LF_L2(0, 0);
-#undef LF_L2
-}
-
 hipError_t launch_cost_l2(const void* views, int dtype, int S, int T, int H, int W, int pitch,
                           const float* hyp, int N, const int16_t* lo, const int16_t* hi,
                           const int64_t* off, float alpha, int32_t cap, uint16_t* cost,
                           float* cost_f32, int64_t cap_cells, hipStream_t st) {
     (void)hi;
     const int HW = H * W;
-    dim3 grid(xcd_band_grid((HW + kPix - 1) / kPix));
+    dim3 grid((HW + kPix - 1) / kPix);
     if (dtype == LF_U8)
-        launch_l2_typed<uint8_t>(grid, st, (const uint8_t*)views, S, T, H, W, pitch, hyp, N, lo,
-                                 off, alpha, (float)cap, cost, cost_f32, cap_cells);
+        hipLaunchKernelGGL(cost_l2_kernel<uint8_t>, grid, dim3(kThreads), 0, st,
+                           (const uint8_t*)views, S, T, H, W, pitch, hyp, N, lo, off, alpha,
+                           (float)cap, cost, cost_f32, cap_cells);
     else
-        launch_l2_typed<float>(grid, st, (const float*)views, S, T, H, W, pitch, hyp, N, lo, off,
-                               alpha, (float)cap, cost, cost_f32, cap_cells);
+        hipLaunchKernelGGL(cost_l2_kernel<float>, grid, dim3(kThreads), 0, st,
+                           (const float*)views, S, T, H, W, pitch, hyp, N, lo, off, alpha,
+                           (float)cap, cost, cost_f32, cap_cells);
     return hipGetLastError();
 }
 
@@ -246,7 +163,7 @@ hipError_t launch_cost_census_all(const uint64_t* census_all, int S, int T, int 
                                   float* cost_f32, int64_t cap_cells, hipStream_t st) {
     (void)hi;
     const int HW = H * W;
-    dim3 grid(xcd_band_grid((HW + kPix - 1) / kPix));
+    dim3 grid((HW + kPix - 1) / kPix);
     hipLaunchKernelGGL(cost_census_all_kernel, grid, dim3(kThreads), 0, st, census_all, S, T, H,
                        W, hyp, N, lo, off, (uint32_t)cap, cost, cost_f32, cap_cells);
     return hipGetLastError();

@@ -154,35 +154,45 @@ __device__ __forceinline__ uint32_t lane_min(const uint32_t (&L)[K]) {
 // ---------------------------------------------------------------------------
 // Initial stage, Eq. (7): the Census cost volume C[z][p][NP] (8-bit, NP = N
 // rounded up to 4) of every cross view, computed once and read by all path
-// directions.  A thread fills 4 hypotheses of one pixel (one 32-bit store);
-// consecutive threads walk the hypotheses of a pixel, then the next pixel.
+// directions.  A workgroup builds the tile of 64 consecutive pixels x NP
+// hypotheses in LDS with lanes over pixels -- for a fixed hypothesis the 64
+// gathered Census strings are consecutive in memory for both shift axes -- and
+// then writes the tile, which is contiguous in C, with 32-bit stores.
+constexpr int kTilePix = 64;
+
 __global__ __launch_bounds__(256) void census_cost_volume_kernel(SgmDense a,
                                                                  const float* __restrict__ hyp,
                                                                  int H, int W, int N, int NP,
                                                                  uint8_t* __restrict__ cvol) {
+    __shared__ uint32_t tile[kTilePix * LF_MAX_HYPOTHESES / 4];
+    __shared__ int s_sh[LF_MAX_HYPOTHESES];
     const int z = blockIdx.y;
-    const int groups = NP / 4;
     const uint32_t HW = (uint32_t)H * W;
-    const uint32_t t = blockIdx.x * 256 + threadIdx.x;
-    if (t >= HW * (uint32_t)groups) return;
-    const uint32_t p = t / groups;
-    const int k0 = (int)(t - p * groups) * 4;
-    const int v = (int)(p / W), u = (int)(p - (uint32_t)v * W);
+    const uint32_t p0 = blockIdx.x * kTilePix;
+    const int npix = (int)min((uint32_t)kTilePix, HW - p0);
     const bool along_u = a.ct[z] == 0;
     const int cs = along_u ? a.cs[z] : a.ct[z];
+    for (int k = threadIdx.x; k < NP; k += 256)
+        s_sh[k] = (int)rintf((float)cs * hyp[min(k, N - 1)]);
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t p = p0 + (uint32_t)min(lane, npix - 1);
+    const int v = (int)(p / W), u = (int)(p - (uint32_t)v * W);
     const uint64_t r = a.cref[p];
     const uint64_t* __restrict__ cv = a.cview + (size_t)z * HW;
-    uint32_t packed = 0;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int k = k0 + j;
-        const int sh = (int)rintf((float)cs * hyp[min(k, N - 1)]);
+    uint8_t* t8 = (uint8_t*)tile;
+    for (int k = wave; k < NP; k += 4) {          // k is wave-uniform
+        const int sh = s_sh[k];
         const uint32_t q = along_u ? (uint32_t)(v * W + clampi(u + sh, 0, W - 1))
                                    : (uint32_t)(clampi(v + sh, 0, H - 1) * W + u);
-        const uint32_t c = k < N ? (uint32_t)__popcll(r ^ cv[q]) : 0u;
-        packed |= c << (8 * j);
+        t8[lane * NP + k] = k < N ? (uint8_t)__popcll(r ^ cv[q]) : (uint8_t)0;
     }
-    *(uint32_t*)(cvol + ((size_t)z * HW + p) * NP + k0) = packed;
+    __syncthreads();
+    // the tile is npix * NP contiguous bytes of C (NP is a multiple of 4)
+    uint32_t* dst = (uint32_t*)(cvol + ((size_t)z * HW + p0) * NP);
+    const int words = npix * NP / 4;
+    for (int i = threadIdx.x; i < words; i += 256) dst[i] = tile[i];
 }
 
 // SGM over the Census cost volume, every direction of every view in one launch;
@@ -466,9 +476,9 @@ hipError_t launch_sgm_dense(const SgmDense& a, const float* hyp, int H, int W, i
     const int NP = dense_np(N);
     uint8_t* cvol = (uint8_t*)scratch;
     void* Lbuf = (char*)scratch + round256((size_t)a.nv * H * W * NP);
-    const uint32_t threads = (uint32_t)H * W * (NP / 4);
-    hipLaunchKernelGGL(census_cost_volume_kernel, dim3((threads + 255) / 256, a.nv), dim3(256), 0,
-                       st, a, hyp, H, W, N, NP, cvol);
+    const uint32_t tiles = ((uint32_t)H * W + kTilePix - 1) / kTilePix;
+    hipLaunchKernelGGL(census_cost_volume_kernel, dim3(tiles, a.nv), dim3(256), 0, st, a, hyp, H,
+                       W, N, NP, cvol);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (bits + P2 <= 255)
