@@ -75,6 +75,10 @@ def _case(name):
         lf = lfsynth.workload("paper_s", seed=12, H=50, W=1, S=3, T=3, N=9)
         lf.params.update(win_h=3, win_w=3, median=0, fill=3)
         return lf
+    if name == "u16_paths":                  # bits + P2 > 255: 16-bit path-cost storage
+        lf = lfsynth.workload("paper_s", seed=14, H=37, W=45, S=5, T=5, N=70)
+        lf.params.update(P1_init=60, P2_init=250)
+        return lf
     if name == "census_cost":                # Eq. (15) as the final cost
         lf = lfsynth.workload("paper_s", seed=13, H=40, W=52, S=5, T=5, N=24)
         lf.params.update(cost_kind=1, win_h=5, win_w=5, sum_bits=16)
@@ -83,7 +87,7 @@ def _case(name):
 
 
 CASES = ["small", "f32_ragged", "u8_n65", "n256", "stage_1x11", "col_7x1", "one_row", "one_col",
-         "census_cost"]
+         "u16_paths", "census_cost"]
 
 
 def _to_dev(lfd):
