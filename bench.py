@@ -29,12 +29,33 @@ sys.path.insert(0, ROOT)
 
 METRIC = ("Gcells/s (pixel×hypothesis, cost+SGM) and depth maps/s at 9×9×512² "
           "vs plain; p99")
-HBM_PEAK_GBS = 8000.0
-# Algorithmic bytes per cell of the initial stage (Census cost + SGM + WTA over the
-# cross views): the 16-bit aggregated cost must make 4 orientation round trips
-# (write, 3 x read+write, final read fused into WTA) = 12 B/cell; the Census
-# strings and the maps add (2*8 + 2)/N B/cell.
-INIT_BYTES_PER_CELL = 12.0
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP32_PEAK_TFLOPS = 157.3       # MI355X fp32 vector
+
+
+def stage_models(S, T, cells_initial, cells_bounded, sum_bits):
+    """Algorithmic work of each stage per light field and the resource that bounds it.
+
+    sgm_initial  (Census cost + SGM + WTA over the cross views): HBM, 12 B/cell --
+                 the 16-bit aggregated cost must make 4 orientation round trips
+                 (write, 3 x read+write, the last read fused into WTA).
+    cost_bounded (l2 over all views, Eq. 12): fp32 ALU, 11 flop per view and cell
+                 (3 FMA, 3 differences, |ref - val|, the running sum) over the
+                 S*T - 1 views that are not the reference.
+    sgm_bounded  (bounded SGM): HBM, 8 B/cell of cost reads (one per orientation)
+                 plus 12 (16-bit sums) or 24 (32-bit sums) B/cell of sum state.
+    """
+    return {
+        "sgm_initial": dict(bound="hbm", unit="GB/s", peak=HBM_PEAK_GBS,
+                            work=12.0 * cells_initial / 1e9,
+                            kernel="census_cost_volume + sgm_dense_paths + dense_sum_wta"),
+        "cost_bounded": dict(bound="alu", unit="TFLOP/s", peak=FP32_PEAK_TFLOPS,
+                             work=11.0 * (S * T - 1) * cells_bounded / 1e12,
+                             kernel="cost_l2_kernel"),
+        "sgm_bounded": dict(bound="hbm", unit="GB/s", peak=HBM_PEAK_GBS,
+                            work=(8.0 + (12.0 if sum_bits == 16 else 24.0)) * cells_bounded / 1e9,
+                            kernel="sgm_bounded_paths + bounded_sum"),
+    }
 
 
 def log(*a):
@@ -46,10 +67,10 @@ def source_sha(path):
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def load_traffic(kernel_src):
-    """HBM bytes per launch measured by rocprofv3 counters for the current source of the
-    dominant kernel, or None if the counters were taken on another version."""
-    path = os.path.join(ROOT, "profiles", "sgm_initial_9x9x512_N100.traffic.txt")
+def load_traffic(kernel, src):
+    """HBM bytes per launch of `kernel` measured by rocprofv3 counters (profiles/), or None
+    if the counters were taken on another version of its source."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}.traffic.txt")
     if not os.path.exists(path):
         return None
     rec = {}
@@ -57,7 +78,7 @@ def load_traffic(kernel_src):
         if "=" in line and not line.startswith("#"):
             k, v = line.split("=", 1)
             rec[k.strip()] = v.strip()
-    if rec.get("source_sha") != source_sha(kernel_src):
+    if rec.get("source_sha") != source_sha(src):
         return None
     try:
         return float(rec["bytes_per_launch"])
@@ -148,11 +169,21 @@ def main():
 
     stage_ms = {k: v[0] / args.steps for k, v in stages.items()}
     stage_launches = {k: v[1] // args.steps for k, v in stages.items()}
-    k_ms, k_launch = stages["sgm_initial"]
-    avg_launch_ms = k_ms / k_launch
-    bytes_per_launch = INIT_BYTES_PER_CELL * cells_initial / stage_launches["sgm_initial"]
-    achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
-    traffic = load_traffic(os.path.join(ROOT, "paper_1907_13449_amd", "csrc", "sgm.hip"))
+    models = stage_models(S, T, cells_initial, cells_bounded, p["sum_bits"])
+    roofs = {}
+    for name, m in models.items():
+        sec = stage_ms[name] * 1e-3
+        achieved = m["work"] / sec          # GB/s or TFLOP/s
+        roofs[name] = {"kernel": m["kernel"], "bound": m["bound"], "achieved": achieved,
+                       "peak": m["peak"], "unit": m["unit"], "frac": achieved / m["peak"],
+                       "ms": stage_ms[name], "launches": stage_launches[name],
+                       "avg_launch_ms": stage_ms[name] / max(stage_launches[name], 1)}
+    dominant = max(roofs, key=lambda k: roofs[k]["ms"])
+    src = {"sgm_initial": "sgm.hip", "sgm_bounded": "sgm.hip", "cost_bounded": "cost.hip"}
+    roofline = dict(roofs[dominant])
+    roofline["stage"] = dominant
+    roofline["traffic"] = load_traffic(
+        dominant, os.path.join(ROOT, "paper_1907_13449_amd", "csrc", src[dominant]))
 
     if args.calib_copy:
         a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
@@ -185,13 +216,8 @@ def main():
         "p50_ms": float(np.percentile(lat, 50)),
         "p99_ms": float(np.percentile(lat, 99)),
         "stage_ms": stage_ms,
-        "stage_launches": stage_launches,
-        "roofline": {"kernel": "sgm_dense_kernel (initial Census cost + SGM + WTA)",
-                     "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic,
-                     "avg_launch_ms": avg_launch_ms,
-                     "algorithmic_bytes_per_launch": bytes_per_launch},
+        "roofline": roofline,
+        "stage_roofline": roofs,
     }
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on one light field")

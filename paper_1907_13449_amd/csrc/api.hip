@@ -428,7 +428,7 @@ lf_status lf_initial_disparity(const lf_view_set* views, const float* hyp, int32
         a.ct[i] = th - st[2 * i + 1];
     }
     {
-        prof::Scope _ps(prof::kSgmInit, stream, 2);
+        prof::Scope _ps(prof::kSgmInit, stream, 3);
     LF_HIP(lf::launch_sgm_dense(a, hyp, H, W, N, prm->sgm_init.P1, prm->sgm_init.P2,
                                     prm->sgm_init.npaths,
                                     prm->census.win_h * prm->census.win_w - 1, pl.paths, stream),
