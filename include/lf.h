@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define LF_ABI_VERSION 1
+#define LF_ABI_VERSION 2
 #define LF_MAX_HYPOTHESES 256
 
 typedef enum {
@@ -50,7 +50,10 @@ typedef enum {
     LF_EINVAL = -1,        /* invalid argument (nothing enqueued) */
     LF_ENOSPACE = -2,      /* a caller buffer or the workspace is too small */
     LF_EDEVICE = -3,       /* a HIP call or kernel launch failed */
-    LF_EUNSUPPORTED = -4   /* valid, but outside what this build implements */
+    LF_EUNSUPPORTED = -4,  /* valid, but outside what this build implements */
+    LF_EBUSY = -5,         /* a queue is full or the object is in use; retry later */
+    LF_ETIMEOUT = -6,      /* a wait ended before the work did */
+    LF_ECANCELED = -7      /* the work was dropped before it ran */
 } lf_status;
 
 typedef enum { LF_U8 = 0, LF_F32 = 1 } lf_dtype;
@@ -224,6 +227,129 @@ size_t lf_depth_workspace_size(int32_t S, int32_t T, int32_t H, int32_t W, int32
 lf_status lf_depth(const lf_view_set* views, const float* hyp, int32_t N,
                    const lf_params* prm, float* disparity, int16_t* d_index, void* ws,
                    size_t ws_bytes, hipStream_t stream);
+
+
+/* ------------------------------------------------------------- batches
+ * Many light fields of uneven resolution, view count and hypothesis range run
+ * together: every stage of the method is ONE grouped launch over all of them
+ * (one launch per kernel variant: view type, hypotheses per lane, cost kind,
+ * sum width), and the whole sequence can be captured once into a HIP graph and
+ * replayed with a single graph launch.  Results are identical to lf_depth on
+ * each light field alone, for every tuning. */
+
+/* One light field and its outputs. */
+typedef struct {
+    lf_view_set views;
+    const float* hyp;       /* [N] device */
+    int32_t N;
+    lf_params params;
+    float* disparity;       /* [H][W] float32 output */
+    int16_t* d_index;       /* [H][W] int16 output, or NULL */
+} lf_request;
+
+/* Schedule parameters of the kernels; none changes a result.  0 selects the
+ * default.  cost_cells_per_thread: 2, 4 (default) or 8 -- cells per thread of
+ * one slice of the bounded cost kernel; cost_stride: 1 (default), 2 or 4 --
+ * slices each cost workgroup walks (persistent workgroups); dense_prefetch: 4, 8
+ * (default) or 16 -- path steps of cost loads in flight per wave in the initial
+ * SGM; bounded_prefetch: 4 or 8 (default) -- the same in the bounded SGM. */
+typedef struct {
+    int32_t cost_cells_per_thread;
+    int32_t cost_stride;
+    int32_t dense_prefetch;
+    int32_t bounded_prefetch;
+} lf_tuning;
+
+typedef struct lf_plan lf_plan;
+
+/* Workspace bytes of a batch: each light field's lf_depth workspace plus the
+ * plan's device tables.  reqs: host array of n >= 1 requests (only shapes and
+ * parameters are read).  Returns 0 for an invalid batch. */
+size_t lf_batch_workspace_size(const lf_request* reqs, int32_t n);
+
+/* Plans a batch over the caller's workspace (>= lf_batch_workspace_size bytes,
+ * 256-byte aligned) and enqueues the upload of its launch tables on `stream`.
+ * reqs is copied; its buffers must stay valid while the plan is used.  tuning
+ * may be NULL (defaults).  Validates every request as lf_depth does; on failure
+ * nothing is enqueued and *plan is NULL. */
+lf_status lf_plan_create(const lf_request* reqs, int32_t n, void* ws, size_t ws_bytes,
+                         const lf_tuning* tuning, hipStream_t stream, lf_plan** plan);
+
+/* Times each candidate schedule on the plan's own light fields (running the
+ * batch several times, `reps` timed runs per candidate, blocking) and keeps the
+ * fastest per stage; writes the choice to `chosen` (host, may be NULL).  Drops a
+ * captured graph.  The outputs hold the batch's results afterwards. */
+lf_status lf_plan_autotune(lf_plan* plan, hipStream_t stream, int32_t reps, lf_tuning* chosen);
+
+/* Captures the plan's launches into a HIP graph (once; later runs replay it). */
+lf_status lf_plan_capture(lf_plan* plan);
+
+/* Runs the batch on `stream`: one graph launch if captured, else the grouped
+ * launches one by one.  Must be ordered after the table upload of
+ * lf_plan_create / lf_plan_autotune (same stream, or synchronised). */
+lf_status lf_plan_run(lf_plan* plan, hipStream_t stream);
+
+/* Kernel launches per run (host), and the tuning in use. */
+int32_t lf_plan_launches(const lf_plan* plan);
+lf_status lf_plan_tuning(const lf_plan* plan, lf_tuning* out);
+
+/* Frees the plan's host memory and graph.  The caller keeps the workspace; work
+ * already enqueued must have completed before the workspace is reused. */
+void lf_plan_destroy(lf_plan* plan);
+
+/* -------------------------------------------------------- request loop
+ * A server that admits light fields as they arrive and runs them on the device
+ * with continuous batching: a scheduler thread admits pending requests whose
+ * workspace fits in the free part of a caller-provided device arena (first fit,
+ * later requests may pass one that does not fit yet), groups those admitted
+ * together into one batch plan and launches it on one of its streams while
+ * earlier batches are still running; when a batch completes its memory returns
+ * to the arena and waiting requests are admitted.  The arena (cost and
+ * aggregation buffers included) stays resident for the server's life. */
+
+typedef struct lf_server lf_server;
+
+typedef struct {
+    void* arena;                /* device memory owned by the caller, 256-byte aligned */
+    size_t arena_bytes;
+    int32_t max_batch;          /* light fields per batch (>= 1) */
+    int32_t max_inflight;       /* batches on the device at once (1..4); one stream each */
+    int32_t max_queue;          /* pending requests before lf_server_submit says LF_EBUSY */
+    lf_tuning tuning;           /* schedule of every batch (zeros: defaults) */
+} lf_server_config;
+
+/* Times of one request on the host steady clock, in seconds since the server
+ * was created, and the batch it ran in. */
+typedef struct {
+    double t_submit, t_admit, t_launch, t_done;
+    int64_t batch;              /* sequence number of its batch */
+    int32_t batch_size;         /* light fields in that batch */
+    int32_t status;             /* lf_status of the request */
+} lf_request_info;
+
+/* Creates the server and its scheduler thread (streams are created on first
+ * use, at default priority). */
+lf_status lf_server_create(const lf_server_config* cfg, lf_server** out);
+
+/* Queues a request (copied; its buffers must stay valid until it completes).
+ * Returns LF_EINVAL for an invalid request, LF_ENOSPACE if its workspace can
+ * never fit in the arena, LF_EBUSY if the queue is full; *ticket identifies it. */
+lf_status lf_server_submit(lf_server* srv, const lf_request* req, int64_t* ticket);
+
+/* Waits up to timeout_s seconds (< 0: forever) for a ticket; on completion
+ * returns the request's status (LF_OK when its outputs are ready) and fills
+ * *info (host, may be NULL), and forgets the ticket.  LF_ETIMEOUT if it is still
+ * running, LF_EINVAL for an unknown ticket. */
+lf_status lf_server_wait(lf_server* srv, int64_t ticket, double timeout_s, lf_request_info* info);
+
+/* Counters (host, any may be NULL): requests completed, batches launched, bytes
+ * of the arena in use now, and the most ever in use. */
+void lf_server_stats(const lf_server* srv, int64_t* completed, int64_t* batches,
+                     int64_t* arena_in_use, int64_t* arena_peak);
+
+/* Stops the scheduler: requests not yet launched complete with LF_ECANCELED,
+ * batches on the device are waited for; then frees the server. */
+void lf_server_destroy(lf_server* srv);
 
 #ifdef __cplusplus
 }

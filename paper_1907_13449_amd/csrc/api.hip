@@ -9,6 +9,27 @@
 #include <string>
 #include <vector>
 
+namespace lf {
+
+int cross_views(int S, int T, int* st) {
+    const int sh = (S - 1) / 2, th = (T - 1) / 2;
+    const int cand[4][2] = {{sh, 0}, {sh, T - 1}, {0, th}, {S - 1, th}};
+    int n = 0;
+    for (int i = 0; i < 4; ++i) {
+        const int s = cand[i][0], t = cand[i][1];
+        if (s == sh && t == th) continue;
+        bool dup = false;
+        for (int j = 0; j < n; ++j) dup |= st[2 * j] == s && st[2 * j + 1] == t;
+        if (dup) continue;
+        st[2 * n] = s;
+        st[2 * n + 1] = t;
+        ++n;
+    }
+    return n;
+}
+
+}  // namespace lf
+
 namespace {
 
 thread_local std::string g_err;
@@ -43,10 +64,9 @@ lf_status device_status(hipError_t e, const char* where) {
 // Opt-in stage timing: a HIP event pair recorded on the call's stream around
 // each group of launches.  Off by default; when off nothing is recorded.
 namespace prof {
-enum Stage { kCensus, kSgmInit, kBorders, kOffsets, kCost, kSgmFinal, kWta, kNumStages };
-const char* const kNames[kNumStages] = {"census", "sgm_initial", "fuse_fill_borders",
-                                        "offsets", "cost_bounded", "sgm_bounded",
-                                        "wta_subpixel_median"};
+const char* const kNames[lf::kNumStages] = {"census", "sgm_initial", "fuse_fill_borders",
+                                            "offsets", "cost_bounded", "sgm_bounded",
+                                            "wta_subpixel_median"};
 struct Rec {
     int stage, launches;
     hipEvent_t a, b;
@@ -67,15 +87,16 @@ hipEvent_t get_event() {
     return e;
 }
 
+// Brackets the launches a runner issues while the scope lives.
 struct Scope {
-    int stage, launches;
-    hipStream_t st;
+    int stage, before;
+    const lf::Runner& r;
     hipEvent_t a = nullptr;
-    Scope(int stage_, hipStream_t st_, int launches_) : stage(stage_), launches(launches_), st(st_) {
+    Scope(int stage_, const lf::Runner& r_) : stage(stage_), before(r_.launches), r(r_) {
         std::lock_guard<std::mutex> g(mu);
-        if (!on) return;
+        if (!on || r.rec) return;               // recorded launches are timed by their plan
         a = get_event();
-        if (a && hipEventRecord(a, st) != hipSuccess) {
+        if (a && hipEventRecord(a, r.stream) != hipSuccess) {
             pool.push_back(a);
             a = nullptr;
         }
@@ -84,8 +105,8 @@ struct Scope {
         if (!a) return;
         std::lock_guard<std::mutex> g(mu);
         hipEvent_t b = get_event();
-        if (b && hipEventRecord(b, st) == hipSuccess) {
-            pending.push_back(Rec{stage, launches, a, b});
+        if (b && hipEventRecord(b, r.stream) == hipSuccess) {
+            pending.push_back(Rec{stage, r.launches - before, a, b});
         } else {
             pool.push_back(a);
             if (b) pool.push_back(b);
@@ -109,23 +130,6 @@ struct Carve {
         return p;
     }
 };
-
-int cross_views(int S, int T, int* st) {
-    const int sh = (S - 1) / 2, th = (T - 1) / 2;
-    const int cand[4][2] = {{sh, 0}, {sh, T - 1}, {0, th}, {S - 1, th}};
-    int n = 0;
-    for (int i = 0; i < 4; ++i) {
-        const int s = cand[i][0], t = cand[i][1];
-        if (s == sh && t == th) continue;
-        bool dup = false;
-        for (int j = 0; j < n; ++j) dup |= st[2 * j] == s && st[2 * j + 1] == t;
-        if (dup) continue;
-        st[2 * n] = s;
-        st[2 * n + 1] = t;
-        ++n;
-    }
-    return n;
-}
 
 lf_status check_shape(int S, int T, int H, int W, int N) {
     if (S < 1 || T < 1 || S % 2 == 0 || T % 2 == 0)
@@ -211,7 +215,7 @@ struct InitPlan {
 size_t plan_initial(Carve& c, int S, int T, int H, int W, int N, const lf_params* prm,
                     InitPlan* p) {
     int st[8];
-    const int nv = cross_views(S, T, st);
+    const int nv = lf::cross_views(S, T, st);
     const size_t HW = (size_t)H * W;
     InitPlan q;
     q.census = (uint64_t*)c.take((1 + nv) * HW * sizeof(uint64_t));
@@ -281,6 +285,124 @@ size_t plan_depth(void* base, int S, int T, int H, int W, int N, const lf_params
     return c.used;
 }
 
+
+lf_status check_initial_size(int H, int W, int N) {
+    if ((int64_t)H * W * ((N + 3) / 4 * 4) * 2 >= ((int64_t)1 << 31))
+        return fail(LF_EUNSUPPORTED, "H*W*N = %lld cells per view (max 2^30)",
+                    (long long)H * W * N);
+    return LF_OK;
+}
+
+lf_status check_views_size(const lf_view_set* v) {
+    const int64_t bytes = (int64_t)v->S * v->T * v->H * v->pitch * (v->dtype == LF_U8 ? 1 : 4);
+    if (bytes >= ((int64_t)1 << 31))
+        return fail(LF_EUNSUPPORTED, "light field of %lld bytes (max 2 GiB)", (long long)bytes);
+    return LF_OK;
+}
+
+lf_status check_depth_args(const lf_view_set* views, const float* hyp, int N,
+                           const lf_params* prm, const float* disparity, const void* ws,
+                           size_t ws_bytes) {
+    LF_CHECK(check_views(views));
+    LF_CHECK(check_shape(views->S, views->T, views->H, views->W, N));
+    LF_CHECK(check_params(prm));
+    LF_CHECK(check_initial_size(views->H, views->W, N));
+    LF_CHECK(check_views_size(views));
+    if (!hyp || !disparity || !ws) return fail(LF_EINVAL, "NULL argument");
+    const size_t need = plan_depth(nullptr, views->S, views->T, views->H, views->W, N, prm, nullptr);
+    if (ws_bytes < need) return fail(LF_ENOSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
+    if ((uintptr_t)ws % kAlign) return fail(LF_EINVAL, "workspace not 256-byte aligned");
+    return LF_OK;
+}
+
+// The fields of a job that come from the light field and the parameters.
+lf::Job base_job(const lf_view_set* v, const float* hyp, int N, const lf_params* prm) {
+    lf::Job j{};
+    j.views = v->data;
+    j.dtype = v->dtype;
+    j.S = v->S;
+    j.T = v->T;
+    j.H = v->H;
+    j.W = v->W;
+    j.pitch = v->pitch;
+    j.N = N;
+    j.hyp = hyp;
+    j.prm = *prm;
+    j.alpha = eff_alpha(prm, v->dtype);
+    j.cap = lf_cost_cap(prm->sgm_final.P2, prm->sgm_final.npaths, prm->sum_bits);
+    j.nv = lf::cross_views(v->S, v->T, j.st);
+    return j;
+}
+
+// A whole-method job over the workspace layout of plan_depth.
+lf::Job depth_job(const lf_view_set* v, const float* hyp, int N, const lf_params* prm,
+                  float* disparity, int16_t* d_index, void* ws) {
+    DepthPlan pl;
+    plan_depth(ws, v->S, v->T, v->H, v->W, N, prm, &pl);
+    lf::Job j = base_job(v, hyp, N, prm);
+    Carve ci(pl.init_ws);
+    InitPlan ip;
+    plan_initial(ci, v->S, v->T, v->H, v->W, N, prm, &ip);
+    Carve cc(pl.cost_ws);
+    CostPlan cp;
+    plan_cost(cc, v->S, v->T, v->H, v->W, prm, &cp);
+    j.census = ip.census;
+    j.paths = ip.paths;
+    j.maps = ip.maps;
+    j.fill_tmp = ip.tmp;
+    j.dinit = pl.dinit;
+    j.lo = pl.lo;
+    j.hi = pl.hi;
+    j.offsets = pl.offsets;
+    j.scan = cp.scan;
+    j.census_all = cp.census_all;
+    j.cost = pl.cost;
+    j.cost_f32 = nullptr;
+    j.cap_cells = (int64_t)v->H * v->W * N;
+    j.sgm_ws = pl.sgm_ws;
+    j.csum = pl.csum;
+    j.d_index = d_index ? d_index : pl.d_index;
+    j.pre_median = pl.pre_median;
+    j.disparity = disparity;
+    return j;
+}
+
+lf_status run_initial(lf::Runner& r, const lf::Jobs& jobs) {
+    {
+        prof::Scope _ps(lf::kStCensus, r);
+        LF_HIP(lf::stage_census(r, jobs, false), "census");
+    }
+    {
+        prof::Scope _ps(lf::kStSgmInit, r);
+        LF_HIP(lf::stage_sgm_initial(r, jobs), "initial SGM");
+    }
+    prof::Scope _ps(lf::kStBorders, r);
+    LF_HIP(lf::stage_borders(r, jobs), "fusion/fill/borders");
+    return LF_OK;
+}
+
+lf_status run_cost(lf::Runner& r, const lf::Jobs& jobs) {
+    {
+        prof::Scope _ps(lf::kStOffsets, r);
+        LF_HIP(lf::stage_offsets(r, jobs), "offsets");
+    }
+    prof::Scope _ps(lf::kStCost, r);
+    LF_HIP(lf::stage_cost(r, jobs), "bounded cost");
+    return LF_OK;
+}
+
+lf_status run_depth(lf::Runner& r, const lf::Jobs& jobs) {
+    LF_CHECK(run_initial(r, jobs));
+    LF_CHECK(run_cost(r, jobs));
+    {
+        prof::Scope _ps(lf::kStSgmFinal, r);
+        LF_HIP(lf::stage_sgm_final(r, jobs), "bounded SGM");
+    }
+    prof::Scope _ps(lf::kStWta, r);
+    LF_HIP(lf::stage_wta(r, jobs), "wta/subpixel");
+    return LF_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -300,7 +422,7 @@ int32_t lf_profile_read(double* ms, int64_t* launches, int32_t n) {
         std::lock_guard<std::mutex> g(prof::mu);
         recs.swap(prof::pending);
     }
-    for (int i = 0; i < n && i < prof::kNumStages; ++i) {
+    for (int i = 0; i < n && i < lf::kNumStages; ++i) {
         if (ms) ms[i] = 0.0;
         if (launches) launches[i] = 0;
     }
@@ -317,11 +439,11 @@ int32_t lf_profile_read(double* ms, int64_t* launches, int32_t n) {
         prof::pool.push_back(r.a);
         prof::pool.push_back(r.b);
     }
-    return prof::kNumStages;
+    return lf::kNumStages;
 }
 
 const char* lf_profile_stage_name(int32_t i) {
-    return i >= 0 && i < prof::kNumStages ? prof::kNames[i] : "";
+    return i >= 0 && i < lf::kNumStages ? prof::kNames[i] : "";
 }
 
 const char* lf_last_error(void) { return g_err.c_str(); }
@@ -347,7 +469,7 @@ int32_t lf_cost_cap(int32_t P2_final, int32_t npaths, int32_t sum_bits) {
 
 int32_t lf_cross_views(int32_t S, int32_t T, int32_t* st) {
     int tmp[8];
-    const int n = cross_views(S, T, tmp);
+    const int n = lf::cross_views(S, T, tmp);
     if (st)
         for (int i = 0; i < 2 * n; ++i) st[i] = tmp[i];
     return n;
@@ -359,18 +481,15 @@ lf_status lf_census(const void* img, int32_t dtype, int32_t H, int32_t W, int32_
     if (dtype != LF_U8 && dtype != LF_F32) return fail(LF_EINVAL, "dtype %d", dtype);
     if (H < 1 || W < 1 || pitch < W) return fail(LF_EINVAL, "image %dx%d pitch %d", H, W, pitch);
     LF_CHECK(check_window(win));
-    lf::CensusBatch b{};
-    b.base = img;
-    b.off[0] = 0;
-    b.n = 1;
-    LF_HIP(lf::launch_census(b, dtype, H, W, pitch, win.win_h, win.win_w, out, stream),
-           "lf_census");
+    lf::Runner r;
+    r.stream = stream;
+    prof::Scope _ps(lf::kStCensus, r);
+    LF_HIP(lf::census_image(r, img, dtype, H, W, pitch, win.win_h, win.win_w, out), "lf_census");
     return LF_OK;
 }
 
 size_t lf_initial_workspace_size(int32_t S, int32_t T, int32_t H, int32_t W, int32_t N,
                                  const lf_params* prm) {
-    (void)prm;
     if (S < 1 || T < 1 || H < 1 || W < 1 || N < 1) return 0;
     if (!prm) return 0;
     Carve c(nullptr);
@@ -384,11 +503,9 @@ lf_status lf_initial_disparity(const lf_view_set* views, const float* hyp, int32
     LF_CHECK(check_views(views));
     LF_CHECK(check_shape(views->S, views->T, views->H, views->W, N));
     LF_CHECK(check_params(prm));
+    LF_CHECK(check_initial_size(views->H, views->W, N));
     if (!hyp || !d_init || !d_lo || !d_hi || !ws) return fail(LF_EINVAL, "NULL argument");
     const int S = views->S, T = views->T, H = views->H, W = views->W;
-    if ((int64_t)H * W * ((N + 3) / 4 * 4) * 2 >= ((int64_t)1 << 31))
-        return fail(LF_EUNSUPPORTED, "H*W*N = %lld cells per view (max 2^30)",
-                    (long long)H * W * N);
     Carve sizer(nullptr);
     const size_t need = plan_initial(sizer, S, T, H, W, N, prm, nullptr);
     if (ws_bytes < need) return fail(LF_ENOSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
@@ -397,55 +514,17 @@ lf_status lf_initial_disparity(const lf_view_set* views, const float* hyp, int32
     InitPlan pl;
     plan_initial(c, S, T, H, W, N, prm, &pl);
 
-    int st[8];
-    const int nv = cross_views(S, T, st);
-    const int sh = (S - 1) / 2, th = (T - 1) / 2;
-    const size_t HW = (size_t)H * W;
-    int16_t* maps = d_maps ? d_maps : pl.maps;
-
-    // 1. Census of the reference view and the cross views
-    lf::CensusBatch b{};
-    b.base = views->data;
-    b.n = 1 + nv;
-    const int64_t vs = (int64_t)H * views->pitch;
-    b.off[0] = ((int64_t)th * S + sh) * vs;
-    for (int i = 0; i < nv; ++i) b.off[1 + i] = ((int64_t)st[2 * i + 1] * S + st[2 * i]) * vs;
-    {
-        prof::Scope _ps(prof::kCensus, stream, 1);
-    LF_HIP(lf::launch_census(b, views->dtype, H, W, views->pitch, prm->census.win_h,
-                                 prm->census.win_w, pl.census, stream),
-               "census");
-    }
-
-    // 2. full-range Census cost + SGM + WTA per cross view
-    lf::SgmDense a{};
-    a.cref = pl.census;
-    a.cview = pl.census + HW;
-    a.dmap = maps;
-    a.nv = nv;
-    for (int i = 0; i < nv; ++i) {
-        a.cs[i] = sh - st[2 * i];
-        a.ct[i] = th - st[2 * i + 1];
-    }
-    {
-        prof::Scope _ps(prof::kSgmInit, stream, 3);
-    LF_HIP(lf::launch_sgm_dense(a, hyp, H, W, N, prm->sgm_init.P1, prm->sgm_init.P2,
-                                    prm->sgm_init.npaths,
-                                    prm->census.win_h * prm->census.win_w - 1, pl.paths, stream),
-               "initial SGM");
-    }
-
-    // 3. fusion, hole filling (ping-pong, ending in d_init), edges and borders
-    prof::Scope _ps(prof::kBorders, stream, 2 + prm->fill_passes);
-    int16_t* buf[2] = {d_init, pl.tmp};
-    int cur = prm->fill_passes % 2;
-    LF_HIP(lf::launch_fuse(maps, nv, (int)HW, prm->phi, buf[cur], stream), "fusion");
-    for (int f = 0; f < prm->fill_passes; ++f, cur ^= 1)
-        LF_HIP(lf::launch_fill(buf[cur], buf[cur ^ 1], H, W, stream), "fill");
-    LF_HIP(lf::launch_borders(d_init, view_ptr(views, sh, th), views->dtype, views->pitch, H, W,
-                              N, prm->lambda, eff_alpha(prm, views->dtype), prm->edge_tau, d_lo,
-                              d_hi, stream),
-           "borders");
+    lf::Job j = base_job(views, hyp, N, prm);
+    j.census = pl.census;
+    j.paths = pl.paths;
+    j.maps = d_maps ? d_maps : pl.maps;
+    j.fill_tmp = pl.tmp;
+    j.dinit = d_init;
+    j.lo = d_lo;
+    j.hi = d_hi;
+    lf::Runner r;
+    r.stream = stream;
+    LF_CHECK(run_initial(r, {&j}));
     return LF_OK;
 }
 
@@ -465,13 +544,11 @@ lf_status lf_cost_volume_bounded(const lf_view_set* views, const float* hyp, int
     LF_CHECK(check_views(views));
     LF_CHECK(check_shape(views->S, views->T, views->H, views->W, N));
     LF_CHECK(check_params(prm));
+    LF_CHECK(check_views_size(views));
     if (!hyp || !d_lo || !d_hi || !offsets || !cost || !ws)
         return fail(LF_EINVAL, "NULL argument");
     const int S = views->S, T = views->T, H = views->H, W = views->W;
     const int64_t HW = (int64_t)H * W;
-    if ((int64_t)S * T * H * views->pitch * (views->dtype == LF_U8 ? 1 : 4) >= ((int64_t)1 << 31))
-        return fail(LF_EUNSUPPORTED, "light field of %lld bytes (max 2 GiB)",
-                    (long long)S * T * H * views->pitch * (views->dtype == LF_U8 ? 1 : 4));
     if (cap_cells < HW * N)
         return fail(LF_ENOSPACE, "cap_cells %lld < H*W*N = %lld", (long long)cap_cells,
                     (long long)(HW * N));
@@ -483,31 +560,18 @@ lf_status lf_cost_volume_bounded(const lf_view_set* views, const float* hyp, int
     CostPlan pl;
     plan_cost(c, S, T, H, W, prm, &pl);
 
-    {
-        prof::Scope _ps(prof::kOffsets, stream, 3);
-    LF_HIP(lf::launch_offsets(d_lo, d_hi, HW, offsets, pl.scan, stream), "offsets");
-    }
-    const int32_t cap = lf_cost_cap(prm->sgm_final.P2, prm->sgm_final.npaths, prm->sum_bits);
-    prof::Scope _ps(prof::kCost, stream, prm->cost_kind == LF_COST_L2 ? 1 : 2);
-    if (prm->cost_kind == LF_COST_L2) {
-        LF_HIP(lf::launch_cost_l2(views->data, views->dtype, S, T, H, W, views->pitch, hyp, N,
-                                  d_lo, d_hi, offsets, eff_alpha(prm, views->dtype), cap, cost,
-                                  cost_f32, cap_cells, stream),
-               "l2 cost");
-    } else {
-        lf::CensusBatch b{};
-        b.base = views->data;
-        b.n = S * T;
-        b.stride = (int64_t)H * views->pitch;
-        if (b.n <= lf::kMaxBatchImages)
-            for (int z = 0; z < b.n; ++z) b.off[z] = z * b.stride;
-        LF_HIP(lf::launch_census(b, views->dtype, H, W, views->pitch, prm->census.win_h,
-                                 prm->census.win_w, pl.census_all, stream),
-               "census (all views)");
-        LF_HIP(lf::launch_cost_census_all(pl.census_all, S, T, H, W, hyp, N, d_lo, d_hi, offsets,
-                                          cap, cost, cost_f32, cap_cells, stream),
-               "census cost");
-    }
+    lf::Job j = base_job(views, hyp, N, prm);
+    j.lo = const_cast<int16_t*>(d_lo);
+    j.hi = const_cast<int16_t*>(d_hi);
+    j.offsets = offsets;
+    j.scan = pl.scan;
+    j.census_all = pl.census_all;
+    j.cost = cost;
+    j.cost_f32 = cost_f32;
+    j.cap_cells = cap_cells;
+    lf::Runner r;
+    r.stream = stream;
+    LF_CHECK(run_cost(r, {&j}));
     return LF_OK;
 }
 
@@ -532,12 +596,23 @@ lf_status lf_sgm_aggregate(const uint16_t* cost, const int64_t* offsets, const i
         return fail(LF_EINVAL, "P2=%d leaves no room for costs in %d-bit sums", sgm.P2, sum_bits);
     const size_t need = lf_sgm_workspace_size(H, W, N, sgm.npaths);
     if (ws_bytes < need) return fail(LF_ENOSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
-    lf::SgmBounded a{cost, offsets, d_lo, d_hi, csum, sum_bits};
-    {
-        prof::Scope _ps(prof::kSgmFinal, stream, 2);
-        LF_HIP(lf::launch_sgm_bounded(a, H, W, N, sgm.P1, sgm.P2, sgm.npaths, ws, stream),
-               "bounded SGM");
-    }
+    if ((uintptr_t)ws % kAlign) return fail(LF_EINVAL, "workspace not 256-byte aligned");
+    lf::Job j{};
+    j.H = H;
+    j.W = W;
+    j.N = N;
+    j.prm.sgm_final = sgm;
+    j.prm.sum_bits = sum_bits;
+    j.cost = const_cast<uint16_t*>(cost);
+    j.offsets = const_cast<int64_t*>(offsets);
+    j.lo = const_cast<int16_t*>(d_lo);
+    j.hi = const_cast<int16_t*>(d_hi);
+    j.sgm_ws = ws;
+    j.csum = csum;
+    lf::Runner r;
+    r.stream = stream;
+    prof::Scope _ps(lf::kStSgmFinal, r);
+    LF_HIP(lf::stage_sgm_final(r, {&j}), "bounded SGM");
     return LF_OK;
 }
 
@@ -560,21 +635,24 @@ lf_status lf_wta_subpixel(const void* csum, int32_t sum_bits, const int64_t* off
     if (median == 3 && (!ws || ws_bytes < lf_wta_workspace_size(H, W)))
         return fail(LF_ENOSPACE, "workspace %zu < %zu bytes", ws_bytes,
                     lf_wta_workspace_size(H, W));
-    prof::Scope _ps(prof::kWta, stream, median == 3 ? 2 : 1);
-    if (median == 3) {
-        if (!ws || ws_bytes < lf_wta_workspace_size(H, W))
-            return fail(LF_ENOSPACE, "workspace %zu < %zu bytes", ws_bytes,
-                        lf_wta_workspace_size(H, W));
-        float* pre = (float*)ws;
-        LF_HIP(lf::launch_wta_subpixel(csum, sum_bits, offsets, d_lo, d_hi, H, W, hyp, d_index,
-                                       pre, stream),
-               "wta/subpixel");
-        LF_HIP(lf::launch_median3(pre, disparity, H, W, stream), "median");
-    } else {
-        LF_HIP(lf::launch_wta_subpixel(csum, sum_bits, offsets, d_lo, d_hi, H, W, hyp, d_index,
-                                       disparity, stream),
-               "wta/subpixel");
-    }
+    lf::Job j{};
+    j.H = H;
+    j.W = W;
+    j.N = N;
+    j.hyp = hyp;
+    j.prm.sum_bits = sum_bits;
+    j.prm.median = median;
+    j.csum = const_cast<void*>(csum);
+    j.offsets = const_cast<int64_t*>(offsets);
+    j.lo = const_cast<int16_t*>(d_lo);
+    j.hi = const_cast<int16_t*>(d_hi);
+    j.d_index = d_index;
+    j.pre_median = (float*)ws;
+    j.disparity = disparity;
+    lf::Runner r;
+    r.stream = stream;
+    prof::Scope _ps(lf::kStWta, r);
+    LF_HIP(lf::stage_wta(r, {&j}), "wta/subpixel");
     return LF_OK;
 }
 
@@ -587,27 +665,45 @@ size_t lf_depth_workspace_size(int32_t S, int32_t T, int32_t H, int32_t W, int32
 lf_status lf_depth(const lf_view_set* views, const float* hyp, int32_t N, const lf_params* prm,
                    float* disparity, int16_t* d_index, void* ws, size_t ws_bytes,
                    hipStream_t stream) {
-    LF_CHECK(check_views(views));
-    LF_CHECK(check_shape(views->S, views->T, views->H, views->W, N));
-    LF_CHECK(check_params(prm));
-    if (!hyp || !disparity || !ws) return fail(LF_EINVAL, "NULL argument");
-    const int S = views->S, T = views->T, H = views->H, W = views->W;
-    const size_t need = plan_depth(nullptr, S, T, H, W, N, prm, nullptr);
-    if (ws_bytes < need) return fail(LF_ENOSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
-    if ((uintptr_t)ws % kAlign) return fail(LF_EINVAL, "workspace not 256-byte aligned");
-    DepthPlan pl;
-    plan_depth(ws, S, T, H, W, N, prm, &pl);
-    const int64_t cells = (int64_t)H * W * N;
-    LF_CHECK(lf_initial_disparity(views, hyp, N, prm, nullptr, pl.dinit, pl.lo, pl.hi,
-                                  pl.init_ws, pl.init_bytes, stream));
-    LF_CHECK(lf_cost_volume_bounded(views, hyp, N, prm, pl.lo, pl.hi, pl.offsets, pl.cost, cells,
-                                    nullptr, pl.cost_ws, pl.cost_bytes, stream));
-    LF_CHECK(lf_sgm_aggregate(pl.cost, pl.offsets, pl.lo, pl.hi, H, W, N, prm->sgm_final,
-                              prm->sum_bits, pl.csum, pl.sgm_ws, pl.sgm_bytes, stream));
-    LF_CHECK(lf_wta_subpixel(pl.csum, prm->sum_bits, pl.offsets, pl.lo, pl.hi, H, W, hyp, N,
-                             prm->median, d_index ? d_index : pl.d_index, disparity,
-                             pl.pre_median, lf_wta_workspace_size(H, W), stream));
-    return LF_OK;
+    LF_CHECK(check_depth_args(views, hyp, N, prm, disparity, ws, ws_bytes));
+    lf::Job j = depth_job(views, hyp, N, prm, disparity, d_index, ws);
+    lf::Runner r;
+    r.stream = stream;
+    return run_depth(r, {&j});
 }
 
 }  // extern "C"
+
+// --- used by the batch plan and the request loop ----------------------------------
+namespace lf {
+
+lf_status validate_request(const lf_request* q, size_t ws_bytes, const void* ws) {
+    if (!q) return fail(LF_EINVAL, "request is NULL");
+    if (!ws) {
+        LF_CHECK(check_views(&q->views));
+        LF_CHECK(check_shape(q->views.S, q->views.T, q->views.H, q->views.W, q->N));
+        LF_CHECK(check_params(&q->params));
+        LF_CHECK(check_initial_size(q->views.H, q->views.W, q->N));
+        LF_CHECK(check_views_size(&q->views));
+        if (!q->hyp || !q->disparity) return fail(LF_EINVAL, "NULL argument");
+        return LF_OK;
+    }
+    return check_depth_args(&q->views, q->hyp, q->N, &q->params, q->disparity, ws, ws_bytes);
+}
+
+size_t request_workspace_bytes(const lf_request* q) {
+    return lf_depth_workspace_size(q->views.S, q->views.T, q->views.H, q->views.W, q->N,
+                                   &q->params);
+}
+
+Job request_job(const lf_request* q, void* ws) {
+    return depth_job(&q->views, q->hyp, q->N, &q->params, q->disparity, q->d_index, ws);
+}
+
+lf_status run_depth_jobs(Runner& r, const Jobs& jobs) { return run_depth(r, jobs); }
+
+lf_status record_error(lf_status s, const char* fmt, const char* what) {
+    return fail(s, fmt, what);
+}
+
+}  // namespace lf

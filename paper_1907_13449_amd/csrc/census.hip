@@ -11,35 +11,48 @@ namespace {
 
 constexpr int kBX = 32, kBY = 8;
 
-template <typename T>
-__global__ __launch_bounds__(256) void census_kernel(CensusBatch b, int H, int W, int pitch,
-                                                     int win_h, int win_w,
-                                                     uint64_t* __restrict__ out) {
-    __shared__ float tile[(kBY + 2 * kMaxCensusRadius) * (kBX + 2 * kMaxCensusRadius)];
-    const int z = blockIdx.z;
-    const int64_t off = b.n > kMaxBatchImages ? (int64_t)z * b.stride : b.off[z];
-    const T* __restrict__ img = reinterpret_cast<const T*>(b.base) + off;
-    uint64_t* __restrict__ dst = out + (size_t)z * H * W;
+// Up to kMaxBatchImages images of one size; image z starts at base + off[z]
+// elements, or at base + z * stride when n > kMaxBatchImages.
+struct CensusArgs {
+    const void* base;
+    int64_t off[kMaxBatchImages];
+    int64_t stride;
+    int n;
+    int H, W, pitch, win_h, win_w;
+    int bx, by;               // tiles along x and y
+    uint64_t* out;            // [n][H*W]
+};
 
-    const int rh = win_h / 2, rw = win_w / 2;
+template <typename T>
+__device__ __forceinline__ void census_block(const CensusArgs& a, uint32_t b, float* tile) {
+    const int per = a.bx * a.by;
+    const int z = (int)b / per;
+    const int rem = (int)b - z * per;
+    const int by = rem / a.bx, bx = rem - by * a.bx;
+    const int H = a.H, W = a.W;
+    const int64_t off = a.n > kMaxBatchImages ? (int64_t)z * a.stride : a.off[z];
+    const T* __restrict__ img = reinterpret_cast<const T*>(a.base) + off;
+    uint64_t* __restrict__ dst = a.out + (size_t)z * H * W;
+
+    const int rh = a.win_h / 2, rw = a.win_w / 2;
     const int tw = kBX + 2 * rw, th = kBY + 2 * rh;
-    const int x0 = blockIdx.x * kBX - rw, y0 = blockIdx.y * kBY - rh;
+    const int x0 = bx * kBX - rw, y0 = by * kBY - rh;
     for (int i = threadIdx.x; i < tw * th; i += 256) {
         const int ty = i / tw, tx = i - ty * tw;
         const int y = clampi(y0 + ty, 0, H - 1), x = clampi(x0 + tx, 0, W - 1);
-        tile[ty * tw + tx] = ld(img + (size_t)y * pitch + x);
+        tile[ty * tw + tx] = ld(img + (size_t)y * a.pitch + x);
     }
     __syncthreads();
 
     const int lx = threadIdx.x % kBX, ly = threadIdx.x / kBX;
-    const int u = blockIdx.x * kBX + lx, v = blockIdx.y * kBY + ly;
+    const int u = bx * kBX + lx, v = by * kBY + ly;
     if (u >= W || v >= H) return;
     const float c = tile[(ly + rh) * tw + lx + rw];
     uint64_t bits = 0;
     int n = 0;
-    for (int i = 0; i < win_h; ++i) {
+    for (int i = 0; i < a.win_h; ++i) {
         const float* row = tile + (ly + i) * tw + lx;
-        for (int j = 0; j < win_w; ++j) {
+        for (int j = 0; j < a.win_w; ++j) {
             if (i == rh && j == rw) continue;
             bits |= (uint64_t)(c > row[j]) << n;
             ++n;
@@ -48,18 +61,82 @@ __global__ __launch_bounds__(256) void census_kernel(CensusBatch b, int H, int W
     dst[(size_t)v * W + u] = bits;
 }
 
+template <class Src, typename T>
+__global__ __launch_bounds__(256) void census_kernel(Src src) {
+    __shared__ float tile[(kBY + 2 * kMaxCensusRadius) * (kBX + 2 * kMaxCensusRadius)];
+    for (uint32_t vb = blockIdx.x; vb < src.total; vb += gridDim.x) {
+        uint32_t b;
+        const CensusArgs& a = member(src, vb, b);
+        __syncthreads();                          // the tile of the previous block is read
+        census_block<T>(a, b, tile);
+    }
+}
+
+uint32_t census_blocks(const CensusArgs& a) {
+    return (uint32_t)a.bx * a.by * a.n;
+}
+
+CensusArgs census_args(const void* base, int H, int W, int pitch, int win_h, int win_w,
+                       uint64_t* out) {
+    CensusArgs a{};
+    a.base = base;
+    a.H = H;
+    a.W = W;
+    a.pitch = pitch;
+    a.win_h = win_h;
+    a.win_w = win_w;
+    a.bx = (W + kBX - 1) / kBX;
+    a.by = (H + kBY - 1) / kBY;
+    a.out = out;
+    return a;
+}
+
+hipError_t launch_census(Runner& r, int stage, int dtype, const std::vector<CensusArgs>& args) {
+    std::vector<uint32_t> blocks;
+    for (const CensusArgs& a : args) blocks.push_back(census_blocks(a));
+    if (dtype == LF_U8)
+        return launch(r, stage, census_kernel<Single<CensusArgs>, uint8_t>,
+                      census_kernel<Group<CensusArgs>, uint8_t>, args, blocks, 256);
+    return launch(r, stage, census_kernel<Single<CensusArgs>, float>,
+                  census_kernel<Group<CensusArgs>, float>, args, blocks, 256);
+}
+
 }  // namespace
 
-hipError_t launch_census(const CensusBatch& b, int dtype, int H, int W, int pitch, int win_h,
-                         int win_w, uint64_t* out, hipStream_t st) {
-    dim3 grid((W + kBX - 1) / kBX, (H + kBY - 1) / kBY, b.n);
-    if (dtype == LF_U8)
-        hipLaunchKernelGGL(census_kernel<uint8_t>, grid, dim3(256), 0, st, b, H, W, pitch,
-                           win_h, win_w, out);
-    else
-        hipLaunchKernelGGL(census_kernel<float>, grid, dim3(256), 0, st, b, H, W, pitch, win_h,
-                           win_w, out);
-    return hipGetLastError();
+hipError_t census_image(Runner& r, const void* img, int dtype, int H, int W, int pitch,
+                        int win_h, int win_w, uint64_t* out) {
+    CensusArgs a = census_args(img, H, W, pitch, win_h, win_w, out);
+    a.n = 1;
+    a.off[0] = 0;
+    return launch_census(r, kStCensus, dtype, {a});
+}
+
+hipError_t stage_census(Runner& r, const Jobs& jobs, bool all_views) {
+    std::vector<CensusArgs> by_type[2];
+    for (const Job* j : jobs) {
+        const int64_t vs = (int64_t)j->H * j->pitch;
+        CensusArgs a = census_args(j->views, j->H, j->W, j->pitch, j->prm.census.win_h,
+                                   j->prm.census.win_w, all_views ? j->census_all : j->census);
+        if (all_views) {
+            a.n = j->S * j->T;
+            a.stride = vs;
+            for (int z = 0; z < a.n && z < kMaxBatchImages; ++z) a.off[z] = z * vs;
+        } else {
+            const int sh = (j->S - 1) / 2, th = (j->T - 1) / 2;
+            a.n = 1 + j->nv;
+            a.off[0] = ((int64_t)th * j->S + sh) * vs;
+            for (int i = 0; i < j->nv; ++i)
+                a.off[1 + i] = ((int64_t)j->st[2 * i + 1] * j->S + j->st[2 * i]) * vs;
+        }
+        by_type[j->dtype == LF_U8 ? 0 : 1].push_back(a);
+    }
+    const int stage = all_views ? kStCost : kStCensus;
+    for (int t = 0; t < 2; ++t) {
+        if (by_type[t].empty()) continue;
+        hipError_t e = launch_census(r, stage, t == 0 ? LF_U8 : LF_F32, by_type[t]);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace lf

@@ -3,12 +3,10 @@
 //
 // Work is flattened over the cells of the CSR volume so that pixels whose range
 // is the full hypothesis set and pixels with a 2*lambda+1 window share the
-// machine evenly: a 256-thread workgroup owns 64 consecutive pixels, stages their
-// offsets and ranges in LDS, and its threads stride over the cells of those
-// pixels; a cell finds its pixel by binary search in LDS.  Consecutive threads
-// therefore handle consecutive hypotheses of one pixel and then the next pixel
-// of the row, so the four bilinear taps of a view are read from a narrow band of
-// two rows (L1/L2 resident) and the cost writes are fully coalesced.
+// machine evenly; a cell finds its pixel by binary search over offsets staged in
+// LDS.  Consecutive threads handle consecutive hypotheses of one pixel and then
+// the next pixel of the row, so the bilinear taps of a view are read from a
+// narrow band of two rows (L1/L2 resident) and the cost writes are coalesced.
 //
 // The view loop runs t outer, s inner, float32, with the shift of each view and
 // hypothesis rounded once: this is the precision the quantised integer cost is
@@ -18,28 +16,8 @@
 namespace lf {
 namespace {
 
-constexpr int kPix = 64;        // pixels per workgroup
+constexpr int kPix = 64;        // pixels per workgroup (Census kind)
 constexpr int kThreads = 256;
-
-struct CellMap {
-    int64_t first;              // first cell of the workgroup
-    int64_t end;                // one past its last cell
-    int p0;                     // first pixel
-};
-
-// Stages offsets/lo of the workgroup's pixels; returns its cell span.
-__device__ __forceinline__ CellMap stage_cells(const int64_t* __restrict__ off,
-                                               const int16_t* __restrict__ lo, int HW,
-                                               int64_t* s_off, int* s_lo) {
-    const int p0 = blockIdx.x * kPix;
-    const int np = min(kPix, HW - p0);
-    for (int i = threadIdx.x; i <= np; i += kThreads) {
-        s_off[i] = off[p0 + i];
-        if (i < np) s_lo[i] = lo[p0 + i];
-    }
-    __syncthreads();
-    return CellMap{s_off[0], s_off[np], p0};
-}
 
 // Largest i with s_off[i] <= c (the pixel that owns cell c).
 __device__ __forceinline__ int find_pixel(const int64_t* s_off, int np, int64_t c) {
@@ -52,23 +30,23 @@ __device__ __forceinline__ int find_pixel(const int64_t* s_off, int np, int64_t 
 }
 
 // ---------------------------------------------------------------------------
-// l2 cost, Eq. (12).  Work is dealt in equal slices of cells: workgroup b takes
-// the cells [b*kChunk, (b+1)*kChunk) of the CSR volume, whatever pixels they
-// belong to, so pixels with the full hypothesis range and pixels with a
-// 2*lambda+1 window cost the same per cell and no workgroup is a straggler.
-// The first pixel of the slice is found by binary search over the offsets; the
-// offsets and lower bounds of the slice's pixels are staged in LDS, and each
-// cell finds its pixel there.  Consecutive threads take consecutive cells
-// (consecutive hypotheses of a pixel, then the next pixel).
+// l2 cost, Eq. (12).  Work is dealt in equal slices of cells: slice i is the
+// cells [i*chunk, (i+1)*chunk) of the CSR volume, whatever pixels they belong
+// to, so pixels with the full hypothesis range and pixels with a 2*lambda+1
+// window cost the same per cell and no workgroup is a straggler.  The number of
+// slices is only known on the device (the last offset), so a light field gets
+// nblk workgroups sized for its worst case, and workgroup b walks the slices
+// b, b + nblk, ... that exist.  The first pixel of a slice is found by binary
+// search over the offsets; the offsets and lower bounds of the slice's pixels
+// are staged in LDS, and each cell finds its pixel there.  Consecutive threads
+// take consecutive cells (consecutive hypotheses of a pixel, then the next
+// pixel).
 //
 // Per view the two taps of a bilinear row, (x0, x0+1), are fetched by one 8-byte
 // load (the view pointer is only 4-byte aligned, which global loads allow):
 // that halves the gather instructions, whose issue rate -- not bytes -- bounds
 // this kernel.  At the image edges a tap is clamped; the pair then starts at
 // min(x_a, W-2) and each tap picks its element of the pair.
-constexpr int kChunk = 1024;           // cells per workgroup
-constexpr int kCPT = kChunk / kThreads;
-
 template <typename T>
 struct Pair {
     float lo, hi;
@@ -87,166 +65,274 @@ __device__ __forceinline__ Pair<T> ld_pair(const T* p) {
     }
 }
 
-template <typename T>
-__global__ __launch_bounds__(kThreads) void cost_l2_kernel(
-    const T* __restrict__ views, int S, int T_, int H, int W, int pitch,
-    const float* __restrict__ hyp, int N, const int16_t* __restrict__ lo,
-    const int64_t* __restrict__ off, float alpha, float cap, uint16_t* __restrict__ cost,
-    float* __restrict__ cost_f32, int64_t cap_cells) {
-    __shared__ int64_t s_off[kChunk + 1];
-    __shared__ int s_lo[kChunk];
-    __shared__ int s_p0, s_np;
+struct L2Args {
+    const void* views;        // [T][S][H][pitch]
+    const float* hyp;
+    const int16_t* lo;
+    const int64_t* off;       // [H*W + 1]
+    uint16_t* cost;
+    float* cost_f32;          // nullable
+    int64_t cap_cells;
+    int S, T, H, W, pitch, N;
+    float alpha, cap;
+    uint32_t nblk;            // workgroups of this light field
+};
+
+template <typename T, int CPT, bool Walk>
+__device__ __forceinline__ void l2_slices(const L2Args& a, uint32_t b, int64_t* s_off, int* s_lo,
+                                          int* s_p) {
+    constexpr int kChunk = kThreads * CPT;
+    const int S = a.S, T_ = a.T, H = a.H, W = a.W, pitch = a.pitch, N = a.N;
+    const int16_t* __restrict__ lo = a.lo;
+    const int64_t* __restrict__ off = a.off;
     const int HW = H * W;
-    const int64_t total = min(off[HW], cap_cells);
-    const int64_t c0 = (int64_t)blockIdx.x * kChunk;
-    if (c0 >= total) return;                     // uniform: the whole workgroup
-    const int64_t c1 = min(c0 + kChunk, total);
-    if (threadIdx.x == 0) {
-        int a = 0, b = HW;                       // off[a] <= c0 < off[b]
-        while (b - a > 1) {
-            const int mid = (a + b) >> 1;
-            if (off[mid] <= c0) a = mid; else b = mid;
-        }
-        s_p0 = a;
-        s_np = min(kChunk, HW - a);
-    }
-    __syncthreads();
-    const int p0 = s_p0, npx = s_np;
-    for (int i = threadIdx.x; i <= npx; i += kThreads) {
-        s_off[i] = off[p0 + i];
-        if (i < npx) s_lo[i] = lo[p0 + i];
-    }
-    __syncthreads();
-    int np = npx;                                 // pixels that own cells of the slice
-    {
-        int a = 0, b = npx;                       // largest i with s_off[i] <= c1 - 1
-        while (b - a > 1) {
-            const int mid = (a + b) >> 1;
-            if (s_off[mid] <= c1 - 1) a = mid; else b = mid;
-        }
-        np = a + 1;
-    }
+    const int64_t total = min(off[HW], a.cap_cells);
     const int sh = (S - 1) / 2, th = (T_ - 1) / 2;
     const size_t vstride = (size_t)H * pitch;
+    const T* __restrict__ views = (const T*)a.views;
     const T* __restrict__ refv = views + ((size_t)th * S + sh) * vstride;
     const bool pairs = W >= 2;
 
-    for (int r = 0; r < kCPT; ++r) {
-        const int64_t c = c0 + threadIdx.x + (int64_t)r * kThreads;
-        if (c >= c1) break;
-        const int i = find_pixel(s_off, np, c);
-        const int p = p0 + i;
-        const int v = p / W, u = p - v * W;
-        const int k = s_lo[i] + (int)(c - s_off[i]);
-        if ((unsigned)k >= (unsigned)N) continue;      // only for ranges outside [0, N)
-        const float d = hyp[k];
-        const float ref = ld(refv + (size_t)v * pitch + u);
-        float acc = 0.0f;
-        for (int t = 0; t < T_; ++t) {
-            const float shy = (float)(th - t) * d;
-            const float y0 = floorf(shy);
-            const float fy = shy - y0;
-            const int ya = clampi(v + (int)y0, 0, H - 1), yb = clampi(v + (int)y0 + 1, 0, H - 1);
-            const T* __restrict__ vt = views + (size_t)t * S * vstride;
-            for (int s = 0; s < S; ++s) {
-                if (s == sh && t == th) continue;        // adds exactly +0
-                const float shx = (float)(sh - s) * d;
-                const float x0 = floorf(shx);
-                const float fx = shx - x0;
-                const int xa = clampi(u + (int)x0, 0, W - 1), xb = clampi(u + (int)x0 + 1, 0, W - 1);
-                const T* __restrict__ vs = vt + (size_t)s * vstride;
-                float a, b, cc, e;
-                if (pairs) {
-                    const int q = min(xa, W - 2);          // xa, xb in {q, q+1}
-                    const Pair<T> top = ld_pair(vs + (size_t)ya * pitch + q);
-                    const Pair<T> bot = ld_pair(vs + (size_t)yb * pitch + q);
-                    a = xa == q ? top.lo : top.hi;
-                    b = xb == q ? top.lo : top.hi;
-                    cc = xa == q ? bot.lo : bot.hi;
-                    e = xb == q ? bot.lo : bot.hi;
-                } else {
-                    a = ld(vs + (size_t)ya * pitch + xa);
-                    b = ld(vs + (size_t)ya * pitch + xb);
-                    cc = ld(vs + (size_t)yb * pitch + xa);
-                    e = ld(vs + (size_t)yb * pitch + xb);
-                }
-                const float top = fmaf(fx, b - a, a);
-                const float bot = fmaf(fx, e - cc, cc);
-                const float val = fmaf(fy, bot - top, top);
-                acc = acc + fabsf(ref - val);
+    for (int64_t slice = b; slice * kChunk < total; slice += a.nblk) {   // uniform
+        const int64_t c0 = slice * kChunk;
+        const int64_t c1 = min(c0 + kChunk, total);
+        if constexpr (Walk) __syncthreads();      // LDS of the previous slice is read
+        if (threadIdx.x == 0) {
+            int x = 0, y = HW;                    // off[x] <= c0 < off[y]
+            while (y - x > 1) {
+                const int mid = (x + y) >> 1;
+                if (off[mid] <= c0) x = mid; else y = mid;
             }
+            s_p[0] = x;
+            s_p[1] = min(kChunk, HW - x);
         }
-        const float q = rintf(alpha * acc);
-        cost[c] = (uint16_t)(q > cap ? cap : q);
-        if (cost_f32) cost_f32[c] = acc;
+        __syncthreads();
+        const int p0 = s_p[0], npx = s_p[1];
+        for (int i = threadIdx.x; i <= npx; i += kThreads) {
+            s_off[i] = off[p0 + i];
+            if (i < npx) s_lo[i] = lo[p0 + i];
+        }
+        __syncthreads();
+        int np;                                   // pixels that own cells of the slice
+        {
+            int x = 0, y = npx;                   // largest i with s_off[i] <= c1 - 1
+            while (y - x > 1) {
+                const int mid = (x + y) >> 1;
+                if (s_off[mid] <= c1 - 1) x = mid; else y = mid;
+            }
+            np = x + 1;
+        }
+
+        for (int r = 0; r < CPT; ++r) {
+            const int64_t c = c0 + threadIdx.x + (int64_t)r * kThreads;
+            if (c >= c1) break;
+            const int i = find_pixel(s_off, np, c);
+            const int p = p0 + i;
+            const int v = p / W, u = p - v * W;
+            const int k = s_lo[i] + (int)(c - s_off[i]);
+            if ((unsigned)k >= (unsigned)N) continue;      // only for ranges outside [0, N)
+            const float d = a.hyp[k];
+            const float ref = ld(refv + (size_t)v * pitch + u);
+            float acc = 0.0f;
+            for (int t = 0; t < T_; ++t) {
+                const float shy = (float)(th - t) * d;
+                const float y0 = floorf(shy);
+                const float fy = shy - y0;
+                const int ya = clampi(v + (int)y0, 0, H - 1), yb = clampi(v + (int)y0 + 1, 0, H - 1);
+                const T* __restrict__ vt = views + (size_t)t * S * vstride;
+                for (int s = 0; s < S; ++s) {
+                    if (s == sh && t == th) continue;        // adds exactly +0
+                    const float shx = (float)(sh - s) * d;
+                    const float x0 = floorf(shx);
+                    const float fx = shx - x0;
+                    const int xa = clampi(u + (int)x0, 0, W - 1), xb = clampi(u + (int)x0 + 1, 0, W - 1);
+                    const T* __restrict__ vs = vt + (size_t)s * vstride;
+                    float ta, tb, bc, be;
+                    if (pairs) {
+                        const int q = min(xa, W - 2);          // xa, xb in {q, q+1}
+                        const Pair<T> top = ld_pair(vs + (size_t)ya * pitch + q);
+                        const Pair<T> bot = ld_pair(vs + (size_t)yb * pitch + q);
+                        ta = xa == q ? top.lo : top.hi;
+                        tb = xb == q ? top.lo : top.hi;
+                        bc = xa == q ? bot.lo : bot.hi;
+                        be = xb == q ? bot.lo : bot.hi;
+                    } else {
+                        ta = ld(vs + (size_t)ya * pitch + xa);
+                        tb = ld(vs + (size_t)ya * pitch + xb);
+                        bc = ld(vs + (size_t)yb * pitch + xa);
+                        be = ld(vs + (size_t)yb * pitch + xb);
+                    }
+                    const float top = fmaf(fx, tb - ta, ta);
+                    const float bot = fmaf(fx, be - bc, bc);
+                    const float val = fmaf(fy, bot - top, top);
+                    acc = acc + fabsf(ref - val);
+                }
+            }
+            const float q = rintf(a.alpha * acc);
+            a.cost[c] = (uint16_t)(q > a.cap ? a.cap : q);
+            if (a.cost_f32) a.cost_f32[c] = acc;
+        }
+        if constexpr (!Walk) break;               // one slice per workgroup
     }
 }
 
-__global__ __launch_bounds__(kThreads) void cost_census_all_kernel(
-    const uint64_t* __restrict__ census, int S, int T_, int H, int W,
-    const float* __restrict__ hyp, int N, const int16_t* __restrict__ lo,
-    const int64_t* __restrict__ off, uint32_t cap, uint16_t* __restrict__ cost,
-    float* __restrict__ cost_f32, int64_t cap_cells) {
+// One workgroup per virtual block (the grid is never capped); with Walk a
+// workgroup takes every nblk-th slice of its light field, else exactly one.
+template <class Src, typename T, int CPT, bool Walk>
+__global__ __launch_bounds__(kThreads) void cost_l2_kernel(Src src) {
+    __shared__ int64_t s_off[kThreads * CPT + 1];
+    __shared__ int s_lo[kThreads * CPT];
+    __shared__ int s_p[2];
+    uint32_t b;
+    const L2Args& a = member(src, blockIdx.x, b);
+    l2_slices<T, CPT, Walk>(a, b, s_off, s_lo, s_p);
+}
+
+// ---------------------------------------------------------------------------
+// Census kind, Eq. (15): 64 pixels per workgroup, their cells strided over the
+// threads.
+struct CensusAllArgs {
+    const uint64_t* census;   // [S*T][H*W]
+    const float* hyp;
+    const int16_t* lo;
+    const int64_t* off;
+    uint16_t* cost;
+    float* cost_f32;
+    int64_t cap_cells;
+    int S, T, H, W, N;
+    uint32_t cap;
+};
+
+template <class Src>
+__global__ __launch_bounds__(kThreads) void cost_census_all_kernel(Src src) {
     __shared__ int64_t s_off[kPix + 1];
     __shared__ int s_lo[kPix];
-    const int HW = H * W;
-    const CellMap cm = stage_cells(off, lo, HW, s_off, s_lo);
-    const int np = min(kPix, HW - cm.p0);
-    const int sh = (S - 1) / 2, th = (T_ - 1) / 2;
-    const uint64_t* __restrict__ cref = census + ((size_t)th * S + sh) * HW;
-    for (int64_t c = cm.first + threadIdx.x; c < cm.end; c += kThreads) {
-        if (c >= cap_cells) break;
-        const int i = find_pixel(s_off, np, c);
-        const int p = cm.p0 + i;
-        const int v = p / W, u = p - v * W;
-        const int k = s_lo[i] + (int)(c - s_off[i]);
-        if ((unsigned)k >= (unsigned)N) continue;
-        const float d = hyp[k];
-        const uint64_t r = cref[p];
-        uint32_t acc = 0;
-        for (int t = 0; t < T_; ++t) {
-            const int y = clampi(v + (int)rintf((float)(th - t) * d), 0, H - 1);
-            for (int s = 0; s < S; ++s) {
-                const int x = clampi(u + (int)rintf((float)(sh - s) * d), 0, W - 1);
-                acc += (uint32_t)__popcll(r ^ census[((size_t)t * S + s) * HW + (size_t)y * W + x]);
-            }
+    for (uint32_t vb = blockIdx.x; vb < src.total; vb += gridDim.x) {
+        uint32_t b;
+        const CensusAllArgs& a = member(src, vb, b);
+        const int S = a.S, T_ = a.T, H = a.H, W = a.W, N = a.N;
+        const int HW = H * W;
+        const int p0 = (int)b * kPix;
+        const int np = min(kPix, HW - p0);
+        __syncthreads();
+        for (int i = threadIdx.x; i <= np; i += kThreads) {
+            s_off[i] = a.off[p0 + i];
+            if (i < np) s_lo[i] = a.lo[p0 + i];
         }
-        cost[c] = (uint16_t)min(acc, cap);
-        if (cost_f32) cost_f32[c] = (float)acc;
+        __syncthreads();
+        const int sh = (S - 1) / 2, th = (T_ - 1) / 2;
+        const uint64_t* __restrict__ census = a.census;
+        const uint64_t* __restrict__ cref = census + ((size_t)th * S + sh) * HW;
+        for (int64_t c = s_off[0] + threadIdx.x; c < s_off[np]; c += kThreads) {
+            if (c >= a.cap_cells) break;
+            const int i = find_pixel(s_off, np, c);
+            const int p = p0 + i;
+            const int v = p / W, u = p - v * W;
+            const int k = s_lo[i] + (int)(c - s_off[i]);
+            if ((unsigned)k >= (unsigned)N) continue;
+            const float d = a.hyp[k];
+            const uint64_t r = cref[p];
+            uint32_t acc = 0;
+            for (int t = 0; t < T_; ++t) {
+                const int y = clampi(v + (int)rintf((float)(th - t) * d), 0, H - 1);
+                for (int s = 0; s < S; ++s) {
+                    const int x = clampi(u + (int)rintf((float)(sh - s) * d), 0, W - 1);
+                    acc += (uint32_t)__popcll(r ^ census[((size_t)t * S + s) * HW + (size_t)y * W + x]);
+                }
+            }
+            a.cost[c] = (uint16_t)min(acc, a.cap);
+            if (a.cost_f32) a.cost_f32[c] = (float)acc;
+        }
     }
+}
+
+template <typename T, bool Walk>
+hipError_t l2_variant(Runner& r, const std::vector<L2Args>& args,
+                      const std::vector<uint32_t>& blocks) {
+    switch (r.tune.cost_cpt) {
+        case 2:
+            return launch(r, kStCost, cost_l2_kernel<Single<L2Args>, T, 2, Walk>,
+                          cost_l2_kernel<Group<L2Args>, T, 2, Walk>, args, blocks, kThreads);
+        case 8:
+            return launch(r, kStCost, cost_l2_kernel<Single<L2Args>, T, 8, Walk>,
+                          cost_l2_kernel<Group<L2Args>, T, 8, Walk>, args, blocks, kThreads);
+        default:
+            return launch(r, kStCost, cost_l2_kernel<Single<L2Args>, T, 4, Walk>,
+                          cost_l2_kernel<Group<L2Args>, T, 4, Walk>, args, blocks, kThreads);
+    }
+}
+
+template <typename T>
+hipError_t l2_walk(Runner& r, const std::vector<L2Args>& args,
+                   const std::vector<uint32_t>& blocks) {
+    return r.tune.cost_stride > 1 ? l2_variant<T, true>(r, args, blocks)
+                                  : l2_variant<T, false>(r, args, blocks);
 }
 
 }  // namespace
 
-hipError_t launch_cost_l2(const void* views, int dtype, int S, int T, int H, int W, int pitch,
-                          const float* hyp, int N, const int16_t* lo, const int16_t* hi,
-                          const int64_t* off, float alpha, int32_t cap, uint16_t* cost,
-                          float* cost_f32, int64_t cap_cells, hipStream_t st) {
-    (void)hi;
-    // worst-case number of slices; those past the device-side cell count exit
-    const int64_t slices = ((int64_t)H * W * N + kChunk - 1) / kChunk;
-    dim3 grid((unsigned)slices);
-    if (dtype == LF_U8)
-        hipLaunchKernelGGL(cost_l2_kernel<uint8_t>, grid, dim3(kThreads), 0, st,
-                           (const uint8_t*)views, S, T, H, W, pitch, hyp, N, lo, off, alpha,
-                           (float)cap, cost, cost_f32, cap_cells);
-    else
-        hipLaunchKernelGGL(cost_l2_kernel<float>, grid, dim3(kThreads), 0, st,
-                           (const float*)views, S, T, H, W, pitch, hyp, N, lo, off, alpha,
-                           (float)cap, cost, cost_f32, cap_cells);
-    return hipGetLastError();
-}
-
-hipError_t launch_cost_census_all(const uint64_t* census_all, int S, int T, int H, int W,
-                                  const float* hyp, int N, const int16_t* lo, const int16_t* hi,
-                                  const int64_t* off, int32_t cap, uint16_t* cost,
-                                  float* cost_f32, int64_t cap_cells, hipStream_t st) {
-    (void)hi;
-    const int HW = H * W;
-    dim3 grid((HW + kPix - 1) / kPix);
-    hipLaunchKernelGGL(cost_census_all_kernel, grid, dim3(kThreads), 0, st, census_all, S, T, H,
-                       W, hyp, N, lo, off, (uint32_t)cap, cost, cost_f32, cap_cells);
-    return hipGetLastError();
+hipError_t stage_cost(Runner& r, const Jobs& jobs) {
+    std::vector<L2Args> l2[2];
+    std::vector<uint32_t> l2_blocks[2];
+    std::vector<CensusAllArgs> ca;
+    std::vector<uint32_t> ca_blocks;
+    Jobs census_jobs;
+    const int cpt = r.tune.cost_cpt == 2 || r.tune.cost_cpt == 8 ? r.tune.cost_cpt : 4;
+    const int stride = std::max(1, r.tune.cost_stride);
+    for (const Job* j : jobs) {
+        const int64_t HW = (int64_t)j->H * j->W;
+        if (j->prm.cost_kind == LF_COST_L2) {
+            L2Args a{};
+            a.views = j->views;
+            a.hyp = j->hyp;
+            a.lo = j->lo;
+            a.off = j->offsets;
+            a.cost = j->cost;
+            a.cost_f32 = j->cost_f32;
+            a.cap_cells = j->cap_cells;
+            a.S = j->S;
+            a.T = j->T;
+            a.H = j->H;
+            a.W = j->W;
+            a.pitch = j->pitch;
+            a.N = j->N;
+            a.alpha = j->alpha;
+            a.cap = (float)j->cap;
+            // worst-case slices; those past the device-side cell count are skipped
+            const int64_t slices = (HW * j->N + kThreads * cpt - 1) / (kThreads * cpt);
+            a.nblk = (uint32_t)std::max<int64_t>(1, (slices + stride - 1) / stride);
+            const int t = j->dtype == LF_U8 ? 0 : 1;
+            l2[t].push_back(a);
+            l2_blocks[t].push_back(a.nblk);
+        } else {
+            census_jobs.push_back(j);
+            CensusAllArgs a{};
+            a.census = j->census_all;
+            a.hyp = j->hyp;
+            a.lo = j->lo;
+            a.off = j->offsets;
+            a.cost = j->cost;
+            a.cost_f32 = j->cost_f32;
+            a.cap_cells = j->cap_cells;
+            a.S = j->S;
+            a.T = j->T;
+            a.H = j->H;
+            a.W = j->W;
+            a.N = j->N;
+            a.cap = (uint32_t)j->cap;
+            ca.push_back(a);
+            ca_blocks.push_back((uint32_t)((HW + kPix - 1) / kPix));
+        }
+    }
+    hipError_t e = hipSuccess;
+    if (!l2[0].empty() && (e = l2_walk<uint8_t>(r, l2[0], l2_blocks[0])) != hipSuccess) return e;
+    if (!l2[1].empty() && (e = l2_walk<float>(r, l2[1], l2_blocks[1])) != hipSuccess) return e;
+    if (!census_jobs.empty()) {
+        if ((e = stage_census(r, census_jobs, true)) != hipSuccess) return e;
+        e = launch(r, kStCost, cost_census_all_kernel<Single<CensusAllArgs>>,
+                   cost_census_all_kernel<Group<CensusAllArgs>>, ca, ca_blocks, kThreads);
+    }
+    return e;
 }
 
 }  // namespace lf

@@ -1,10 +1,23 @@
-// Internal declarations of liblf: device helpers and the host-side launchers each
-// kernel file provides to the API layer (api.hip).  Not part of the ABI.
+// Internal declarations of liblf: the description of one light field's work
+// (Job), the way a stage's launches are issued (Runner), and the stage functions
+// each kernel file provides to the API layer.  Not part of the ABI.
+//
+// Every kernel exists in two forms built from one body:
+//   Single<A>  one light field, its argument record A passed by value;
+//   Group<A>   n light fields, records in device memory, member i owning the
+//              virtual blocks [prefix[i], prefix[i+1]) of the launch.
+// A launch may have fewer workgroups than virtual blocks; a workgroup then loops
+// over them (persistent workgroups).  The single-light-field entry points issue
+// Single launches directly; a batch plan records Group launches over all of its
+// light fields, one per stage and kernel variant.
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <stddef.h>
+
+#include <functional>
+#include <vector>
 
 #include "../../include/lf.h"
 
@@ -19,73 +32,174 @@ __device__ __forceinline__ int clampi(int x, int lo, int hi) { return min(max(x,
 // Loads one view sample as float (8-bit values convert exactly).
 template <typename T> __device__ __forceinline__ float ld(const T* p) { return (float)*p; }
 
-// Census of up to kMaxBatchImages images sharing a size; image z starts at
-// base + off[z] elements.  When n > kMaxBatchImages the images are taken at a
-// constant stride: off[z] = z * stride.
-struct CensusBatch {
-    const void* base;
-    int64_t off[kMaxBatchImages];
-    int64_t stride;
+// --- grouped launches --------------------------------------------------------
+template <class A> struct Single {
+    A a;
+    uint32_t total;
+};
+
+template <class A> struct Group {
+    const A* a;
+    const uint32_t* prefix;   // [n + 1]
     int n;
+    uint32_t total;
 };
 
-hipError_t launch_census(const CensusBatch& b, int dtype, int H, int W, int pitch, int win_h,
-                         int win_w, uint64_t* out, hipStream_t st);
+template <class A>
+__device__ __forceinline__ const A& member(const Single<A>& s, uint32_t vb, uint32_t& local) {
+    local = vb;
+    return s.a;
+}
 
-// --- SGM -------------------------------------------------------------------
-struct SgmDense {                // initial stage: Census cost on the fly, all N hypotheses
-    const uint64_t* cref;        // [H*W]
-    const uint64_t* cview;       // [nv][H*W]
-    int16_t* dmap;               // [nv][H*W] WTA result
-    int cs[4], ct[4];            // s_hat - s, t_hat - t of each cross view
-    int nv;
+template <class A>
+__device__ __forceinline__ const A& member(const Group<A>& g, uint32_t vb, uint32_t& local) {
+    int lo = 0, hi = g.n;                     // prefix[lo] <= vb < prefix[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (g.prefix[mid] <= vb) lo = mid; else hi = mid;
+    }
+    local = vb - g.prefix[lo];
+    return g.a[lo];
+}
+
+// Tunable schedule parameters.  None of them changes a result.
+struct Tuning {
+    int cost_cpt = 4;        // cells per thread of the bounded cost kernel (2, 4, 8)
+    int cost_stride = 1;     // slices walked per cost workgroup (1, 2, 4)
+    int dense_depth = 8;     // steps prefetched by the initial-stage SGM (4, 8, 16)
+    int bounded_depth = 8;   // steps prefetched by the bounded SGM (4, 8)
 };
 
-struct SgmBounded {              // final stage: CSR volume over per-pixel ranges
-    const uint16_t* cost;
-    const int64_t* off;          // [H*W+1]; off[H*W] is the cell count
-    const int16_t* lo;
-    const int16_t* hi;
-    void* csum;                  // uint16 or uint32 [cells]
-    int sum_bits;
+// Stages of the method, in order (also the profiling buckets).
+enum Stage { kStCensus, kStSgmInit, kStBorders, kStOffsets, kStCost, kStSgmFinal, kStWta,
+             kNumStages };
+
+// Receives the launches of a batch plan.  table() copies host records into the
+// plan's device table and returns their device address.
+class Recorder {
+public:
+    virtual ~Recorder() = default;
+    virtual const void* table(const void* host, size_t bytes) = 0;
+    virtual void add(int stage, std::function<hipError_t(hipStream_t)> fn) = 0;
 };
 
-// Scratch for the per-direction path costs (bytes).
+struct Runner {
+    hipStream_t stream = nullptr;   // immediate launches
+    Recorder* rec = nullptr;        // non-null: record instead
+    Tuning tune;
+    int launches = 0;               // kernels launched or recorded so far
+};
+
+constexpr size_t kMaxArgRecord = 256;   // bytes of one argument record in a plan table
+
+template <class A>
+hipError_t launch(Runner& r, int stage, void (*ks)(Single<A>), void (*kg)(Group<A>),
+                  const std::vector<A>& args, const std::vector<uint32_t>& blocks,
+                  uint32_t threads, uint32_t grid_cap = 0) {
+    static_assert(sizeof(A) <= kMaxArgRecord, "argument record too large for a plan table");
+    const int n = (int)args.size();
+    if (!r.rec) {
+        for (int i = 0; i < n; ++i) {
+            if (blocks[i] == 0) continue;
+            const uint32_t grid = grid_cap && grid_cap < blocks[i] ? grid_cap : blocks[i];
+            Single<A> s{args[i], blocks[i]};
+            void* kargs[] = {&s};
+            hipError_t e = hipLaunchKernel((const void*)ks, dim3(grid), dim3(threads), kargs, 0,
+                                           r.stream);
+            if (e != hipSuccess) return e;
+            ++r.launches;
+        }
+        return hipGetLastError();
+    }
+    std::vector<uint32_t> prefix(n + 1, 0);
+    for (int i = 0; i < n; ++i) prefix[i + 1] = prefix[i] + blocks[i];
+    const uint32_t total = prefix[n];
+    if (total == 0) return hipSuccess;
+    Group<A> g;
+    g.a = (const A*)r.rec->table(args.data(), n * sizeof(A));
+    g.prefix = (const uint32_t*)r.rec->table(prefix.data(), (n + 1) * sizeof(uint32_t));
+    g.n = n;
+    g.total = total;
+    const uint32_t grid = grid_cap && grid_cap < total ? grid_cap : total;
+    ++r.launches;
+    r.rec->add(stage, [=](hipStream_t st) mutable -> hipError_t {
+        void* kargs[] = {&g};
+        return hipLaunchKernel((const void*)kg, dim3(grid), dim3(threads), kargs, 0, st);
+    });
+    return hipSuccess;
+}
+
+// --- one light field's work ----------------------------------------------------
+// Inputs, parameters and the device buffers every stage reads or writes.  A stage
+// uses only the buffers it needs; the others may be null.
+struct Job {
+    const void* views;        // [T][S][H][pitch]
+    int dtype, S, T, H, W, pitch, N;
+    const float* hyp;         // [N]
+    lf_params prm;
+    float alpha;              // effective cost scale
+    int32_t cap;              // saturation of the quantised cost
+    int nv;                   // cross views
+    int st[8];                // (s, t) of each cross view
+    // initial stage
+    uint64_t* census;         // [1 + nv][H*W]: reference, then the cross views
+    void* paths;              // initial SGM scratch (sgm_dense_scratch_bytes)
+    int16_t* maps;            // [nv][H*W] D_i
+    int16_t* fill_tmp;        // [H*W]
+    int16_t* dinit;           // [H*W]
+    int16_t* lo;              // [H*W]
+    int16_t* hi;              // [H*W]
+    // bounded stage
+    int64_t* offsets;         // [H*W + 1]
+    void* scan;               // scan_scratch_bytes(H*W)
+    uint64_t* census_all;     // [S*T][H*W] (Census cost kind)
+    uint16_t* cost;           // [cells]
+    float* cost_f32;          // [cells] or null
+    int64_t cap_cells;
+    void* sgm_ws;             // sgm_bounded_scratch_bytes
+    void* csum;               // [cells] uint16 or uint32
+    int16_t* d_index;         // [H*W]
+    float* pre_median;        // [H*W] (median == 3)
+    float* disparity;         // [H*W]
+};
+
+using Jobs = std::vector<const Job*>;
+
+int cross_views(int S, int T, int* st);
+int dense_np(int N);
+
+// Scratch sizes (bytes).
 size_t sgm_dense_scratch_bytes(int nv, int H, int W, int N, int npaths, int bits, int P2);
 size_t sgm_bounded_scratch_bytes(int H, int W, int N, int npaths);
-
-// bits: Census string length (bounds the initial cost); scratch: see above.
-hipError_t launch_sgm_dense(const SgmDense& a, const float* hyp, int H, int W, int N, int P1,
-                            int P2, int npaths, int bits, void* scratch, hipStream_t st);
-hipError_t launch_sgm_bounded(const SgmBounded& a, int H, int W, int N, int P1, int P2,
-                              int npaths, void* scratch, hipStream_t st);
-
-// --- per-pixel stages ------------------------------------------------------
-hipError_t launch_fuse(const int16_t* maps, int nv, int HW, int phi, int16_t* dinit,
-                       hipStream_t st);
-hipError_t launch_fill(const int16_t* in, int16_t* out, int H, int W, hipStream_t st);
-hipError_t launch_borders(const int16_t* dinit, const void* ref, int dtype, int pitch, int H,
-                          int W, int N, int lambda, float alpha, float tau, int16_t* lo,
-                          int16_t* hi, hipStream_t st);
-
-// exclusive prefix sum of range widths -> offsets[HW+1]; scratch >= scan_scratch_bytes(HW)
 size_t scan_scratch_bytes(int64_t HW);
-hipError_t launch_offsets(const int16_t* lo, const int16_t* hi, int64_t HW, int64_t* offsets,
-                          void* scratch, hipStream_t st);
 
-hipError_t launch_cost_l2(const void* views, int dtype, int S, int T, int H, int W, int pitch,
-                          const float* hyp, int N, const int16_t* lo, const int16_t* hi,
-                          const int64_t* off, float alpha, int32_t cap, uint16_t* cost,
-                          float* cost_f32, int64_t cap_cells, hipStream_t st);
-hipError_t launch_cost_census_all(const uint64_t* census_all, int S, int T, int H, int W,
-                                  const float* hyp, int N, const int16_t* lo, const int16_t* hi,
-                                  const int64_t* off, int32_t cap, uint16_t* cost,
-                                  float* cost_f32, int64_t cap_cells, hipStream_t st);
+// Census of the reference and cross views (initial) or of all S*T views (into
+// census_all, for the Census cost kind).
+hipError_t stage_census(Runner& r, const Jobs& jobs, bool all_views);
+// A standalone Census transform of one image.
+hipError_t census_image(Runner& r, const void* img, int dtype, int H, int W, int pitch,
+                        int win_h, int win_w, uint64_t* out);
+// Census cost + SGM + WTA over the cross views -> maps.
+hipError_t stage_sgm_initial(Runner& r, const Jobs& jobs);
+// Fusion, fill passes ending in dinit, edges and borders -> dinit, lo, hi.
+hipError_t stage_borders(Runner& r, const Jobs& jobs);
+// Exclusive prefix sum of the range widths -> offsets.
+hipError_t stage_offsets(Runner& r, const Jobs& jobs);
+// Bounded matching cost (l2 or Census kind) -> cost (and cost_f32).
+hipError_t stage_cost(Runner& r, const Jobs& jobs);
+// Bounded SGM -> csum.
+hipError_t stage_sgm_final(Runner& r, const Jobs& jobs);
+// WTA + sub-pixel (+ median) -> d_index, disparity.
+hipError_t stage_wta(Runner& r, const Jobs& jobs);
 
-hipError_t launch_wta_subpixel(const void* csum, int sum_bits, const int64_t* off,
-                               const int16_t* lo, const int16_t* hi, int H, int W,
-                               const float* hyp, int16_t* d_index, float* disp,
-                               hipStream_t st);
-hipError_t launch_median3(const float* in, float* out, int H, int W, hipStream_t st);
+// --- the whole method over jobs (api.hip) --------------------------------------
+// Checks a request as lf_depth checks its arguments (ws may be null: then only
+// the light field and parameters are checked).
+lf_status validate_request(const lf_request* q, size_t ws_bytes, const void* ws);
+size_t request_workspace_bytes(const lf_request* q);
+Job request_job(const lf_request* q, void* ws);
+lf_status run_depth_jobs(Runner& r, const Jobs& jobs);
+// Sets the thread's last error (lf_last_error) and returns s.
+lf_status record_error(lf_status s, const char* fmt, const char* what);
 
 }  // namespace lf

@@ -10,35 +10,48 @@ namespace {
 
 constexpr int kThreads = 256;
 
-inline dim3 grid1d(int64_t n) { return dim3((unsigned)((n + kThreads - 1) / kThreads)); }
+uint32_t blocks_for(int64_t n) { return (uint32_t)((n + kThreads - 1) / kThreads); }
 
 // --- fusion with confidence threshold phi (Sec. 3.4) -----------------------
-__global__ __launch_bounds__(kThreads) void fuse_kernel(const int16_t* __restrict__ maps, int nv,
-                                                        int HW, int phi,
-                                                        int16_t* __restrict__ dinit) {
-    const int p = blockIdx.x * kThreads + threadIdx.x;
-    if (p >= HW) return;
-    int acc = maps[p];
-    bool valid = true;
-    for (int i = 1; i < nv; ++i) {
-        const int di = maps[(size_t)i * HW + p];
-        if (valid && abs(acc - di) < phi)
-            acc = (acc + di) >> 1;
-        else
-            valid = false;
+struct FuseArgs {
+    const int16_t* maps;      // [nv][HW]
+    int16_t* dinit;
+    int nv, HW, phi;
+};
+
+template <class Src>
+__global__ __launch_bounds__(kThreads) void fuse_kernel(Src src) {
+    for (uint32_t vb = blockIdx.x; vb < src.total; vb += gridDim.x) {
+        uint32_t b;
+        const FuseArgs& a = member(src, vb, b);
+        const int p = (int)b * kThreads + threadIdx.x;
+        if (p >= a.HW) continue;
+        int acc = a.maps[p];
+        bool valid = true;
+        for (int i = 1; i < a.nv; ++i) {
+            const int di = a.maps[(size_t)i * a.HW + p];
+            if (valid && abs(acc - di) < a.phi)
+                acc = (acc + di) >> 1;
+            else
+                valid = false;
+        }
+        a.dinit[p] = (int16_t)(valid ? acc : -1);
     }
-    dinit[p] = (int16_t)(valid ? acc : -1);
 }
 
 // --- one median hole-filling pass: lower median of the valid 8-neighbours ---
-__global__ __launch_bounds__(kThreads) void fill_kernel(const int16_t* __restrict__ in,
-                                                        int16_t* __restrict__ out, int H, int W) {
-    const int p = blockIdx.x * kThreads + threadIdx.x;
-    if (p >= H * W) return;
+struct FillArgs {
+    const int16_t* in;
+    int16_t* out;
+    int H, W;
+};
+
+__device__ __forceinline__ void fill_pixel(const FillArgs& a, int p) {
+    const int H = a.H, W = a.W;
     const int v = p / W, u = p - v * W;
-    const int d0 = in[p];
+    const int d0 = a.in[p];
     if (d0 >= 0) {
-        out[p] = (int16_t)d0;
+        a.out[p] = (int16_t)d0;
         return;
     }
     // rank-based selection: the lower median of n values is the one with
@@ -49,55 +62,90 @@ __global__ __launch_bounds__(kThreads) void fill_kernel(const int16_t* __restric
             if (i == 0 && j == 0) continue;
             const int y = v + i, x = u + j;
             if (y < 0 || y >= H || x < 0 || x >= W) continue;
-            const int d = in[(size_t)y * W + x];
+            const int d = a.in[(size_t)y * W + x];
             if (d >= 0) vals[n++] = d;
         }
     int res = -1;
     const int want = (n - 1) / 2;
-    for (int a = 0; a < n; ++a) {
+    for (int x = 0; x < n; ++x) {
         int below = 0, atmost = 0;
-        for (int b = 0; b < n; ++b) {
-            below += vals[b] < vals[a];
-            atmost += vals[b] <= vals[a];
+        for (int y = 0; y < n; ++y) {
+            below += vals[y] < vals[x];
+            atmost += vals[y] <= vals[x];
         }
-        if (below <= want && want < atmost) res = vals[a];
+        if (below <= want && want < atmost) res = vals[x];
     }
-    out[p] = (int16_t)res;
+    a.out[p] = (int16_t)res;
+}
+
+template <class Src>
+__global__ __launch_bounds__(kThreads) void fill_kernel(Src src) {
+    for (uint32_t vb = blockIdx.x; vb < src.total; vb += gridDim.x) {
+        uint32_t b;
+        const FillArgs& a = member(src, vb, b);
+        const int p = (int)b * kThreads + threadIdx.x;
+        if (p < a.H * a.W) fill_pixel(a, p);
+    }
 }
 
 // --- Sobel edge exclusion and borders, Eq. (11) -----------------------------
+struct BordersArgs {
+    const int16_t* dinit;
+    const void* ref;
+    int16_t* lo;
+    int16_t* hi;
+    int pitch, H, W, N, lambda;
+    float alpha, tau;
+};
+
 template <typename T>
-__global__ __launch_bounds__(kThreads) void borders_kernel(const int16_t* __restrict__ dinit,
-                                                           const T* __restrict__ ref, int pitch,
-                                                           int H, int W, int N, int lambda,
-                                                           float alpha, float tau,
-                                                           int16_t* __restrict__ lo,
-                                                           int16_t* __restrict__ hi) {
-    const int p = blockIdx.x * kThreads + threadIdx.x;
-    if (p >= H * W) return;
+__device__ __forceinline__ void borders_pixel(const BordersArgs& a, int p) {
+    const int H = a.H, W = a.W;
+    const T* __restrict__ ref = (const T*)a.ref;
     const int v = p / W, u = p - v * W;
     const int ym = max(v - 1, 0), yp = min(v + 1, H - 1);
     const int xm = max(u - 1, 0), xp = min(u + 1, W - 1);
-    auto I = [&](int y, int x) { return ld(ref + (size_t)y * pitch + x); };
+    auto I = [&](int y, int x) { return ld(ref + (size_t)y * a.pitch + x); };
     const float gx = ((I(ym, xp) + 2.0f * I(v, xp)) + I(yp, xp)) -
                      ((I(ym, xm) + 2.0f * I(v, xm)) + I(yp, xm));
     const float gy = ((I(yp, xm) + 2.0f * I(yp, u)) + I(yp, xp)) -
                      ((I(ym, xm) + 2.0f * I(ym, u)) + I(ym, xp));
     const float g = fabsf(gx) + fabsf(gy);
-    const bool edge = alpha * g > tau;
-    const int d = dinit[p];
+    const bool edge = a.alpha * g > a.tau;
+    const int d = a.dinit[p];
     if (d < 0 || edge) {
-        lo[p] = 0;
-        hi[p] = (int16_t)(N - 1);
+        a.lo[p] = 0;
+        a.hi[p] = (int16_t)(a.N - 1);
     } else {
-        lo[p] = (int16_t)max(d - lambda, 0);
-        hi[p] = (int16_t)min(d + lambda, N - 1);
+        a.lo[p] = (int16_t)max(d - a.lambda, 0);
+        a.hi[p] = (int16_t)min(d + a.lambda, a.N - 1);
+    }
+}
+
+template <class Src, typename T>
+__global__ __launch_bounds__(kThreads) void borders_kernel(Src src) {
+    for (uint32_t vb = blockIdx.x; vb < src.total; vb += gridDim.x) {
+        uint32_t b;
+        const BordersArgs& a = member(src, vb, b);
+        const int p = (int)b * kThreads + threadIdx.x;
+        if (p < a.H * a.W) borders_pixel<T>(a, p);
     }
 }
 
 // --- exclusive prefix sum of the range widths -> CSR offsets ----------------
+// Three launches: per-tile totals, a scan of the totals (one workgroup per light
+// field), and the per-tile scan plus its tile base.
 constexpr int kScanPerThread = 8;
 constexpr int kScanTile = kThreads * kScanPerThread;
+
+struct ScanArgs {
+    const int16_t* lo;
+    const int16_t* hi;
+    int64_t* bsum;            // [nb]: tile totals, then tile bases
+    int64_t* offsets;         // [HW + 1]
+    int64_t HW;
+    int nb;
+};
 
 __device__ __forceinline__ int64_t block_exclusive_scan(int64_t x, int64_t* sh, int64_t& total) {
     // Hillis-Steele over the 256 per-thread partial sums in LDS
@@ -116,74 +164,86 @@ __device__ __forceinline__ int64_t block_exclusive_scan(int64_t x, int64_t* sh, 
     return excl;
 }
 
-__global__ __launch_bounds__(kThreads) void scan_reduce_kernel(const int16_t* __restrict__ lo,
-                                                               const int16_t* __restrict__ hi,
-                                                               int64_t HW,
-                                                               int64_t* __restrict__ bsum) {
+template <class Src>
+__global__ __launch_bounds__(kThreads) void scan_reduce_kernel(Src src) {
     __shared__ int64_t sh[kThreads];
-    const int64_t base = (int64_t)blockIdx.x * kScanTile;
-    int64_t s = 0;
-    for (int i = 0; i < kScanPerThread; ++i) {
-        const int64_t p = base + (int64_t)i * kThreads + threadIdx.x;
-        if (p < HW) s += (int64_t)(hi[p] - lo[p] + 1);
-    }
-    int64_t total;
-    block_exclusive_scan(s, sh, total);
-    if (threadIdx.x == 0) bsum[blockIdx.x] = total;
-}
-
-__global__ __launch_bounds__(kThreads) void scan_blocks_kernel(int64_t* __restrict__ bsum,
-                                                               int nblocks,
-                                                               int64_t* __restrict__ offsets,
-                                                               int64_t HW) {
-    // single workgroup: exclusive scan of the per-tile totals, in chunks of 256
-    __shared__ int64_t sh[kThreads];
-    int64_t carry = 0;
-    for (int c = 0; c < nblocks; c += kThreads) {
-        const int i = c + threadIdx.x;
-        const int64_t x = i < nblocks ? bsum[i] : 0;
+    for (uint32_t vb = blockIdx.x; vb < src.total; vb += gridDim.x) {
+        uint32_t b;
+        const ScanArgs& a = member(src, vb, b);
+        const int64_t base = (int64_t)b * kScanTile;
+        int64_t s = 0;
+        for (int i = 0; i < kScanPerThread; ++i) {
+            const int64_t p = base + (int64_t)i * kThreads + threadIdx.x;
+            if (p < a.HW) s += (int64_t)(a.hi[p] - a.lo[p] + 1);
+        }
         int64_t total;
-        const int64_t ex = block_exclusive_scan(x, sh, total);
-        if (i < nblocks) bsum[i] = carry + ex;
-        carry += total;
+        block_exclusive_scan(s, sh, total);
+        if (threadIdx.x == 0) a.bsum[b] = total;
     }
-    if (threadIdx.x == 0) offsets[HW] = carry;
 }
 
-__global__ __launch_bounds__(kThreads) void scan_apply_kernel(const int16_t* __restrict__ lo,
-                                                              const int16_t* __restrict__ hi,
-                                                              int64_t HW,
-                                                              const int64_t* __restrict__ bsum,
-                                                              int64_t* __restrict__ offsets) {
+template <class Src>
+__global__ __launch_bounds__(kThreads) void scan_blocks_kernel(Src src) {
+    // one workgroup per light field: exclusive scan of the tile totals, in chunks of 256
     __shared__ int64_t sh[kThreads];
-    // each thread owns kScanPerThread consecutive pixels of the tile
-    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPerThread;
-    int w[kScanPerThread];
-    int64_t s = 0;
-    for (int i = 0; i < kScanPerThread; ++i) {
-        const int64_t p = base + i;
-        w[i] = p < HW ? hi[p] - lo[p] + 1 : 0;
-        s += w[i];
+    for (uint32_t vb = blockIdx.x; vb < src.total; vb += gridDim.x) {
+        uint32_t b;
+        const ScanArgs& a = member(src, vb, b);
+        int64_t carry = 0;
+        for (int c = 0; c < a.nb; c += kThreads) {
+            const int i = c + threadIdx.x;
+            const int64_t x = i < a.nb ? a.bsum[i] : 0;
+            int64_t total;
+            const int64_t ex = block_exclusive_scan(x, sh, total);
+            if (i < a.nb) a.bsum[i] = carry + ex;
+            carry += total;
+        }
+        if (threadIdx.x == 0) a.offsets[a.HW] = carry;
     }
-    int64_t total;
-    int64_t run = bsum[blockIdx.x] + block_exclusive_scan(s, sh, total);
-    for (int i = 0; i < kScanPerThread; ++i) {
-        const int64_t p = base + i;
-        if (p < HW) offsets[p] = run;
-        run += w[i];
+}
+
+template <class Src>
+__global__ __launch_bounds__(kThreads) void scan_apply_kernel(Src src) {
+    __shared__ int64_t sh[kThreads];
+    for (uint32_t vb = blockIdx.x; vb < src.total; vb += gridDim.x) {
+        uint32_t b;
+        const ScanArgs& a = member(src, vb, b);
+        // each thread owns kScanPerThread consecutive pixels of the tile
+        const int64_t base = (int64_t)b * kScanTile + (int64_t)threadIdx.x * kScanPerThread;
+        int w[kScanPerThread];
+        int64_t s = 0;
+        for (int i = 0; i < kScanPerThread; ++i) {
+            const int64_t p = base + i;
+            w[i] = p < a.HW ? a.hi[p] - a.lo[p] + 1 : 0;
+            s += w[i];
+        }
+        int64_t total;
+        int64_t run = a.bsum[b] + block_exclusive_scan(s, sh, total);
+        for (int i = 0; i < kScanPerThread; ++i) {
+            const int64_t p = base + i;
+            if (p < a.HW) a.offsets[p] = run;
+            run += w[i];
+        }
     }
 }
 
 // --- WTA (Eq. 10) and the parabola sub-pixel step (Sec. 3.6) ----------------
+struct WtaArgs {
+    const void* csum;
+    const int64_t* off;
+    const int16_t* lo;
+    const int16_t* hi;
+    const float* hyp;
+    int16_t* d_index;
+    float* disp;
+    int HW;
+};
+
 template <typename SumT>
-__global__ __launch_bounds__(kThreads) void wta_subpixel_kernel(
-    const SumT* __restrict__ csum, const int64_t* __restrict__ off,
-    const int16_t* __restrict__ lo, const int16_t* __restrict__ hi, int HW,
-    const float* __restrict__ hyp, int16_t* __restrict__ d_index, float* __restrict__ disp) {
-    const int p = blockIdx.x * kThreads + threadIdx.x;
-    if (p >= HW) return;
-    const int l = lo[p], h = hi[p];
-    const SumT* c = csum + off[p] - l;     // c[k] for k in [l, h]
+__device__ __forceinline__ void wta_pixel(const WtaArgs& a, int p) {
+    const int l = a.lo[p], h = a.hi[p];
+    const SumT* c = (const SumT*)a.csum + a.off[p] - l;     // c[k] for k in [l, h]
+    const float* hyp = a.hyp;
     int best = l;
     uint32_t bv = c[l];
     for (int k = l + 1; k <= h; ++k) {
@@ -193,7 +253,7 @@ __global__ __launch_bounds__(kThreads) void wta_subpixel_kernel(
             best = k;
         }
     }
-    d_index[p] = (int16_t)best;
+    a.d_index[p] = (int16_t)best;
     float d = hyp[best];
     if (best - 1 >= l && best + 1 <= h && h - l >= 4) {
         const int64_t cm = c[best - 1], c0 = c[best], cp = c[best + 1];
@@ -201,95 +261,191 @@ __global__ __launch_bounds__(kThreads) void wta_subpixel_kernel(
         d = o >= 0.0f ? fmaf(o, hyp[best + 1] - hyp[best], hyp[best])
                       : fmaf(o, hyp[best] - hyp[best - 1], hyp[best]);
     }
-    disp[p] = d;
+    a.disp[p] = d;
+}
+
+template <class Src, typename SumT>
+__global__ __launch_bounds__(kThreads) void wta_subpixel_kernel(Src src) {
+    for (uint32_t vb = blockIdx.x; vb < src.total; vb += gridDim.x) {
+        uint32_t b;
+        const WtaArgs& a = member(src, vb, b);
+        const int p = (int)b * kThreads + threadIdx.x;
+        if (p < a.HW) wta_pixel<SumT>(a, p);
+    }
 }
 
 // --- 3x3 median, clamp-to-edge ----------------------------------------------
-__global__ __launch_bounds__(kThreads) void median3_kernel(const float* __restrict__ in,
-                                                           float* __restrict__ out, int H, int W) {
-    const int p = blockIdx.x * kThreads + threadIdx.x;
-    if (p >= H * W) return;
+struct MedianArgs {
+    const float* in;
+    float* out;
+    int H, W;
+};
+
+__device__ __forceinline__ void median_pixel(const MedianArgs& a, int p) {
+    const int H = a.H, W = a.W;
     const int v = p / W, u = p - v * W;
     float w[9];
     int n = 0;
     for (int i = -1; i <= 1; ++i) {
         const int y = clampi(v + i, 0, H - 1);
-        for (int j = -1; j <= 1; ++j) w[n++] = in[(size_t)y * W + clampi(u + j, 0, W - 1)];
+        for (int j = -1; j <= 1; ++j) w[n++] = a.in[(size_t)y * W + clampi(u + j, 0, W - 1)];
     }
     // rank selection: the median has at most 4 values below it and at least 5 at or below
     float med = w[4];
 #pragma unroll
-    for (int a = 0; a < 9; ++a) {
+    for (int x = 0; x < 9; ++x) {
         int below = 0, atmost = 0;
 #pragma unroll
-        for (int b = 0; b < 9; ++b) {
-            below += w[b] < w[a];
-            atmost += w[b] <= w[a];
+        for (int y = 0; y < 9; ++y) {
+            below += w[y] < w[x];
+            atmost += w[y] <= w[x];
         }
-        if (below <= 4 && 4 < atmost) med = w[a];
+        if (below <= 4 && 4 < atmost) med = w[x];
     }
-    out[p] = med;
+    a.out[p] = med;
+}
+
+template <class Src>
+__global__ __launch_bounds__(kThreads) void median3_kernel(Src src) {
+    for (uint32_t vb = blockIdx.x; vb < src.total; vb += gridDim.x) {
+        uint32_t b;
+        const MedianArgs& a = member(src, vb, b);
+        const int p = (int)b * kThreads + threadIdx.x;
+        if (p < a.H * a.W) median_pixel(a, p);
+    }
 }
 
 }  // namespace
-
-hipError_t launch_fuse(const int16_t* maps, int nv, int HW, int phi, int16_t* dinit,
-                       hipStream_t st) {
-    hipLaunchKernelGGL(fuse_kernel, grid1d(HW), dim3(kThreads), 0, st, maps, nv, HW, phi, dinit);
-    return hipGetLastError();
-}
-
-hipError_t launch_fill(const int16_t* in, int16_t* out, int H, int W, hipStream_t st) {
-    hipLaunchKernelGGL(fill_kernel, grid1d((int64_t)H * W), dim3(kThreads), 0, st, in, out, H, W);
-    return hipGetLastError();
-}
-
-hipError_t launch_borders(const int16_t* dinit, const void* ref, int dtype, int pitch, int H,
-                          int W, int N, int lambda, float alpha, float tau, int16_t* lo,
-                          int16_t* hi, hipStream_t st) {
-    if (dtype == LF_U8)
-        hipLaunchKernelGGL(borders_kernel<uint8_t>, grid1d((int64_t)H * W), dim3(kThreads), 0, st,
-                           dinit, (const uint8_t*)ref, pitch, H, W, N, lambda, alpha, tau, lo, hi);
-    else
-        hipLaunchKernelGGL(borders_kernel<float>, grid1d((int64_t)H * W), dim3(kThreads), 0, st,
-                           dinit, (const float*)ref, pitch, H, W, N, lambda, alpha, tau, lo, hi);
-    return hipGetLastError();
-}
 
 size_t scan_scratch_bytes(int64_t HW) {
     const int64_t nb = (HW + kScanTile - 1) / kScanTile;
     return (size_t)(nb + 1) * sizeof(int64_t);
 }
 
-hipError_t launch_offsets(const int16_t* lo, const int16_t* hi, int64_t HW, int64_t* offsets,
-                          void* scratch, hipStream_t st) {
-    const int nb = (int)((HW + kScanTile - 1) / kScanTile);
-    int64_t* bsum = (int64_t*)scratch;
-    hipLaunchKernelGGL(scan_reduce_kernel, dim3(nb), dim3(kThreads), 0, st, lo, hi, HW, bsum);
-    hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(kThreads), 0, st, bsum, nb, offsets, HW);
-    hipLaunchKernelGGL(scan_apply_kernel, dim3(nb), dim3(kThreads), 0, st, lo, hi, HW, bsum,
-                       offsets);
-    return hipGetLastError();
+hipError_t stage_borders(Runner& r, const Jobs& jobs) {
+    std::vector<FuseArgs> fuse;
+    std::vector<uint32_t> fuse_blocks;
+    std::vector<BordersArgs> brd[2];
+    std::vector<uint32_t> brd_blocks[2];
+    int max_passes = 0;
+    for (const Job* j : jobs) {
+        const int HW = j->H * j->W;
+        int16_t* buf[2] = {j->dinit, j->fill_tmp};
+        // the passes ping-pong between the two buffers and end in dinit
+        fuse.push_back(FuseArgs{j->maps, buf[j->prm.fill_passes % 2], j->nv, HW, j->prm.phi});
+        fuse_blocks.push_back(blocks_for(HW));
+        max_passes = std::max(max_passes, j->prm.fill_passes);
+        const int sh = (j->S - 1) / 2, th = (j->T - 1) / 2;
+        const size_t elem = j->dtype == LF_U8 ? 1 : 4;
+        BordersArgs b{};
+        b.dinit = j->dinit;
+        b.ref = (const char*)j->views + ((size_t)th * j->S + sh) * j->H * j->pitch * elem;
+        b.lo = j->lo;
+        b.hi = j->hi;
+        b.pitch = j->pitch;
+        b.H = j->H;
+        b.W = j->W;
+        b.N = j->N;
+        b.lambda = j->prm.lambda;
+        b.alpha = j->alpha;
+        b.tau = j->prm.edge_tau;
+        brd[j->dtype == LF_U8 ? 0 : 1].push_back(b);
+        brd_blocks[j->dtype == LF_U8 ? 0 : 1].push_back(blocks_for(HW));
+    }
+    hipError_t e = launch(r, kStBorders, fuse_kernel<Single<FuseArgs>>,
+                          fuse_kernel<Group<FuseArgs>>, fuse, fuse_blocks, kThreads);
+    if (e != hipSuccess) return e;
+    for (int f = 0; f < max_passes; ++f) {
+        std::vector<FillArgs> fill;
+        std::vector<uint32_t> fill_blocks;
+        for (const Job* j : jobs) {
+            if (f >= j->prm.fill_passes) continue;
+            int16_t* buf[2] = {j->dinit, j->fill_tmp};
+            const int cur = (j->prm.fill_passes + f) % 2;
+            fill.push_back(FillArgs{buf[cur], buf[cur ^ 1], j->H, j->W});
+            fill_blocks.push_back(blocks_for((int64_t)j->H * j->W));
+        }
+        e = launch(r, kStBorders, fill_kernel<Single<FillArgs>>, fill_kernel<Group<FillArgs>>,
+                   fill, fill_blocks, kThreads);
+        if (e != hipSuccess) return e;
+    }
+    if (!brd[0].empty()) {
+        e = launch(r, kStBorders, borders_kernel<Single<BordersArgs>, uint8_t>,
+                   borders_kernel<Group<BordersArgs>, uint8_t>, brd[0], brd_blocks[0], kThreads);
+        if (e != hipSuccess) return e;
+    }
+    if (!brd[1].empty())
+        e = launch(r, kStBorders, borders_kernel<Single<BordersArgs>, float>,
+                   borders_kernel<Group<BordersArgs>, float>, brd[1], brd_blocks[1], kThreads);
+    return e;
 }
 
-hipError_t launch_wta_subpixel(const void* csum, int sum_bits, const int64_t* off,
-                               const int16_t* lo, const int16_t* hi, int H, int W,
-                               const float* hyp, int16_t* d_index, float* disp,
-                               hipStream_t st) {
-    const int HW = H * W;
-    if (sum_bits == 16)
-        hipLaunchKernelGGL(wta_subpixel_kernel<uint16_t>, grid1d(HW), dim3(kThreads), 0, st,
-                           (const uint16_t*)csum, off, lo, hi, HW, hyp, d_index, disp);
-    else
-        hipLaunchKernelGGL(wta_subpixel_kernel<uint32_t>, grid1d(HW), dim3(kThreads), 0, st,
-                           (const uint32_t*)csum, off, lo, hi, HW, hyp, d_index, disp);
-    return hipGetLastError();
+hipError_t stage_offsets(Runner& r, const Jobs& jobs) {
+    std::vector<ScanArgs> args;
+    std::vector<uint32_t> tiles, ones;
+    for (const Job* j : jobs) {
+        const int64_t HW = (int64_t)j->H * j->W;
+        ScanArgs a{};
+        a.lo = j->lo;
+        a.hi = j->hi;
+        a.bsum = (int64_t*)j->scan;
+        a.offsets = j->offsets;
+        a.HW = HW;
+        a.nb = (int)((HW + kScanTile - 1) / kScanTile);
+        args.push_back(a);
+        tiles.push_back((uint32_t)a.nb);
+        ones.push_back(1);
+    }
+    hipError_t e = launch(r, kStOffsets, scan_reduce_kernel<Single<ScanArgs>>,
+                          scan_reduce_kernel<Group<ScanArgs>>, args, tiles, kThreads);
+    if (e != hipSuccess) return e;
+    e = launch(r, kStOffsets, scan_blocks_kernel<Single<ScanArgs>>,
+               scan_blocks_kernel<Group<ScanArgs>>, args, ones, kThreads);
+    if (e != hipSuccess) return e;
+    return launch(r, kStOffsets, scan_apply_kernel<Single<ScanArgs>>,
+                  scan_apply_kernel<Group<ScanArgs>>, args, tiles, kThreads);
 }
 
-hipError_t launch_median3(const float* in, float* out, int H, int W, hipStream_t st) {
-    hipLaunchKernelGGL(median3_kernel, grid1d((int64_t)H * W), dim3(kThreads), 0, st, in, out, H,
-                       W);
-    return hipGetLastError();
+hipError_t stage_wta(Runner& r, const Jobs& jobs) {
+    std::vector<WtaArgs> wta[2];
+    std::vector<uint32_t> wta_blocks[2];
+    std::vector<MedianArgs> med;
+    std::vector<uint32_t> med_blocks;
+    for (const Job* j : jobs) {
+        const int HW = j->H * j->W;
+        const bool median = j->prm.median == 3;
+        WtaArgs a{};
+        a.csum = j->csum;
+        a.off = j->offsets;
+        a.lo = j->lo;
+        a.hi = j->hi;
+        a.hyp = j->hyp;
+        a.d_index = j->d_index;
+        a.disp = median ? j->pre_median : j->disparity;
+        a.HW = HW;
+        const int sb = j->prm.sum_bits == 16 ? 0 : 1;
+        wta[sb].push_back(a);
+        wta_blocks[sb].push_back(blocks_for(HW));
+        if (median) {
+            med.push_back(MedianArgs{j->pre_median, j->disparity, j->H, j->W});
+            med_blocks.push_back(blocks_for(HW));
+        }
+    }
+    hipError_t e = hipSuccess;
+    if (!wta[0].empty()) {
+        e = launch(r, kStWta, wta_subpixel_kernel<Single<WtaArgs>, uint16_t>,
+                   wta_subpixel_kernel<Group<WtaArgs>, uint16_t>, wta[0], wta_blocks[0], kThreads);
+        if (e != hipSuccess) return e;
+    }
+    if (!wta[1].empty()) {
+        e = launch(r, kStWta, wta_subpixel_kernel<Single<WtaArgs>, uint32_t>,
+                   wta_subpixel_kernel<Group<WtaArgs>, uint32_t>, wta[1], wta_blocks[1], kThreads);
+        if (e != hipSuccess) return e;
+    }
+    if (!med.empty())
+        e = launch(r, kStWta, median3_kernel<Single<MedianArgs>>, median3_kernel<Group<MedianArgs>>,
+                   med, med_blocks, kThreads);
+    return e;
 }
 
 }  // namespace lf

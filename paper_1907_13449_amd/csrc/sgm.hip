@@ -13,7 +13,7 @@
 //   - the matching cost of the K hypotheses, read from a cost volume whose row of
 //     the pixel is contiguous (initial stage: the 8-bit Census cost volume, built
 //     once by a popcount kernel; final stage: the CSR volume), with the loads of
-//     the next kDepth steps in flight;
+//     the next D steps in flight (D is a tuning parameter);
 //   - the neighbours k-1 / k+1 of the previous pixel come from the lane's own
 //     registers or, at the lane boundary, from lane l-1 / l+1 by a DPP wave
 //     shift (wave_shr:1 / wave_shl:1);
@@ -113,7 +113,6 @@ __device__ __forceinline__ LineInfo locate(const Lines& L, int H, int W, int g) 
 }
 
 constexpr int kWavesPerBlock = 4;
-constexpr int kDepth = 8;          // steps of input prefetched ahead of the recurrence
 
 // Copies a wave-uniform value into a VGPR that the compiler treats as divergent.
 // Loads addressed through it stay vector-memory loads, which complete in order,
@@ -160,20 +159,28 @@ __device__ __forceinline__ uint32_t lane_min(const uint32_t (&L)[K]) {
 // then writes the tile, which is contiguous in C, with 32-bit stores.
 constexpr int kTilePix = 64;
 
-__global__ __launch_bounds__(256) void census_cost_volume_kernel(SgmDense a,
-                                                                 const float* __restrict__ hyp,
-                                                                 int H, int W, int N, int NP,
-                                                                 uint8_t* __restrict__ cvol) {
-    __shared__ uint32_t tile[kTilePix * LF_MAX_HYPOTHESES / 4];
-    __shared__ int s_sh[LF_MAX_HYPOTHESES];
-    const int z = blockIdx.y;
+struct CcvArgs {
+    const uint64_t* cref;     // [H*W]
+    const uint64_t* cview;    // [nv][H*W]
+    const float* hyp;
+    int cs[4], ct[4];         // s_hat - s, t_hat - t of each cross view
+    int nv, H, W, N, NP;
+    uint32_t tiles;           // pixel tiles per view
+    uint8_t* cvol;            // [nv][H*W][NP]
+};
+
+__device__ __forceinline__ void ccv_block(const CcvArgs& a, uint32_t b, uint32_t* tile,
+                                          int* s_sh) {
+    const int z = (int)(b / a.tiles);
+    const uint32_t t = b - (uint32_t)z * a.tiles;
+    const int H = a.H, W = a.W, N = a.N, NP = a.NP;
     const uint32_t HW = (uint32_t)H * W;
-    const uint32_t p0 = blockIdx.x * kTilePix;
+    const uint32_t p0 = t * kTilePix;
     const int npix = (int)min((uint32_t)kTilePix, HW - p0);
     const bool along_u = a.ct[z] == 0;
     const int cs = along_u ? a.cs[z] : a.ct[z];
     for (int k = threadIdx.x; k < NP; k += 256)
-        s_sh[k] = (int)rintf((float)cs * hyp[min(k, N - 1)]);
+        s_sh[k] = (int)rintf((float)cs * a.hyp[min(k, N - 1)]);
     __syncthreads();
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -190,25 +197,47 @@ __global__ __launch_bounds__(256) void census_cost_volume_kernel(SgmDense a,
     }
     __syncthreads();
     // the tile is npix * NP contiguous bytes of C (NP is a multiple of 4)
-    uint32_t* dst = (uint32_t*)(cvol + ((size_t)z * HW + p0) * NP);
+    uint32_t* dst = (uint32_t*)(a.cvol + ((size_t)z * HW + p0) * NP);
     const int words = npix * NP / 4;
     for (int i = threadIdx.x; i < words; i += 256) dst[i] = tile[i];
 }
 
-// SGM over the Census cost volume, every direction of every view in one launch;
-// blockIdx.y = view.  Output: Lbuf[r][z][p][NP], storage type LT.
-template <int K, typename LT>
-__global__ __launch_bounds__(64 * kWavesPerBlock) void sgm_dense_paths_kernel(
-    const uint8_t* __restrict__ cvol, int nv, Lines lines, int H, int W, int N, int NP,
-    uint32_t P1, uint32_t P2, LT* __restrict__ Lbuf) {
+template <class Src>
+__global__ __launch_bounds__(256) void census_cost_volume_kernel(Src src) {
+    __shared__ uint32_t tile[kTilePix * LF_MAX_HYPOTHESES / 4];
+    __shared__ int s_sh[LF_MAX_HYPOTHESES];
+    for (uint32_t vb = blockIdx.x; vb < src.total; vb += gridDim.x) {
+        uint32_t b;
+        const CcvArgs& a = member(src, vb, b);
+        __syncthreads();                          // LDS of the previous block is read
+        ccv_block(a, b, tile, s_sh);
+    }
+}
+
+// SGM over the Census cost volume, every direction of every view in one launch.
+// Output: Lbuf[r][z][p][NP], storage type LT.
+struct DenseArgs {
+    const uint8_t* cvol;
+    void* Lbuf;
+    Lines lines;
+    int nv, H, W, N, NP;
+    uint32_t P1, P2;
+    uint32_t wblocks;         // blocks per view
+};
+
+template <int K, typename LT, int D>
+__device__ __forceinline__ void dense_wave(const DenseArgs& a, uint32_t b) {
     const int lane = threadIdx.x & 63;
-    const int g = __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6));
-    if (g >= lines.base[lines.npaths]) return;         // wave-uniform exit
-    const int z = blockIdx.y;
-    const LineInfo li = locate(lines, H, W, g);
+    const int z = (int)(b / a.wblocks);
+    const uint32_t wb = b - (uint32_t)z * a.wblocks;
+    const int g = __builtin_amdgcn_readfirstlane(wb * kWavesPerBlock + (threadIdx.x >> 6));
+    if (g >= a.lines.base[a.lines.npaths]) return;        // wave-uniform exit
+    const int H = a.H, W = a.W, N = a.N, NP = a.NP;
+    const uint32_t P1 = a.P1, P2 = a.P2;
+    const LineInfo li = locate(a.lines, H, W, g);
     const uint32_t HW = (uint32_t)H * W;
-    const uint8_t* __restrict__ cz = cvol + (size_t)z * HW * NP;
-    LT* __restrict__ out = Lbuf + ((size_t)li.r * nv + z) * HW * NP;
+    const uint8_t* __restrict__ cz = a.cvol + (size_t)z * HW * NP;
+    LT* __restrict__ out = (LT*)a.Lbuf + ((size_t)li.r * a.nv + z) * HW * NP;
 
     // the lane's K bytes of a pixel row; lanes past N read in-row bytes and add kInf
     const uint32_t lofs = (uint32_t)min(lane * K, NP - K);
@@ -225,21 +254,21 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void sgm_dense_paths_kernel(
         else if constexpr (K == 4) return *(const uint32_t*)(cz + o);
         else return (uint32_t)cz[o] | ((uint32_t)cz[o + 1] << 8) | ((uint32_t)cz[o + 2] << 16);
     };
-    uint32_t cb[kDepth];
+    uint32_t cb[D];
 #pragma unroll
-    for (int i = 0; i < kDepth; ++i) cb[i] = load(i);
+    for (int i = 0; i < D; ++i) cb[i] = load(i);
 
     uint32_t Lp[K], m = 0;
 #pragma unroll
     for (int j = 0; j < K; ++j) Lp[j] = kInf;
-    for (int base = 0; base < li.len; base += kDepth) {
+    for (int base = 0; base < li.len; base += D) {
 #pragma unroll
-        for (int i = 0; i < kDepth; ++i) {
+        for (int i = 0; i < D; ++i) {
             const int step = base + i;           // steps past the line end are computed
             uint32_t C[K];                       // and not stored
 #pragma unroll
             for (int j = 0; j < K; ++j) C[j] = ((cb[i] >> (8 * j)) & 0xFFu) + cinit[j];
-            cb[i] = load(step + kDepth);         // refill the slot just consumed
+            cb[i] = load(step + D);              // refill the slot just consumed
             uint32_t L[K];
             if (step == 0) {
 #pragma unroll
@@ -271,39 +300,66 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void sgm_dense_paths_kernel(
     }
 }
 
+template <class Src, int K, typename LT, int D>
+__global__ __launch_bounds__(64 * kWavesPerBlock) void sgm_dense_paths_kernel(Src src) {
+    for (uint32_t vb = blockIdx.x; vb < src.total; vb += gridDim.x) {
+        uint32_t b;
+        const DenseArgs& a = member(src, vb, b);
+        dense_wave<K, LT, D>(a, b);
+    }
+}
+
 // Sum over directions + WTA (Eq. 9-10) of the initial stage: one wave per pixel,
 // lane l holds hypotheses 2l and 2l+1 (+128 per round); lowest index on ties.
+struct SumWtaArgs {
+    const void* Lbuf;
+    int64_t HW;
+    int nv, N, NP;
+    int16_t* dmap;            // [nv][H*W]
+};
+
 template <typename LT>
-__global__ __launch_bounds__(256) void dense_sum_wta_kernel(const LT* __restrict__ Lbuf,
-                                                            int npaths, int nv, int64_t HW,
-                                                            int N, int NP,
-                                                            int16_t* __restrict__ dmap) {
+__device__ __forceinline__ void sum_wta_block(const SumWtaArgs& a, uint32_t b) {
+    constexpr int kPaths = 8;                                     // the only count accepted
     const int lane = threadIdx.x & 63;
-    const int64_t nwaves = (int64_t)gridDim.x * 4;
-    const size_t dir_stride = (size_t)nv * HW * NP;
-    for (int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); q < nv * HW; q += nwaves) {
-        const LT* base = Lbuf + (size_t)q * NP;        // q = z*HW + p
-        uint32_t key = UINT_MAX;
-        for (int k = 2 * lane; k < N; k += 128) {
-            uint32_t t0 = 0, t1 = 0;
-#pragma unroll 8
-            for (int r = 0; r < npaths; ++r) {
-                const LT* e = base + (size_t)r * dir_stride + k;
-                if constexpr (sizeof(LT) == 1) {
-                    const uint32_t x = *(const uint16_t*)e;
-                    t0 += x & 0xFF;
-                    t1 += x >> 8;
-                } else {
-                    const uint32_t x = *(const uint32_t*)e;
-                    t0 += x & 0xFFFF;
-                    t1 += x >> 16;
-                }
-            }
-            key = min(key, (t0 << 8) | (uint32_t)k);
-            if (k + 1 < N) key = min(key, (t1 << 8) | (uint32_t)(k + 1));
+    const int64_t q = (int64_t)b * 4 + (threadIdx.x >> 6);       // q = z*HW + p
+    if (q >= a.nv * a.HW) return;                                 // wave-uniform
+    const int N = a.N, NP = a.NP;
+    const size_t dir_stride = (size_t)a.nv * a.HW * NP;
+    const LT* __restrict__ base = (const LT*)a.Lbuf + (size_t)q * NP;
+    uint32_t key = UINT_MAX;
+    for (int k = 2 * lane; k < N; k += 128) {
+        uint32_t x[kPaths];                                       // all loads in flight first
+#pragma unroll
+        for (int r = 0; r < kPaths; ++r) {
+            const LT* e = base + (size_t)r * dir_stride + k;
+            if constexpr (sizeof(LT) == 1) x[r] = *(const uint16_t*)e;
+            else x[r] = *(const uint32_t*)e;
         }
-        key = wave_min(key);
-        if (lane == 0) dmap[q] = (int16_t)(key & 0xFF);
+        uint32_t t0 = 0, t1 = 0;
+#pragma unroll
+        for (int r = 0; r < kPaths; ++r) {
+            if constexpr (sizeof(LT) == 1) {
+                t0 += x[r] & 0xFF;
+                t1 += x[r] >> 8;
+            } else {
+                t0 += x[r] & 0xFFFF;
+                t1 += x[r] >> 16;
+            }
+        }
+        key = min(key, (t0 << 8) | (uint32_t)k);
+        if (k + 1 < N) key = min(key, (t1 << 8) | (uint32_t)(k + 1));
+    }
+    key = wave_min(key);
+    if (lane == 0) a.dmap[q] = (int16_t)(key & 0xFF);
+}
+
+template <class Src, typename LT>
+__global__ __launch_bounds__(256) void dense_sum_wta_kernel(Src src) {
+    for (uint32_t vb = blockIdx.x; vb < src.total; vb += gridDim.x) {
+        uint32_t b;
+        const SumWtaArgs& a = member(src, vb, b);
+        sum_wta_block<LT>(a, b);
     }
 }
 
@@ -316,30 +372,51 @@ struct alignas(16) PixMeta {
     int32_t pad;
 };
 
-__global__ __launch_bounds__(256) void pix_meta_kernel(const int64_t* __restrict__ off,
-                                                       const int16_t* __restrict__ lo,
-                                                       const int16_t* __restrict__ hi, int HW,
-                                                       PixMeta* __restrict__ meta) {
-    const int p = blockIdx.x * 256 + threadIdx.x;
-    if (p >= HW) return;
-    PixMeta m;
-    m.base = off[p] - lo[p];
-    m.lohi = (int32_t)((uint16_t)lo[p] | ((uint32_t)(uint16_t)hi[p] << 16));
-    m.pad = 0;
-    meta[p] = m;
+struct MetaArgs {
+    const int64_t* off;
+    const int16_t* lo;
+    const int16_t* hi;
+    PixMeta* meta;
+    int HW;
+};
+
+template <class Src>
+__global__ __launch_bounds__(256) void pix_meta_kernel(Src src) {
+    for (uint32_t vb = blockIdx.x; vb < src.total; vb += gridDim.x) {
+        uint32_t b;
+        const MetaArgs& a = member(src, vb, b);
+        const int p = (int)b * 256 + threadIdx.x;
+        if (p >= a.HW) continue;
+        PixMeta m;
+        m.base = a.off[p] - a.lo[p];
+        m.lohi = (int32_t)((uint16_t)a.lo[p] | ((uint32_t)(uint16_t)a.hi[p] << 16));
+        m.pad = 0;
+        a.meta[p] = m;
+    }
 }
 
-template <int K>
-__global__ __launch_bounds__(64 * kWavesPerBlock) void sgm_bounded_paths_kernel(
-    SgmBounded a, const PixMeta* __restrict__ meta, Lines lines, int H, int W, uint32_t P1,
-    uint32_t P2, size_t dir_stride, uint16_t* __restrict__ Lbuf) {
-    constexpr int kMeta = kDepth, kCost = kDepth / 2;   // two-stage prefetch
+struct BoundedArgs {
+    const uint16_t* cost;
+    const PixMeta* meta;
+    uint16_t* Lbuf;           // [npaths][dir_stride]
+    size_t dir_stride;
+    Lines lines;
+    int H, W;
+    uint32_t P1, P2;
+};
+
+template <int K, int D>
+__device__ __forceinline__ void bounded_wave(const BoundedArgs& a, uint32_t b) {
+    constexpr int kMeta = D, kCost = D / 2;   // two-stage prefetch
     const int lane = threadIdx.x & 63;
-    const int g = __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6));
-    if (g >= lines.base[lines.npaths]) return;
-    const LineInfo li = locate(lines, H, W, g);
+    const int g = __builtin_amdgcn_readfirstlane(b * kWavesPerBlock + (threadIdx.x >> 6));
+    if (g >= a.lines.base[a.lines.npaths]) return;
+    const int H = a.H, W = a.W;
+    const uint32_t P1 = a.P1, P2 = a.P2;
+    const LineInfo li = locate(a.lines, H, W, g);
     const uint16_t* __restrict__ cost = a.cost;
-    uint16_t* __restrict__ out = Lbuf + (size_t)li.r * dir_stride;
+    const PixMeta* __restrict__ meta = a.meta;
+    uint16_t* __restrict__ out = a.Lbuf + (size_t)li.r * a.dir_stride;
 
     auto load_meta = [&](int step) {
         const int u = li.u0 + step * li.du, v = li.v0 + step * li.dv;
@@ -401,63 +478,106 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void sgm_bounded_paths_kernel(
     }
 }
 
-// csum[c] = sum_r Lbuf[r][c] over the cells of the CSR volume.
-template <typename SumT>
-__global__ __launch_bounds__(256) void bounded_sum_kernel(const uint16_t* __restrict__ Lbuf,
-                                                          int npaths, size_t dir_stride,
-                                                          const int64_t* __restrict__ total,
-                                                          SumT* __restrict__ csum) {
-    const int64_t n = *total;
-    for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < n;
-         c += (int64_t)gridDim.x * 256) {
-        uint32_t s = 0;
-        for (int r = 0; r < npaths; ++r) s += Lbuf[(size_t)r * dir_stride + c];
-        csum[c] = (SumT)s;
+template <class Src, int K, int D>
+__global__ __launch_bounds__(64 * kWavesPerBlock) void sgm_bounded_paths_kernel(Src src) {
+    for (uint32_t vb = blockIdx.x; vb < src.total; vb += gridDim.x) {
+        uint32_t b;
+        const BoundedArgs& a = member(src, vb, b);
+        bounded_wave<K, D>(a, b);
     }
 }
 
+// csum[c] = sum_r Lbuf[r][c] over the cells of the CSR volume; each of a light
+// field's nblk workgroups strides over its device-side cell count.
+struct BsumArgs {
+    const uint16_t* Lbuf;     // [8][dir_stride]
+    size_t dir_stride;
+    const int64_t* total;     // device-side cell count
+    void* csum;
+    uint32_t nblk;
+};
+
+template <class Src, typename SumT>
+__global__ __launch_bounds__(256) void bounded_sum_kernel(Src src) {
+    constexpr int kPaths = 8;
+    for (uint32_t vb = blockIdx.x; vb < src.total; vb += gridDim.x) {
+        uint32_t b;
+        const BsumArgs& a = member(src, vb, b);
+        const int64_t n = *a.total;
+        const uint16_t* __restrict__ L = a.Lbuf;
+        SumT* __restrict__ csum = (SumT*)a.csum;
+        for (int64_t c = (int64_t)b * 256 + threadIdx.x; c < n; c += (int64_t)a.nblk * 256) {
+            uint32_t x[kPaths];
+#pragma unroll
+            for (int r = 0; r < kPaths; ++r) x[r] = L[(size_t)r * a.dir_stride + c];
+            uint32_t s = 0;
+#pragma unroll
+            for (int r = 0; r < kPaths; ++r) s += x[r];
+            csum[c] = (SumT)s;
+        }
+    }
+}
+
+// --- host-side dispatch of the kernel variants ---------------------------------
 template <int K, typename LT>
-hipError_t dense_launch(const SgmDense& a, const Lines& lines, int H, int W, int N, int NP, int P1,
-                        int P2, const uint8_t* cvol, void* Lbuf, hipStream_t st) {
-    dim3 grid((lines.base[lines.npaths] + kWavesPerBlock - 1) / kWavesPerBlock, a.nv);
-    hipLaunchKernelGGL((sgm_dense_paths_kernel<K, LT>), grid, dim3(64 * kWavesPerBlock), 0, st,
-                       cvol, a.nv, lines, H, W, N, NP, (uint32_t)P1, (uint32_t)P2, (LT*)Lbuf);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    const int64_t HW = (int64_t)H * W;
-    const int64_t waves = a.nv * HW;
-    const int blocks = (int)std::min<int64_t>((waves + 3) / 4, 8192);
-    hipLaunchKernelGGL((dense_sum_wta_kernel<LT>), dim3(blocks), dim3(256), 0, st,
-                       (const LT*)Lbuf, lines.npaths, a.nv, HW, N, NP, a.dmap);
-    return hipGetLastError();
+hipError_t dense_variant(Runner& r, const std::vector<DenseArgs>& args,
+                         const std::vector<uint32_t>& blocks) {
+    switch (r.tune.dense_depth) {
+        case 4:
+            return launch(r, kStSgmInit, sgm_dense_paths_kernel<Single<DenseArgs>, K, LT, 4>,
+                          sgm_dense_paths_kernel<Group<DenseArgs>, K, LT, 4>, args, blocks,
+                          64 * kWavesPerBlock);
+        case 16:
+            return launch(r, kStSgmInit, sgm_dense_paths_kernel<Single<DenseArgs>, K, LT, 16>,
+                          sgm_dense_paths_kernel<Group<DenseArgs>, K, LT, 16>, args, blocks,
+                          64 * kWavesPerBlock);
+        default:
+            return launch(r, kStSgmInit, sgm_dense_paths_kernel<Single<DenseArgs>, K, LT, 8>,
+                          sgm_dense_paths_kernel<Group<DenseArgs>, K, LT, 8>, args, blocks,
+                          64 * kWavesPerBlock);
+    }
 }
 
 template <typename LT>
-hipError_t dense_dispatch(const SgmDense& a, const Lines& lines, int H, int W, int N, int NP,
-                          int P1, int P2, const uint8_t* cvol, void* Lbuf, hipStream_t st) {
-    switch ((N + 63) / 64) {
-        case 1: return dense_launch<1, LT>(a, lines, H, W, N, NP, P1, P2, cvol, Lbuf, st);
-        case 2: return dense_launch<2, LT>(a, lines, H, W, N, NP, P1, P2, cvol, Lbuf, st);
-        case 3: return dense_launch<3, LT>(a, lines, H, W, N, NP, P1, P2, cvol, Lbuf, st);
-        default: return dense_launch<4, LT>(a, lines, H, W, N, NP, P1, P2, cvol, Lbuf, st);
+hipError_t dense_k(Runner& r, int K, const std::vector<DenseArgs>& args,
+                   const std::vector<uint32_t>& blocks) {
+    switch (K) {
+        case 1: return dense_variant<1, LT>(r, args, blocks);
+        case 2: return dense_variant<2, LT>(r, args, blocks);
+        case 3: return dense_variant<3, LT>(r, args, blocks);
+        default: return dense_variant<4, LT>(r, args, blocks);
     }
 }
 
 template <int K>
-hipError_t bounded_launch(const SgmBounded& a, const PixMeta* meta, const Lines& lines, int H,
-                          int W, int P1, int P2, size_t dir_stride, uint16_t* Lbuf,
-                          hipStream_t st) {
-    dim3 grid((lines.base[lines.npaths] + kWavesPerBlock - 1) / kWavesPerBlock);
-    hipLaunchKernelGGL((sgm_bounded_paths_kernel<K>), grid, dim3(64 * kWavesPerBlock), 0, st, a,
-                       meta, lines, H, W, (uint32_t)P1, (uint32_t)P2, dir_stride, Lbuf);
-    return hipGetLastError();
+hipError_t bounded_variant(Runner& r, const std::vector<BoundedArgs>& args,
+                           const std::vector<uint32_t>& blocks) {
+    if (r.tune.bounded_depth == 4)
+        return launch(r, kStSgmFinal, sgm_bounded_paths_kernel<Single<BoundedArgs>, K, 4>,
+                      sgm_bounded_paths_kernel<Group<BoundedArgs>, K, 4>, args, blocks,
+                      64 * kWavesPerBlock);
+    return launch(r, kStSgmFinal, sgm_bounded_paths_kernel<Single<BoundedArgs>, K, 8>,
+                  sgm_bounded_paths_kernel<Group<BoundedArgs>, K, 8>, args, blocks,
+                  64 * kWavesPerBlock);
 }
+
+hipError_t bounded_k(Runner& r, int K, const std::vector<BoundedArgs>& args,
+                     const std::vector<uint32_t>& blocks) {
+    switch (K) {
+        case 1: return bounded_variant<1>(r, args, blocks);
+        case 2: return bounded_variant<2>(r, args, blocks);
+        case 3: return bounded_variant<3>(r, args, blocks);
+        default: return bounded_variant<4>(r, args, blocks);
+    }
+}
+
+size_t round256(size_t x) { return (x + 255) / 256 * 256; }
+
+uint32_t div_up(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
 
 }  // namespace
 
 int dense_np(int N) { return (N + 3) / 4 * 4; }
-
-static size_t round256(size_t x) { return (x + 255) / 256 * 256; }
 
 size_t sgm_dense_scratch_bytes(int nv, int H, int W, int N, int npaths, int bits, int P2) {
     const size_t lt = bits + P2 <= 255 ? 1 : 2;
@@ -466,53 +586,159 @@ size_t sgm_dense_scratch_bytes(int nv, int H, int W, int N, int npaths, int bits
 }
 
 size_t sgm_bounded_scratch_bytes(int H, int W, int N, int npaths) {
-    const size_t meta = ((size_t)H * W * sizeof(PixMeta) + 255) / 256 * 256;
+    const size_t meta = round256((size_t)H * W * sizeof(PixMeta));
     return meta + (size_t)npaths * H * W * N * sizeof(uint16_t);
 }
 
-hipError_t launch_sgm_dense(const SgmDense& a, const float* hyp, int H, int W, int N, int P1,
-                            int P2, int npaths, int bits, void* scratch, hipStream_t st) {
-    const Lines lines = make_lines(H, W, npaths);
-    const int NP = dense_np(N);
-    uint8_t* cvol = (uint8_t*)scratch;
-    void* Lbuf = (char*)scratch + round256((size_t)a.nv * H * W * NP);
-    const uint32_t tiles = ((uint32_t)H * W + kTilePix - 1) / kTilePix;
-    hipLaunchKernelGGL(census_cost_volume_kernel, dim3(tiles, a.nv), dim3(256), 0, st, a, hyp, H,
-                       W, N, NP, cvol);
-    hipError_t e = hipGetLastError();
+hipError_t stage_sgm_initial(Runner& r, const Jobs& jobs) {
+    std::vector<CcvArgs> ccv;
+    std::vector<uint32_t> ccv_blocks;
+    // variants: K in 1..4 x path-cost storage (8 or 16 bit)
+    std::vector<DenseArgs> dense[4][2];
+    std::vector<uint32_t> dense_blocks[4][2];
+    std::vector<SumWtaArgs> sums[2];
+    std::vector<uint32_t> sum_blocks[2];
+    for (const Job* j : jobs) {
+        const int H = j->H, W = j->W, N = j->N, NP = dense_np(N);
+        const size_t HW = (size_t)H * W;
+        const lf_sgm_params& sp = j->prm.sgm_init;
+        const int bits = j->prm.census.win_h * j->prm.census.win_w - 1;
+        const int lt = bits + sp.P2 <= 255 ? 0 : 1;
+        uint8_t* cvol = (uint8_t*)j->paths;
+        void* Lbuf = (char*)j->paths + round256((size_t)j->nv * HW * NP);
+        const int sh = (j->S - 1) / 2, th = (j->T - 1) / 2;
+
+        CcvArgs c{};
+        c.cref = j->census;
+        c.cview = j->census + HW;
+        c.hyp = j->hyp;
+        for (int i = 0; i < j->nv; ++i) {
+            c.cs[i] = sh - j->st[2 * i];
+            c.ct[i] = th - j->st[2 * i + 1];
+        }
+        c.nv = j->nv;
+        c.H = H;
+        c.W = W;
+        c.N = N;
+        c.NP = NP;
+        c.tiles = div_up(HW, kTilePix);
+        c.cvol = cvol;
+        ccv.push_back(c);
+        ccv_blocks.push_back(c.tiles * j->nv);
+
+        DenseArgs d{};
+        d.cvol = cvol;
+        d.Lbuf = Lbuf;
+        d.lines = make_lines(H, W, sp.npaths);
+        d.nv = j->nv;
+        d.H = H;
+        d.W = W;
+        d.N = N;
+        d.NP = NP;
+        d.P1 = (uint32_t)sp.P1;
+        d.P2 = (uint32_t)sp.P2;
+        d.wblocks = div_up(d.lines.base[d.lines.npaths], kWavesPerBlock);
+        const int K = (N + 63) / 64 - 1;
+        dense[K][lt].push_back(d);
+        dense_blocks[K][lt].push_back(d.wblocks * j->nv);
+
+        SumWtaArgs s{};
+        s.Lbuf = Lbuf;
+        s.HW = (int64_t)HW;
+        s.nv = j->nv;
+        s.N = N;
+        s.NP = NP;
+        s.dmap = j->maps;
+        sums[lt].push_back(s);
+        sum_blocks[lt].push_back(div_up((uint64_t)j->nv * HW, 4));
+    }
+    hipError_t e = launch(r, kStSgmInit, census_cost_volume_kernel<Single<CcvArgs>>,
+                          census_cost_volume_kernel<Group<CcvArgs>>, ccv, ccv_blocks, 256);
     if (e != hipSuccess) return e;
-    if (bits + P2 <= 255)
-        return dense_dispatch<uint8_t>(a, lines, H, W, N, NP, P1, P2, cvol, Lbuf, st);
-    return dense_dispatch<uint16_t>(a, lines, H, W, N, NP, P1, P2, cvol, Lbuf, st);
+    for (int K = 0; K < 4; ++K)
+        for (int lt = 0; lt < 2; ++lt) {
+            if (dense[K][lt].empty()) continue;
+            e = lt == 0 ? dense_k<uint8_t>(r, K + 1, dense[K][lt], dense_blocks[K][lt])
+                        : dense_k<uint16_t>(r, K + 1, dense[K][lt], dense_blocks[K][lt]);
+            if (e != hipSuccess) return e;
+        }
+    constexpr uint32_t kSumGrid = 8192;       // persistent: each workgroup walks pixels
+    if (!sums[0].empty()) {
+        e = launch(r, kStSgmInit, dense_sum_wta_kernel<Single<SumWtaArgs>, uint8_t>,
+                   dense_sum_wta_kernel<Group<SumWtaArgs>, uint8_t>, sums[0], sum_blocks[0], 256,
+                   kSumGrid);
+        if (e != hipSuccess) return e;
+    }
+    if (!sums[1].empty()) {
+        e = launch(r, kStSgmInit, dense_sum_wta_kernel<Single<SumWtaArgs>, uint16_t>,
+                   dense_sum_wta_kernel<Group<SumWtaArgs>, uint16_t>, sums[1], sum_blocks[1],
+                   256, kSumGrid);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
-hipError_t launch_sgm_bounded(const SgmBounded& a, int H, int W, int N, int P1, int P2,
-                              int npaths, void* scratch, hipStream_t st) {
-    const Lines lines = make_lines(H, W, npaths);
-    const size_t dir_stride = (size_t)H * W * N;     // worst-case cells per direction
-    const int HW = H * W;
-    PixMeta* meta = (PixMeta*)scratch;
-    uint16_t* Lbuf = (uint16_t*)((char*)scratch + ((size_t)HW * sizeof(PixMeta) + 255) / 256 * 256);
-    hipLaunchKernelGGL(pix_meta_kernel, dim3((HW + 255) / 256), dim3(256), 0, st, a.off, a.lo, a.hi,
-                       HW, meta);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    switch ((N + 63) / 64) {
-        case 1: e = bounded_launch<1>(a, meta, lines, H, W, P1, P2, dir_stride, Lbuf, st); break;
-        case 2: e = bounded_launch<2>(a, meta, lines, H, W, P1, P2, dir_stride, Lbuf, st); break;
-        case 3: e = bounded_launch<3>(a, meta, lines, H, W, P1, P2, dir_stride, Lbuf, st); break;
-        default: e = bounded_launch<4>(a, meta, lines, H, W, P1, P2, dir_stride, Lbuf, st); break;
+hipError_t stage_sgm_final(Runner& r, const Jobs& jobs) {
+    std::vector<MetaArgs> meta;
+    std::vector<uint32_t> meta_blocks;
+    std::vector<BoundedArgs> paths[4];
+    std::vector<uint32_t> path_blocks[4];
+    std::vector<BsumArgs> sums[2];
+    std::vector<uint32_t> sum_blocks[2];
+    for (const Job* j : jobs) {
+        const int H = j->H, W = j->W, N = j->N;
+        const size_t HW = (size_t)H * W;
+        const lf_sgm_params& sp = j->prm.sgm_final;
+        PixMeta* pm = (PixMeta*)j->sgm_ws;
+        uint16_t* Lbuf = (uint16_t*)((char*)j->sgm_ws + round256(HW * sizeof(PixMeta)));
+        const size_t dir_stride = HW * N;          // worst-case cells per direction
+
+        meta.push_back(MetaArgs{j->offsets, j->lo, j->hi, pm, (int)HW});
+        meta_blocks.push_back(div_up(HW, 256));
+
+        BoundedArgs b{};
+        b.cost = j->cost;
+        b.meta = pm;
+        b.Lbuf = Lbuf;
+        b.dir_stride = dir_stride;
+        b.lines = make_lines(H, W, sp.npaths);
+        b.H = H;
+        b.W = W;
+        b.P1 = (uint32_t)sp.P1;
+        b.P2 = (uint32_t)sp.P2;
+        const int K = (N + 63) / 64 - 1;
+        paths[K].push_back(b);
+        path_blocks[K].push_back(div_up(b.lines.base[b.lines.npaths], kWavesPerBlock));
+
+        BsumArgs s{};
+        s.Lbuf = Lbuf;
+        s.dir_stride = dir_stride;
+        s.total = j->offsets + HW;
+        s.csum = j->csum;
+        s.nblk = std::min<uint32_t>(2048, std::max<uint32_t>(1, div_up(dir_stride, 4096)));
+        const int sb = j->prm.sum_bits == 16 ? 0 : 1;
+        sums[sb].push_back(s);
+        sum_blocks[sb].push_back(s.nblk);
     }
+    hipError_t e = launch(r, kStSgmFinal, pix_meta_kernel<Single<MetaArgs>>,
+                          pix_meta_kernel<Group<MetaArgs>>, meta, meta_blocks, 256);
     if (e != hipSuccess) return e;
-    const int blocks = 2048;
-    const int64_t* total = a.off + (int64_t)H * W;
-    if (a.sum_bits == 16)
-        hipLaunchKernelGGL(bounded_sum_kernel<uint16_t>, dim3(blocks), dim3(256), 0, st, Lbuf,
-                           npaths, dir_stride, total, (uint16_t*)a.csum);
-    else
-        hipLaunchKernelGGL(bounded_sum_kernel<uint32_t>, dim3(blocks), dim3(256), 0, st, Lbuf,
-                           npaths, dir_stride, total, (uint32_t*)a.csum);
-    return hipGetLastError();
+    for (int K = 0; K < 4; ++K) {
+        if (paths[K].empty()) continue;
+        e = bounded_k(r, K + 1, paths[K], path_blocks[K]);
+        if (e != hipSuccess) return e;
+    }
+    if (!sums[0].empty()) {
+        e = launch(r, kStSgmFinal, bounded_sum_kernel<Single<BsumArgs>, uint16_t>,
+                   bounded_sum_kernel<Group<BsumArgs>, uint16_t>, sums[0], sum_blocks[0], 256);
+        if (e != hipSuccess) return e;
+    }
+    if (!sums[1].empty()) {
+        e = launch(r, kStSgmFinal, bounded_sum_kernel<Single<BsumArgs>, uint32_t>,
+                   bounded_sum_kernel<Group<BsumArgs>, uint32_t>, sums[1], sum_blocks[1], 256);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace lf

@@ -17,6 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblf.so")
 
 LF_OK, LF_EINVAL, LF_ENOSPACE, LF_EDEVICE, LF_EUNSUPPORTED = 0, -1, -2, -3, -4
+LF_EBUSY, LF_ETIMEOUT, LF_ECANCELED = -5, -6, -7
 LF_U8, LF_F32 = 0, 1
 LF_COST_L2, LF_COST_CENSUS = 0, 1
 
@@ -27,6 +28,10 @@ EXPORTS = (
     "lf_sgm_aggregate",
     "lf_wta_workspace_size", "lf_wta_subpixel", "lf_depth_workspace_size", "lf_depth",
     "lf_profile_enable", "lf_profile_read", "lf_profile_stage_name",
+    "lf_batch_workspace_size", "lf_plan_create", "lf_plan_autotune", "lf_plan_capture",
+    "lf_plan_run", "lf_plan_launches", "lf_plan_tuning", "lf_plan_destroy",
+    "lf_server_create", "lf_server_submit", "lf_server_wait", "lf_server_stats",
+    "lf_server_destroy",
 )
 
 
@@ -56,6 +61,33 @@ class Params(C.Structure):
                 ("median", C.c_int32), ("sum_bits", C.c_int32)]
 
 
+class Request(C.Structure):
+    _fields_ = [("views", ViewSet), ("hyp", C.c_void_p), ("N", C.c_int32), ("params", Params),
+                ("disparity", C.c_void_p), ("d_index", C.c_void_p)]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("cost_cells_per_thread", C.c_int32), ("cost_stride", C.c_int32),
+                ("dense_prefetch", C.c_int32), ("bounded_prefetch", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ServerConfig(C.Structure):
+    _fields_ = [("arena", C.c_void_p), ("arena_bytes", C.c_size_t), ("max_batch", C.c_int32),
+                ("max_inflight", C.c_int32), ("max_queue", C.c_int32), ("tuning", Tuning)]
+
+
+class RequestInfo(C.Structure):
+    _fields_ = [("t_submit", C.c_double), ("t_admit", C.c_double), ("t_launch", C.c_double),
+                ("t_done", C.c_double), ("batch", C.c_int64), ("batch_size", C.c_int32),
+                ("status", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"liblf.so not built ({LIB_PATH}); run python -m paper_1907_13449_amd.build")
@@ -83,6 +115,23 @@ def _load():
     lib.lf_profile_read.argtypes = [P, P, i32]
     lib.lf_profile_stage_name.argtypes = [i32]
     lib.lf_profile_stage_name.restype = C.c_char_p
+    lib.lf_batch_workspace_size.argtypes = [P, i32]
+    lib.lf_batch_workspace_size.restype = sz
+    lib.lf_plan_create.argtypes = [P, i32, P, sz, P, P, P]
+    lib.lf_plan_autotune.argtypes = [P, P, i32, P]
+    lib.lf_plan_capture.argtypes = [P]
+    lib.lf_plan_run.argtypes = [P, P]
+    lib.lf_plan_launches.argtypes = [P]
+    lib.lf_plan_tuning.argtypes = [P, P]
+    lib.lf_plan_destroy.argtypes = [P]
+    lib.lf_plan_destroy.restype = None
+    lib.lf_server_create.argtypes = [P, P]
+    lib.lf_server_submit.argtypes = [P, P, P]
+    lib.lf_server_wait.argtypes = [P, i64, C.c_double, P]
+    lib.lf_server_stats.argtypes = [P, P, P, P, P]
+    lib.lf_server_stats.restype = None
+    lib.lf_server_destroy.argtypes = [P]
+    lib.lf_server_destroy.restype = None
     return lib
 
 
@@ -282,3 +331,135 @@ def lf_depth(views: torch.Tensor, hyp: torch.Tensor, params: dict, ws=None, out=
     _check(lib.lf_depth(C.byref(vs), _ptr(hyp), N, C.byref(prm), _ptr(out), _ptr(d_index),
                         _ptr(ws), ws.numel(), _stream(stream)))
     return out
+
+
+# ------------------------------------------------------------------ batches
+def make_request(views: torch.Tensor, hyp: torch.Tensor, params: dict, disparity: torch.Tensor,
+                 d_index=None) -> Request:
+    _dev(hyp, torch.float32, "hyp")
+    _dev(disparity, torch.float32, "disparity")
+    if d_index is not None:
+        _dev(d_index, torch.int16, "d_index")
+    return Request(view_set(views), hyp.data_ptr(), hyp.shape[0], make_params(params),
+                   disparity.data_ptr(), 0 if d_index is None else d_index.data_ptr())
+
+
+def _requests(reqs):
+    arr = (Request * len(reqs))(*reqs)
+    return arr
+
+
+def batch_workspace_bytes(reqs) -> int:
+    arr = _requests(reqs)
+    return lib.lf_batch_workspace_size(arr, len(reqs))
+
+
+def make_tuning(t: dict | None) -> Tuning | None:
+    if t is None:
+        return None
+    return Tuning(t.get("cost_cells_per_thread", 0), t.get("cost_stride", 0),
+                  t.get("dense_prefetch", 0), t.get("bounded_prefetch", 0))
+
+
+class Plan:
+    """A batch of light fields run together (lf_plan_*).  Keeps the request
+    tensors and the workspace alive while the plan exists."""
+
+    def __init__(self, items, ws=None, tuning: dict | None = None, stream=None):
+        # items: sequence of (views, hyp, params, disparity, d_index or None)
+        self._keep = list(items)
+        reqs = [make_request(*it) for it in self._keep]
+        self._arr = _requests(reqs)
+        self.n = len(reqs)
+        need = lib.lf_batch_workspace_size(self._arr, self.n)
+        if need == 0:
+            raise LFError(LF_EINVAL, "invalid batch")
+        dev = self._keep[0][0].device
+        self.ws = ws if ws is not None else workspace(need, dev)
+        self._h = C.c_void_p()
+        t = make_tuning(tuning)
+        _check(lib.lf_plan_create(self._arr, self.n, _ptr(self.ws), self.ws.numel(),
+                                  None if t is None else C.byref(t), _stream(stream),
+                                  C.byref(self._h)))
+
+    def autotune(self, reps: int = 2, stream=None) -> dict:
+        t = Tuning()
+        _check(lib.lf_plan_autotune(self._h, _stream(stream), reps, C.byref(t)))
+        return t.as_dict()
+
+    def capture(self):
+        _check(lib.lf_plan_capture(self._h))
+
+    def run(self, stream=None):
+        _check(lib.lf_plan_run(self._h, _stream(stream)))
+
+    @property
+    def launches(self) -> int:
+        return lib.lf_plan_launches(self._h)
+
+    @property
+    def tuning(self) -> dict:
+        t = Tuning()
+        _check(lib.lf_plan_tuning(self._h, C.byref(t)))
+        return t.as_dict()
+
+    def close(self):
+        if self._h:
+            lib.lf_plan_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """The request loop (lf_server_*) over a device arena of `arena_bytes`."""
+
+    def __init__(self, arena_bytes: int, device, max_batch=16, max_inflight=2, max_queue=1024,
+                 tuning: dict | None = None, arena=None):
+        self.arena = arena if arena is not None else workspace(arena_bytes, device)
+        t = make_tuning(tuning) or Tuning()
+        cfg = ServerConfig(self.arena.data_ptr(), self.arena.numel(), max_batch, max_inflight,
+                           max_queue, t)
+        self._h = C.c_void_p()
+        _check(lib.lf_server_create(C.byref(cfg), C.byref(self._h)))
+        self._keep = {}
+
+    def submit(self, views, hyp, params, disparity, d_index=None) -> int:
+        req = make_request(views, hyp, params, disparity, d_index)
+        tk = C.c_int64()
+        _check(lib.lf_server_submit(self._h, C.byref(req), C.byref(tk)))
+        self._keep[tk.value] = (views, hyp, disparity, d_index)
+        return tk.value
+
+    def wait(self, ticket: int, timeout: float = -1.0) -> dict:
+        info = RequestInfo()
+        st = lib.lf_server_wait(self._h, ticket, timeout, C.byref(info))
+        if st == LF_ETIMEOUT:
+            raise TimeoutError(f"ticket {ticket} still running")
+        self._keep.pop(ticket, None)
+        d = info.as_dict()
+        if st != LF_OK:
+            d["error"] = lib.lf_last_error().decode()
+        return d
+
+    def stats(self) -> dict:
+        v = [C.c_int64() for _ in range(4)]
+        lib.lf_server_stats(self._h, *[C.byref(x) for x in v])
+        return dict(completed=v[0].value, batches=v[1].value, arena_in_use=v[2].value,
+                    arena_peak=v[3].value)
+
+    def close(self):
+        if self._h:
+            lib.lf_server_destroy(self._h)
+            self._h = C.c_void_p()
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

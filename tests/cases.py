@@ -1,0 +1,58 @@
+"""Seeded light fields shared by the GPU tests: shapes, dtypes, hypothesis counts
+and parameters chosen to reach every kernel variant and edge case (ragged
+tiles, N at the lane boundaries and at its maximum, 3-D light fields, one-row
+and one-column images, 16-bit path costs, the Census cost kind)."""
+import numpy as np
+
+import lfsynth
+
+
+def case(name):
+    if name == "small":                      # 5x5 x 96^2 u8, N=32
+        return lfsynth.workload("small")
+    if name == "f32_ragged":                 # 7x7 x 70x83 f32, N=100 (K=2 with a tail)
+        return lfsynth.workload("paper_s", H=70, W=83, S=7, T=7, N=100)
+    if name == "u8_n65":                     # N=65: one hypothesis in the last lane pair
+        lf = lfsynth.workload("paper_s", seed=7, H=33, W=47, S=5, T=5, N=65)
+        lf.views = np.clip(np.rint(lf.views * 255.0), 0, 255).astype(np.uint8)
+        lf.params.update(alpha=1.0, edge_tau=60.0)
+        return lf
+    if name == "n256":                       # N = 256, the maximum (K = 4)
+        lf = lfsynth.workload("paper_s", seed=8, H=24, W=31, S=3, T=3, N=256)
+        lf.params.update(win_h=5, win_w=5, sum_bits=32)
+        return lf
+    if name == "stage_1x11":                 # horizontal 3-D light field, |V| = 2
+        sc = lfsynth.slanted_scene(9, 40, 120, 0.0, 6.0, S=11, T=1)
+        v, gt = lfsynth.render(sc, 11, 1)
+        v = np.clip(np.rint(v * 255.0), 0, 255).astype(np.uint8)
+        p = lfsynth._params(census=(7, 9), p_init=(21, 45), p_final=(17, 35), lam=3,
+                            edge_tau=128.0, alpha=1.0, sum_bits=32)
+        return lfsynth.LightField(v, lfsynth.hypotheses(0.0, 6.0, 48), gt, p)
+    if name == "col_7x1":                    # vertical 3-D light field
+        sc = lfsynth.slanted_scene(10, 90, 20, -2.0, 2.0, S=1, T=7)
+        v, gt = lfsynth.render(sc, 1, 7)
+        return lfsynth.LightField(v, lfsynth.hypotheses(-2.0, 2.0, 20), gt,
+                                  lfsynth._params(alpha=255.0, lam=1, fill=1, sum_bits=16))
+    if name == "one_row":                    # H = 1: every diagonal line has one pixel
+        lf = lfsynth.workload("paper_s", seed=11, H=1, W=64, S=3, T=3, N=12)
+        lf.params.update(win_h=3, win_w=3, lam=0, fill=0)
+        return lf
+    if name == "one_col":
+        lf = lfsynth.workload("paper_s", seed=12, H=50, W=1, S=3, T=3, N=9)
+        lf.params.update(win_h=3, win_w=3, median=0, fill=3)
+        return lf
+    if name == "u16_paths":                  # bits + P2 > 255: 16-bit path-cost storage
+        lf = lfsynth.workload("paper_s", seed=14, H=37, W=45, S=5, T=5, N=70)
+        lf.params.update(P1_init=60, P2_init=250)
+        return lf
+    if name == "census_cost":                # Eq. (15) as the final cost
+        lf = lfsynth.workload("paper_s", seed=13, H=40, W=52, S=5, T=5, N=24)
+        lf.params.update(cost_kind=1, win_h=5, win_w=5, sum_bits=16)
+        return lf
+    raise KeyError(name)
+
+
+CASES = ["small", "f32_ragged", "u8_n65", "n256", "stage_1x11", "col_7x1", "one_row", "one_col",
+         "u16_paths", "census_cost"]
+
+

@@ -35,7 +35,7 @@ def test_library_exports_every_declared_symbol(lf):
     for name in declared_functions():
         assert hasattr(lf.lib, name), name
     assert set(declared_functions()) == set(lf.EXPORTS)
-    assert lf.lib.lf_abi_version() == 1
+    assert lf.lib.lf_abi_version() == 2
 
 
 def test_struct_layouts_match_header(lf):
