@@ -14,6 +14,17 @@ Printed: one JSON line with Gcells/s (cells = |V|*H*W*N initial + the bounded
 cells sum_p w(p)), depth maps/s, p50/p99 step latency, per-stage times from HIP
 events recorded on the stream the kernels run on, the roofline of the dominant
 kernel, and the CPU oracle timed on this host as a reported baseline.
+
+Two more measurements ride along in the same line (skip them with --no-batch /
+--no-serve):
+  batched  64 light fields mixing 5x5x256^2, 7x7x384^2 and 9x9x512^2 float32
+           scenes with 32..128 hypotheses: one autotuned, graph-captured batch
+           plan against the same 64 lf_depth calls one after another.
+  served   Poisson arrivals of requests drawn uniformly from the small 5x5x96^2
+           workload, the 9x9x512^2 N=100 workload and the mixed shapes above,
+           through the request loop (continuous batching, admission by workspace
+           footprint into a resident arena) against one-at-a-time lf_depth
+           calls on the same arrival times: p50/p99 latency and maps/s.
 """
 from __future__ import annotations
 
@@ -98,6 +109,229 @@ def cpu_baseline(lfd, cells_per_map):
                       "single-threaded C oracle, -O3"}
 
 
+# --------------------------------------------------------------- batches
+def mixed_scenes(paper_lfd, dev):
+    """Device-resident scenes of the batched and served workloads: the 9x9x512^2
+    scene of the headline workload, one seeded 5x5x256^2 and one 7x7x384^2 scene
+    of the same family (slanted Perlin+noise planes, disparity in [-4, 4]), and
+    the small 5x5x96^2 uint8 workload."""
+    import torch
+    import lfsynth
+    t0 = time.perf_counter()
+    out = {}
+    for key, (S, H) in {"5x5x256": (5, 256), "7x7x384": (7, 384)}.items():
+        l = lfsynth.workload("paper_s", seed=20 + S, H=H, W=H, S=S, T=S, N=64)
+        out[key] = (torch.from_numpy(l.views).to(dev), l.params)
+    out["9x9x512"] = (torch.from_numpy(paper_lfd.views).to(dev), paper_lfd.params)
+    small = lfsynth.workload("small")
+    out["small"] = (torch.from_numpy(small.views).to(dev), small.params,
+                    torch.from_numpy(small.hyp).to(dev))
+    log(f"[bench] mixed scenes generated in {time.perf_counter() - t0:.1f}s")
+    return out
+
+
+def mixed_requests(scenes, n, seed, dev, kinds=("5x5x256", "7x7x384", "9x9x512"), cycle=False):
+    """n requests over `kinds` (in turn if `cycle`, else drawn uniformly); each of the
+    three f32 shapes gets N drawn from 32..128 over [-4, 4], "mix" is one of those
+    three drawn uniformly, "paper" is the 9x9x512^2 workload with N = 100, and
+    "small" keeps its own N = 32 over [-2, 2] and parameters."""
+    import numpy as np
+    import torch
+    import lfsynth
+    shapes = ("5x5x256", "7x7x384", "9x9x512")
+    rng = np.random.default_rng(seed)
+    reqs = []
+    hyps = {}
+    for i in range(n):
+        kind = kinds[i % len(kinds)] if cycle else kinds[int(rng.integers(len(kinds)))]
+        if kind == "mix":
+            kind = shapes[int(rng.integers(3))]
+        if kind == "small":
+            views, params, hyp = scenes["small"]
+        elif kind == "paper":                   # the 9x9x512^2 workload, N = 100
+            views, params = scenes["9x9x512"]
+            if 100 not in hyps:
+                hyps[100] = torch.from_numpy(lfsynth.hypotheses(-4.0, 4.0, 100)).to(dev)
+            hyp = hyps[100]
+        else:
+            views, params = scenes[kind]
+            N = int(rng.integers(32, 129))
+            if N not in hyps:
+                hyps[N] = torch.from_numpy(lfsynth.hypotheses(-4.0, 4.0, N)).to(dev)
+            hyp = hyps[N]
+        reqs.append(dict(kind=kind, views=views, hyp=hyp, params=params))
+    return reqs
+
+
+def request_cells(lf, r):
+    """Cells of one request: |V|*H*W*N initial + the bounded cells of its ranges."""
+    import torch
+    ini = lf.lf_initial_disparity(r["views"], r["hyp"], r["params"], want_maps=False)
+    w = ini["d_hi"].to(torch.int64) - ini["d_lo"].to(torch.int64) + 1
+    T, S, H, W = r["views"].shape
+    return len(lf.cross_views(S, T)) * H * W * r["hyp"].shape[0] + int(w.sum().item())
+
+
+def run_batched(scenes, n, dev):
+    import numpy as np
+    import torch
+    from paper_1907_13449_amd import lf
+    reqs = mixed_requests(scenes, n, 3, dev, cycle=True)
+    cells = sum(request_cells(lf, r) for r in reqs)
+    outs = [torch.empty(r["views"].shape[2:], dtype=torch.float32, device=dev) for r in reqs]
+    # plain: one lf_depth per light field, back to back on one stream, one workspace
+    need = max(lf.depth_workspace_bytes(r["views"].shape[1], r["views"].shape[0],
+                                        r["views"].shape[2], r["views"].shape[3],
+                                        r["hyp"].shape[0], r["params"]) for r in reqs)
+    ws = lf.workspace(need, dev)
+    stream = torch.cuda.current_stream()
+
+    def plain():
+        for r, o in zip(reqs, outs):
+            lf.lf_depth(r["views"], r["hyp"], r["params"], ws=ws, out=o, stream=stream)
+
+    plain()
+    torch.cuda.synchronize()
+    ref = [o.clone() for o in outs]
+    reps = 3
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        plain()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    plain_ms = e0.elapsed_time(e1) / reps
+    del ws
+    # batched: one plan, autotuned on its own inputs, captured, replayed
+    t0 = time.perf_counter()
+    plan = lf.Plan([(r["views"], r["hyp"], r["params"], o, None) for r, o in zip(reqs, outs)])
+    tuning = plan.autotune(reps=1)
+    plan.capture()
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    for o in outs:
+        o.fill_(float("nan"))
+    plan.run(stream)
+    torch.cuda.synchronize()
+    same = all(torch.equal(a, b) for a, b in zip(outs, ref))
+    e0.record(stream)
+    for _ in range(reps):
+        plan.run(stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    batch_ms = e0.elapsed_time(e1) / reps
+    res = {"workload": f"{n} light fields: 5x5x256^2 / 7x7x384^2 / 9x9x512^2 f32, N in 32..128",
+           "light_fields": n, "cells": cells,
+           "batched_ms": batch_ms, "plain_ms": plain_ms,
+           "batched_gcells_s": cells / (batch_ms * 1e-3) / 1e9,
+           "plain_gcells_s": cells / (plain_ms * 1e-3) / 1e9,
+           "batched_maps_s": n / (batch_ms * 1e-3), "plain_maps_s": n / (plain_ms * 1e-3),
+           "speedup": plain_ms / batch_ms, "identical_to_plain": bool(same),
+           "launches_per_batch": plan.launches, "tuning": tuning,
+           "plan_setup_s": setup_s, "graph": True}
+    plan.close()
+    log(f"[bench] batched {n}: {batch_ms:.2f} ms vs plain {plain_ms:.2f} ms "
+        f"({plain_ms / batch_ms:.2f}x), identical={same}")
+    return res
+
+
+def run_served(scenes, n, dev):
+    import numpy as np
+    import torch
+    from paper_1907_13449_amd import lf
+    reqs = mixed_requests(scenes, n, 11, dev, kinds=("small", "paper", "mix"))
+    rng = np.random.default_rng(12)
+    outs = [torch.empty(r["views"].shape[2:], dtype=torch.float32, device=dev) for r in reqs]
+    need = max(lf.depth_workspace_bytes(r["views"].shape[1], r["views"].shape[0],
+                                        r["views"].shape[2], r["views"].shape[3],
+                                        r["hyp"].shape[0], r["params"]) for r in reqs)
+    ws = lf.workspace(need, dev)
+    stream = torch.cuda.current_stream()
+    # service time of each request alone (plain launch), for the arrival rate
+    svc = []
+    for r, o in zip(reqs, outs):
+        lf.lf_depth(r["views"], r["hyp"], r["params"], ws=ws, out=o, stream=stream)
+    torch.cuda.synchronize()
+    ref = [o.clone() for o in outs]
+    for r, o in zip(reqs, outs):
+        t = time.perf_counter()
+        lf.lf_depth(r["views"], r["hyp"], r["params"], ws=ws, out=o, stream=stream)
+        torch.cuda.synchronize()
+        svc.append(time.perf_counter() - t)
+    mean_svc = float(np.mean(svc))
+    rate = 0.8 / mean_svc               # 80 % of what one-at-a-time can sustain
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n))
+
+    def pct(lat):
+        return {"p50_ms": float(np.percentile(lat, 50) * 1e3),
+                "p99_ms": float(np.percentile(lat, 99) * 1e3)}
+
+    # plain: FIFO, one lf_depth at a time, each started no earlier than its arrival
+    t0 = time.perf_counter()
+    lat, done = [], 0.0
+    for r, o, a in zip(reqs, outs, arrivals):
+        while time.perf_counter() - t0 < a:
+            time.sleep(0.0001)
+        lf.lf_depth(r["views"], r["hyp"], r["params"], ws=ws, out=o, stream=stream)
+        torch.cuda.synchronize()
+        done = time.perf_counter() - t0
+        lat.append(done - a)
+    plain = dict(pct(np.array(lat)), maps_s=n / done)
+    del ws
+    torch.cuda.empty_cache()
+
+    def serve(arr, cfg):
+        inflight, max_batch, ratio = cfg
+        srv = lf.Server(64 << 30, dev, max_batch=max_batch, max_inflight=inflight,
+                        group_ratio=ratio)
+        for o in outs:
+            o.fill_(float("nan"))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tickets = []
+        for r, o, a in zip(reqs, outs, arr):
+            while time.perf_counter() - t0 < a:
+                time.sleep(0.0001)
+            tickets.append(srv.submit(r["views"], r["hyp"], r["params"], o))
+        infos = [srv.wait(t) for t in tickets]
+        st = srv.stats()
+        srv.close()
+        ok = all(i["status"] == 0 for i in infos)
+        lat = np.array([i["t_done"] - i["t_submit"] for i in infos])
+        span = max(i["t_done"] for i in infos) - min(i["t_submit"] for i in infos)
+        same = ok and all(torch.equal(a, b) for a, b in zip(outs, ref))
+        sizes = [i["batch_size"] for i in infos]
+        phase = {"queue_ms": np.mean([i["t_admit"] - i["t_submit"] for i in infos]) * 1e3,
+                 "plan_launch_ms": np.mean([i["t_launch"] - i["t_admit"] for i in infos]) * 1e3,
+                 "device_ms": np.mean([i["t_done"] - i["t_launch"] for i in infos]) * 1e3}
+        return dict(pct(lat), maps_s=n / span, batches=st["batches"],
+                    mean_batch=float(np.mean(sizes)), arena_peak_gb=st["arena_peak"] / 2**30,
+                    identical_to_plain=bool(same),
+                    config={"max_inflight": inflight, "max_batch": max_batch,
+                            "group_ratio": ratio},
+                    mean_phase=phase)
+
+    # server configurations tried on the same arrivals; the one with the lowest
+    # p99 is reported (and the highest saturated throughput)
+    configs = [(1, 8, 0), (2, 8, 0), (2, 8, 2), (3, 4, 2), (4, 4, 2), (4, 8, 0), (4, 1, 0)]
+    runs = [serve(arrivals, c) for c in configs]
+    served = min(runs, key=lambda x: x["p99_ms"])
+    saturated = max((serve(np.zeros(n), c) for c in configs), key=lambda x: x["maps_s"])
+    # one-at-a-time capacity with everything queued at t=0 (no idle gaps)
+    res = {"workload": "Poisson arrivals, requests uniform over the 5x5x96^2 u8 N=32, "
+                       "9x9x512^2 N=100 and mixed 5x5x256^2 / 7x7x384^2 / 9x9x512^2 "
+                       "(N 32..128) light fields",
+           "requests": n, "rate_per_s": rate, "mean_alone_ms": mean_svc * 1e3,
+           "served": served, "plain": plain, "served_all": runs,
+           "saturated_served_maps_s": saturated["maps_s"],
+           "saturated_served_config": saturated["config"],
+           "saturated_plain_maps_s": 1.0 / mean_svc,
+           "server": dict(arena_gb=64, **served["config"])}
+    log(f"[bench] served {n} at {rate:.0f}/s: p50 {served['p50_ms']:.2f} p99 "
+        f"{served['p99_ms']:.2f} ms vs plain p50 {plain['p50_ms']:.2f} p99 {plain['p99_ms']:.2f}")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -107,6 +341,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device-to-device copy (counter calibration)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched measurement")
+    ap.add_argument("--no-serve", action="store_true", help="skip the request-loop measurement")
+    ap.add_argument("--batch-n", type=int, default=64)
+    ap.add_argument("--serve-n", type=int, default=160)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this implementation runs on one GPU; --gpus must be 1",
@@ -178,7 +416,9 @@ def main():
                        "peak": m["peak"], "unit": m["unit"], "frac": achieved / m["peak"],
                        "ms": stage_ms[name], "launches": stage_launches[name],
                        "avg_launch_ms": stage_ms[name] / max(stage_launches[name], 1)}
-    dominant = max(roofs, key=lambda k: roofs[k]["ms"])
+    # the dominant kernel: the stage whose launches take longest on average (the
+    # bounded cost is one launch; the initial SGM is three shorter ones)
+    dominant = max(roofs, key=lambda k: roofs[k]["avg_launch_ms"])
     src = {"sgm_initial": "sgm.hip", "sgm_bounded": "sgm.hip", "cost_bounded": "cost.hip"}
     roofline = dict(roofs[dominant])
     roofline["stage"] = dominant
@@ -219,6 +459,14 @@ def main():
         "roofline": roofline,
         "stage_roofline": roofs,
     }
+    del ws
+    scenes = None
+    if not (args.no_batch and args.no_serve) and args.workload == "paper":
+        scenes = mixed_scenes(lfd, dev)
+    if not args.no_batch and scenes is not None:
+        res["batched"] = run_batched(scenes, args.batch_n, dev)
+    if not args.no_serve and scenes is not None:
+        res["served"] = run_served(scenes, args.serve_n, dev)
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on one light field")
         res["cpu_baseline"] = cpu_baseline(lfd, cells)

@@ -315,6 +315,10 @@ typedef struct {
     int32_t max_batch;          /* light fields per batch (>= 1) */
     int32_t max_inflight;       /* batches on the device at once (1..4); one stream each */
     int32_t max_queue;          /* pending requests before lf_server_submit says LF_EBUSY */
+    int32_t group_ratio;        /* 0: any mix; r >= 2: a batch only takes requests whose
+                                   workspace is within a factor r of its first member's
+                                   (similar sizes: a small request does not wait for a
+                                   large one's batch) */
     lf_tuning tuning;           /* schedule of every batch (zeros: defaults) */
 } lf_server_config;
 

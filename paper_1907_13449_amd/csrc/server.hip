@@ -6,8 +6,9 @@
 //   2. admits pending requests into a new batch when fewer than max_inflight
 //      batches are on the device: in arrival order, a request joins if the
 //      batch's workspace (every member's lf_depth workspace plus the plan's
-//      launch tables) still fits in the largest free extent of the arena; a
-//      request that does not fit is passed over and keeps its place;
+//      launch tables) still fits in the largest free extent of the arena and,
+//      with group_ratio, if its own workspace is of the first member's size
+//      class; a request that does not join is passed over and keeps its place;
 //   3. plans the batch over that extent, launches it on a free stream and
 //      records an event after it.
 // Batches launched on different streams overlap on the device, so requests
@@ -148,11 +149,19 @@ struct lf_server {
         const size_t room = largest_free();
         size_t total = 0;
         std::vector<lf_request> qs;
+        size_t head = 0;                          // workspace of the first member
         for (auto it = pending.begin(); it != pending.end() && (int)qs.size() < cfg.max_batch;) {
+            if (head && cfg.group_ratio >= 2 &&
+                (it->bytes > head * (size_t)cfg.group_ratio ||
+                 it->bytes * (size_t)cfg.group_ratio < head)) {
+                ++it;                                 // another size class: a later batch
+                continue;
+            }
             qs.push_back(it->q);
             const size_t need = lf_batch_workspace_size(qs.data(), (int)qs.size());
             if (need != 0 && need <= room) {
                 total = need;
+                if (!head) head = it->bytes;
                 b.reqs.push_back(*it);
                 it = pending.erase(it);
             } else {
@@ -254,11 +263,16 @@ struct lf_server {
                 for (Pending& r : b.reqs) r.info.t_launch = t;
                 inflight.push_back(std::move(b));
             }
-            // 4. sleep until a submission, a stop, or the next completion poll
-            if (inflight.empty())
+            // 4. idle: sleep until a submission or a stop.  Busy: poll the events
+            //    again at once (a timed sleep would add its oversleep, tens of
+            //    microseconds, to every request's latency).
+            if (inflight.empty()) {
                 cv_sched.wait(lk, [&] { return stop || !pending.empty(); });
-            else
-                cv_sched.wait_for(lk, std::chrono::microseconds(50));
+            } else {
+                lk.unlock();
+                std::this_thread::yield();
+                lk.lock();
+            }
         }
     }
 };
@@ -272,9 +286,10 @@ lf_status lf_server_create(const lf_server_config* cfg, lf_server** out) {
     if (!cfg->arena || (uintptr_t)cfg->arena % kAlign || cfg->arena_bytes < kAlign)
         return lf::record_error(LF_EINVAL, "%s", "arena NULL, unaligned or empty");
     if (cfg->max_batch < 1 || cfg->max_inflight < 1 || cfg->max_inflight > kMaxInflight ||
-        cfg->max_queue < 1)
+        cfg->max_queue < 1 || cfg->group_ratio < 0 || cfg->group_ratio == 1)
         return lf::record_error(LF_EINVAL, "%s",
-                                "max_batch >= 1, 1 <= max_inflight <= 4, max_queue >= 1");
+                                "max_batch >= 1, 1 <= max_inflight <= 4, max_queue >= 1, "
+                                "group_ratio 0 or >= 2");
     lf_server* s = new lf_server();
     s->cfg = *cfg;
     s->cfg.arena_bytes = cfg->arena_bytes / kAlign * kAlign;

@@ -76,7 +76,8 @@ class Tuning(C.Structure):
 
 class ServerConfig(C.Structure):
     _fields_ = [("arena", C.c_void_p), ("arena_bytes", C.c_size_t), ("max_batch", C.c_int32),
-                ("max_inflight", C.c_int32), ("max_queue", C.c_int32), ("tuning", Tuning)]
+                ("max_inflight", C.c_int32), ("max_queue", C.c_int32),
+                ("group_ratio", C.c_int32), ("tuning", Tuning)]
 
 
 class RequestInfo(C.Structure):
@@ -419,11 +420,11 @@ class Server:
     """The request loop (lf_server_*) over a device arena of `arena_bytes`."""
 
     def __init__(self, arena_bytes: int, device, max_batch=16, max_inflight=2, max_queue=1024,
-                 tuning: dict | None = None, arena=None):
+                 tuning: dict | None = None, arena=None, group_ratio=0):
         self.arena = arena if arena is not None else workspace(arena_bytes, device)
         t = make_tuning(tuning) or Tuning()
         cfg = ServerConfig(self.arena.data_ptr(), self.arena.numel(), max_batch, max_inflight,
-                           max_queue, t)
+                           max_queue, group_ratio, t)
         self._h = C.c_void_p()
         _check(lib.lf_server_create(C.byref(cfg), C.byref(self._h)))
         self._keep = {}
