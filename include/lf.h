@@ -76,7 +76,10 @@ typedef struct {
 typedef struct { int32_t win_h, win_w; } lf_census_window;
 
 /* SGM penalties of Eq. (8) (0 <= P1 <= P2 <= 16383) and the number of path
- * directions (8: the axis and diagonal directions). */
+ * directions: 8 (the axis and diagonal neighbours) or 16 (those and the eight
+ * knight moves (+-1,+-2), (+-2,+-1), the paper's setting in Sec. 4.3).  A path of
+ * direction r starts at every pixel whose predecessor p - r is outside the
+ * image. */
 typedef struct { int32_t P1, P2, npaths; } lf_sgm_params;
 
 /* Method parameters (Sec. 4.3 gives the paper's values). */

@@ -166,8 +166,8 @@ lf_status check_sgm(lf_sgm_params p, const char* which) {
     if (p.P1 < 0 || p.P2 < p.P1 || p.P2 > 16383)
         return fail(LF_EINVAL, "%s penalties P1=%d P2=%d (need 0 <= P1 <= P2 <= 16383)", which,
                     p.P1, p.P2);
-    if (p.npaths != 8)
-        return fail(LF_EUNSUPPORTED, "%s npaths=%d (this build implements 8)", which, p.npaths);
+    if (p.npaths != 8 && p.npaths != 16)
+        return fail(LF_EUNSUPPORTED, "%s npaths=%d (8 or 16)", which, p.npaths);
     return LF_OK;
 }
 

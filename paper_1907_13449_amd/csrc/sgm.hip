@@ -48,17 +48,25 @@ __device__ __forceinline__ uint32_t wave_min(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
 }
 
-const int kDirs[8][2] = {{1, 0}, {-1, 0}, {0, 1}, {0, -1}, {1, 1}, {-1, -1}, {1, -1}, {-1, 1}};
+// Path directions (du, dv): the 8 axis and diagonal neighbours, then the 8
+// knight moves of the 16-path setting (Sec. 4.3).
+const int kDirs[16][2] = {{1, 0},  {-1, 0},  {0, 1},  {0, -1}, {1, 1},  {-1, -1},
+                          {1, -1}, {-1, 1},  {1, 2},  {-1, -2}, {2, 1},  {-2, -1},
+                          {2, -1}, {-2, 1},  {1, -2}, {-1, 2}};
+constexpr int kMaxPaths = 16;
 
+// A path starts at every pixel whose predecessor p - r lies outside the image:
+// the |dv| rows and |du| columns on the entry sides.
 __host__ __device__ inline int num_lines(int H, int W, int du, int dv) {
-    return dv == 0 ? H : (du == 0 ? W : W + H - 1);
+    const int su = min(abs(du), W), sv = min(abs(dv), H);
+    return sv * W + su * (H - sv);
 }
 
 // Lines of every direction, numbered consecutively: direction r owns global
 // lines [base[r], base[r+1]).
 struct Lines {
-    int base[9];
-    int du[8], dv[8];
+    int base[kMaxPaths + 1];
+    int8_t du[kMaxPaths], dv[kMaxPaths];
     int npaths;
 };
 
@@ -67,8 +75,8 @@ Lines make_lines(int H, int W, int npaths) {
     L.npaths = npaths;
     L.base[0] = 0;
     for (int r = 0; r < npaths; ++r) {
-        L.du[r] = kDirs[r][0];
-        L.dv[r] = kDirs[r][1];
+        L.du[r] = (int8_t)kDirs[r][0];
+        L.dv[r] = (int8_t)kDirs[r][1];
         L.base[r + 1] = L.base[r] + num_lines(H, W, L.du[r], L.dv[r]);
     }
     return L;
@@ -78,37 +86,33 @@ struct LineInfo {
     int r, u0, v0, du, dv, len;
 };
 
+// Start pixel and length of global line g (wave-uniform; scalar arithmetic).
+// Lines of a direction are the entry rows first (row-major), then the entry
+// columns below / above them.
 __device__ __forceinline__ LineInfo locate(const Lines& L, int H, int W, int g) {
     LineInfo li;
     int r = 0;
 #pragma unroll
-    for (int i = 1; i < 8; ++i) r += (i < L.npaths && g >= L.base[i]) ? 1 : 0;
+    for (int i = 1; i < kMaxPaths; ++i) r += (i < L.npaths && g >= L.base[i]) ? 1 : 0;
     const int line = g - L.base[r];
     const int du = L.du[r], dv = L.dv[r];
+    const int su = min(abs(du), W), sv = min(abs(dv), H);
     li.r = r;
     li.du = du;
     li.dv = dv;
-    if (dv == 0) {                       // horizontal: one line per row
-        li.u0 = du > 0 ? 0 : W - 1;
-        li.v0 = line;
-        li.len = W;
-    } else if (du == 0) {                // vertical: one line per column
-        li.u0 = line;
-        li.v0 = dv > 0 ? 0 : H - 1;
-        li.len = H;
-    } else {                             // diagonal: entries on a row, then on a column
-        if (line < W) {
-            li.u0 = line;
-            li.v0 = dv > 0 ? 0 : H - 1;
-        } else {
-            const int j = line - W + 1;
-            li.u0 = du > 0 ? 0 : W - 1;
-            li.v0 = dv > 0 ? j : H - 1 - j;
-        }
-        const int lu = du > 0 ? W - li.u0 : li.u0 + 1;
-        const int lv = dv > 0 ? H - li.v0 : li.v0 + 1;
-        li.len = min(lu, lv);
+    if (line < sv * W) {                 // an entry row
+        const int j = line / W;
+        li.u0 = line - j * W;
+        li.v0 = dv >= 0 ? j : H - 1 - j;
+    } else {                             // an entry column, below/above the entry rows
+        const int l2 = line - sv * W;
+        const int i = l2 / su, j = l2 - i * su;
+        li.u0 = du >= 0 ? j : W - 1 - j;
+        li.v0 = dv >= 0 ? sv + i : H - 1 - sv - i;
     }
+    const int lu = du > 0 ? (W - 1 - li.u0) / du + 1 : du < 0 ? li.u0 / -du + 1 : INT_MAX;
+    const int lv = dv > 0 ? (H - 1 - li.v0) / dv + 1 : dv < 0 ? li.v0 / -dv + 1 : INT_MAX;
+    li.len = min(lu, lv);
     return li;
 }
 
@@ -318,9 +322,8 @@ struct SumWtaArgs {
     int16_t* dmap;            // [nv][H*W]
 };
 
-template <typename LT>
+template <typename LT, int kPaths>
 __device__ __forceinline__ void sum_wta_block(const SumWtaArgs& a, uint32_t b) {
-    constexpr int kPaths = 8;                                     // the only count accepted
     const int lane = threadIdx.x & 63;
     const int64_t q = (int64_t)b * 4 + (threadIdx.x >> 6);       // q = z*HW + p
     if (q >= a.nv * a.HW) return;                                 // wave-uniform
@@ -354,12 +357,12 @@ __device__ __forceinline__ void sum_wta_block(const SumWtaArgs& a, uint32_t b) {
     if (lane == 0) a.dmap[q] = (int16_t)(key & 0xFF);
 }
 
-template <class Src, typename LT>
+template <class Src, typename LT, int kPaths>
 __global__ __launch_bounds__(256) void dense_sum_wta_kernel(Src src) {
     for (uint32_t vb = blockIdx.x; vb < src.total; vb += gridDim.x) {
         uint32_t b;
         const SumWtaArgs& a = member(src, vb, b);
-        sum_wta_block<LT>(a, b);
+        sum_wta_block<LT, kPaths>(a, b);
     }
 }
 
@@ -490,16 +493,15 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void sgm_bounded_paths_kernel(
 // csum[c] = sum_r Lbuf[r][c] over the cells of the CSR volume; each of a light
 // field's nblk workgroups strides over its device-side cell count.
 struct BsumArgs {
-    const uint16_t* Lbuf;     // [8][dir_stride]
+    const uint16_t* Lbuf;     // [npaths][dir_stride]
     size_t dir_stride;
     const int64_t* total;     // device-side cell count
     void* csum;
     uint32_t nblk;
 };
 
-template <class Src, typename SumT>
+template <class Src, typename SumT, int kPaths>
 __global__ __launch_bounds__(256) void bounded_sum_kernel(Src src) {
-    constexpr int kPaths = 8;
     for (uint32_t vb = blockIdx.x; vb < src.total; vb += gridDim.x) {
         uint32_t b;
         const BsumArgs& a = member(src, vb, b);
@@ -596,8 +598,8 @@ hipError_t stage_sgm_initial(Runner& r, const Jobs& jobs) {
     // variants: K in 1..4 x path-cost storage (8 or 16 bit)
     std::vector<DenseArgs> dense[4][2];
     std::vector<uint32_t> dense_blocks[4][2];
-    std::vector<SumWtaArgs> sums[2];
-    std::vector<uint32_t> sum_blocks[2];
+    std::vector<SumWtaArgs> sums[2][2];            // [8/16-bit path costs][8/16 paths]
+    std::vector<uint32_t> sum_blocks[2][2];
     for (const Job* j : jobs) {
         const int H = j->H, W = j->W, N = j->N, NP = dense_np(N);
         const size_t HW = (size_t)H * W;
@@ -649,8 +651,9 @@ hipError_t stage_sgm_initial(Runner& r, const Jobs& jobs) {
         s.N = N;
         s.NP = NP;
         s.dmap = j->maps;
-        sums[lt].push_back(s);
-        sum_blocks[lt].push_back(div_up((uint64_t)j->nv * HW, 4));
+        const int np16 = sp.npaths == 16 ? 1 : 0;
+        sums[lt][np16].push_back(s);
+        sum_blocks[lt][np16].push_back(div_up((uint64_t)j->nv * HW, 4));
     }
     hipError_t e = launch(r, kStSgmInit, census_cost_volume_kernel<Single<CcvArgs>>,
                           census_cost_volume_kernel<Group<CcvArgs>>, ccv, ccv_blocks, 256);
@@ -663,18 +666,27 @@ hipError_t stage_sgm_initial(Runner& r, const Jobs& jobs) {
             if (e != hipSuccess) return e;
         }
     constexpr uint32_t kSumGrid = 8192;       // persistent: each workgroup walks pixels
-    if (!sums[0].empty()) {
-        e = launch(r, kStSgmInit, dense_sum_wta_kernel<Single<SumWtaArgs>, uint8_t>,
-                   dense_sum_wta_kernel<Group<SumWtaArgs>, uint8_t>, sums[0], sum_blocks[0], 256,
-                   kSumGrid);
-        if (e != hipSuccess) return e;
-    }
-    if (!sums[1].empty()) {
-        e = launch(r, kStSgmInit, dense_sum_wta_kernel<Single<SumWtaArgs>, uint16_t>,
-                   dense_sum_wta_kernel<Group<SumWtaArgs>, uint16_t>, sums[1], sum_blocks[1],
-                   256, kSumGrid);
-        if (e != hipSuccess) return e;
-    }
+    using SA = SumWtaArgs;
+    if (!sums[0][0].empty() &&
+        (e = launch(r, kStSgmInit, dense_sum_wta_kernel<Single<SA>, uint8_t, 8>,
+                    dense_sum_wta_kernel<Group<SA>, uint8_t, 8>, sums[0][0], sum_blocks[0][0],
+                    256, kSumGrid)) != hipSuccess)
+        return e;
+    if (!sums[1][0].empty() &&
+        (e = launch(r, kStSgmInit, dense_sum_wta_kernel<Single<SA>, uint16_t, 8>,
+                    dense_sum_wta_kernel<Group<SA>, uint16_t, 8>, sums[1][0], sum_blocks[1][0],
+                    256, kSumGrid)) != hipSuccess)
+        return e;
+    if (!sums[0][1].empty() &&
+        (e = launch(r, kStSgmInit, dense_sum_wta_kernel<Single<SA>, uint8_t, 16>,
+                    dense_sum_wta_kernel<Group<SA>, uint8_t, 16>, sums[0][1], sum_blocks[0][1],
+                    256, kSumGrid)) != hipSuccess)
+        return e;
+    if (!sums[1][1].empty() &&
+        (e = launch(r, kStSgmInit, dense_sum_wta_kernel<Single<SA>, uint16_t, 16>,
+                    dense_sum_wta_kernel<Group<SA>, uint16_t, 16>, sums[1][1], sum_blocks[1][1],
+                    256, kSumGrid)) != hipSuccess)
+        return e;
     return hipSuccess;
 }
 
@@ -683,8 +695,8 @@ hipError_t stage_sgm_final(Runner& r, const Jobs& jobs) {
     std::vector<uint32_t> meta_blocks;
     std::vector<BoundedArgs> paths[4];
     std::vector<uint32_t> path_blocks[4];
-    std::vector<BsumArgs> sums[2];
-    std::vector<uint32_t> sum_blocks[2];
+    std::vector<BsumArgs> sums[2][2];              // [16/32-bit sums][8/16 paths]
+    std::vector<uint32_t> sum_blocks[2][2];
     for (const Job* j : jobs) {
         const int H = j->H, W = j->W, N = j->N;
         const size_t HW = (size_t)H * W;
@@ -717,8 +729,9 @@ hipError_t stage_sgm_final(Runner& r, const Jobs& jobs) {
         s.csum = j->csum;
         s.nblk = std::min<uint32_t>(2048, std::max<uint32_t>(1, div_up(dir_stride, 4096)));
         const int sb = j->prm.sum_bits == 16 ? 0 : 1;
-        sums[sb].push_back(s);
-        sum_blocks[sb].push_back(s.nblk);
+        const int np16 = sp.npaths == 16 ? 1 : 0;
+        sums[sb][np16].push_back(s);
+        sum_blocks[sb][np16].push_back(s.nblk);
     }
     hipError_t e = launch(r, kStSgmFinal, pix_meta_kernel<Single<MetaArgs>>,
                           pix_meta_kernel<Group<MetaArgs>>, meta, meta_blocks, 256);
@@ -728,16 +741,27 @@ hipError_t stage_sgm_final(Runner& r, const Jobs& jobs) {
         e = bounded_k(r, K + 1, paths[K], path_blocks[K]);
         if (e != hipSuccess) return e;
     }
-    if (!sums[0].empty()) {
-        e = launch(r, kStSgmFinal, bounded_sum_kernel<Single<BsumArgs>, uint16_t>,
-                   bounded_sum_kernel<Group<BsumArgs>, uint16_t>, sums[0], sum_blocks[0], 256);
-        if (e != hipSuccess) return e;
-    }
-    if (!sums[1].empty()) {
-        e = launch(r, kStSgmFinal, bounded_sum_kernel<Single<BsumArgs>, uint32_t>,
-                   bounded_sum_kernel<Group<BsumArgs>, uint32_t>, sums[1], sum_blocks[1], 256);
-        if (e != hipSuccess) return e;
-    }
+    using BA = BsumArgs;
+    if (!sums[0][0].empty() &&
+        (e = launch(r, kStSgmFinal, bounded_sum_kernel<Single<BA>, uint16_t, 8>,
+                    bounded_sum_kernel<Group<BA>, uint16_t, 8>, sums[0][0], sum_blocks[0][0],
+                    256)) != hipSuccess)
+        return e;
+    if (!sums[1][0].empty() &&
+        (e = launch(r, kStSgmFinal, bounded_sum_kernel<Single<BA>, uint32_t, 8>,
+                    bounded_sum_kernel<Group<BA>, uint32_t, 8>, sums[1][0], sum_blocks[1][0],
+                    256)) != hipSuccess)
+        return e;
+    if (!sums[0][1].empty() &&
+        (e = launch(r, kStSgmFinal, bounded_sum_kernel<Single<BA>, uint16_t, 16>,
+                    bounded_sum_kernel<Group<BA>, uint16_t, 16>, sums[0][1], sum_blocks[0][1],
+                    256)) != hipSuccess)
+        return e;
+    if (!sums[1][1].empty() &&
+        (e = launch(r, kStSgmFinal, bounded_sum_kernel<Single<BA>, uint32_t, 16>,
+                    bounded_sum_kernel<Group<BA>, uint32_t, 16>, sums[1][1], sum_blocks[1][1],
+                    256)) != hipSuccess)
+        return e;
     return hipSuccess;
 }
 

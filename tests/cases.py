@@ -49,10 +49,18 @@ def case(name):
         lf = lfsynth.workload("paper_s", seed=13, H=40, W=52, S=5, T=5, N=24)
         lf.params.update(cost_kind=1, win_h=5, win_w=5, sum_bits=16)
         return lf
+    if name == "paths16":                    # 16 directions (Sec. 4.3), 32-bit sums
+        lf = lfsynth.workload("paper_s", seed=15, H=41, W=53, S=7, T=7, N=70)
+        lf.params.update(npaths=16)
+        return lf
+    if name == "paths16_u16":                # 16 directions, 16-bit sums, 16-bit path costs
+        lf = lfsynth.workload("paper_s", seed=16, H=30, W=37, S=5, T=5, N=40)
+        lf.params.update(npaths=16, sum_bits=16, P1_init=40, P2_init=230)
+        return lf
     raise KeyError(name)
 
 
 CASES = ["small", "f32_ragged", "u8_n65", "n256", "stage_1x11", "col_7x1", "one_row", "one_col",
-         "u16_paths", "census_cost"]
+         "u16_paths", "census_cost", "paths16", "paths16_u16"]
 
 

@@ -160,7 +160,10 @@ def _brute_force_path(cost, lo, hi, du, dv, P1, P2):
 
 @pytest.mark.parametrize("ranged", [False, True])
 @pytest.mark.parametrize("direction", [(1, 0), (-1, 0), (0, 1), (0, -1), (1, 1), (-1, -1),
-                                       (1, -1), (-1, 1)])
+                                       (1, -1), (-1, 1),
+                                       # the 8 more of the 16-path setting (Sec. 4.3)
+                                       (1, 2), (-1, -2), (2, 1), (-2, -1), (2, -1), (-2, 1),
+                                       (1, -2), (-1, 2)])
 def test_sgm_path_equals_exhaustive_min_sum(direction, ranged):
     # Eq. (8) as printed is the min-sum dynamic programme along the path with
     # pairwise penalty 0 / P1 / P2 (P2 >= P1); checked by enumeration on paths of
@@ -199,6 +202,23 @@ def test_sgm_zero_penalties_reduce_to_the_raw_cost():
     cs = lfo.sgm(cost, 0, 0, npaths=8)
     assert np.array_equal(cs, 8 * cost.astype(np.int64))
     assert np.array_equal(lfo.wta(cs), np.argmin(cost, axis=2).astype(np.int16))
+
+
+def test_sgm_16_paths_sum_every_direction_once():
+    # Eq. (9) over 16 directions: P1 = P2 = 0 gives 16 C; a single pixel is the
+    # start of every path; and the set is closed under mirroring and transposition.
+    cost = rng.integers(0, 60, size=(7, 9, 6)).astype(np.int32)
+    assert np.array_equal(lfo.sgm(cost, 0, 0, npaths=16), 16 * cost.astype(np.int64))
+    one = np.array([[[5, 2, 9]]], np.int32)
+    assert np.array_equal(lfo.sgm(one, 3, 9, npaths=16)[0, 0], [80, 32, 144])
+    c = rng.integers(0, 40, size=(6, 8, 5)).astype(np.int32)
+    a = lfo.sgm(c, 4, 19, npaths=16)
+    assert np.array_equal(lfo.sgm(c[:, ::-1].copy(), 4, 19, npaths=16), a[:, ::-1])
+    assert np.array_equal(lfo.sgm(c[::-1].copy(), 4, 19, npaths=16), a[::-1])
+    assert np.array_equal(lfo.sgm(c.transpose(1, 0, 2).copy(), 4, 19, npaths=16),
+                          a.transpose(1, 0, 2))
+    # the 16-path sum exceeds the 8-path one by the 8 knight-move paths, each >= 0
+    assert (a >= lfo.sgm(c, 4, 19, npaths=8)).all()
 
 
 def test_sgm_flip_equivariance():
