@@ -15,8 +15,10 @@ cells sum_p w(p)), depth maps/s, p50/p99 step latency, per-stage times from HIP
 events recorded on the stream the kernels run on, the roofline of the dominant
 kernel, and the CPU oracle timed on this host as a reported baseline.
 
-Two more measurements ride along in the same line (skip them with --no-batch /
---no-serve):
+Also in the same line: the accuracy of the map against the scene's ground truth
+(BadPix 0.07, MSE, M-metric of Sec. 4.2) beside the boundary-less search
+(lambda = -1, Sec. 4.5) on the same light field, and two more measurements
+(skip them with --no-batch / --no-serve):
   batched  64 light fields mixing 5x5x256^2, 7x7x384^2 and 9x9x512^2 float32
            scenes with 32..128 hypotheses: one autotuned, graph-captured batch
            plan against the same 64 lf_depth calls one after another.
@@ -107,6 +109,49 @@ def cpu_baseline(lfd, cells_per_map):
             "kind": "oracle", "seconds_per_map": dt, "maps_per_s": 1.0 / dt,
             "sample": "one whole light field of the workload (9x9x512^2 f32, N=100), "
                       "single-threaded C oracle, -O3"}
+
+
+# --------------------------------------------------------------- quality
+def quality_vs_boundless(lf, lfd, views, hyp, out, ms_bounded, cells_bounded, stream, steps=5):
+    """Sec. 4.2 measures of the headline map against the scene's ground truth, beside
+    the boundary-less search (Sec. 4.5: lambda = -1, every pixel over the full
+    range, no initial map) on the same light field: what the bounds save in cells
+    and time, and what they cost or gain in accuracy."""
+    import numpy as np
+    import torch
+    from paper_1907_13449_amd import quality
+    # pixels whose largest shift can reach past the image edge are left out
+    dmax = float(max(abs(lfd.hyp[0]), abs(lfd.hyp[-1])))
+    border = int(np.ceil(dmax * (max(lfd.S, lfd.T) - 1) / 2))
+    H, W, N = lfd.H, lfd.W, lfd.N
+    torch.cuda.synchronize()
+    bounded = out.cpu().numpy()
+    p = dict(lfd.params, lam=-1)
+    ws = lf.workspace(lf.depth_workspace_bytes(lfd.S, lfd.T, H, W, N, p), views.device)
+    free = torch.empty_like(out)
+    lf.lf_depth(views, hyp, p, ws=ws, out=free, stream=stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        lf.lf_depth(views, hyp, p, ws=ws, out=free, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_free = e0.elapsed_time(e1) / steps
+    free_map = free.cpu().numpy()
+    del ws
+
+    def q(m, ms):
+        bp = quality.badpix(m, lfd.gt, 0.07, border)
+        return {"badpix_0.07": bp, "mse": quality.mse(m, lfd.gt, border), "ms": ms,
+                "m_metric_pct_per_s": quality.m_metric(bp, ms * 1e-3)}
+    res = {"border_px": border, "ground_truth": "synthetic scene disparity (reference view)",
+           "bounded": dict(q(bounded, ms_bounded), final_cells=cells_bounded),
+           "boundless": dict(q(free_map, ms_free), final_cells=H * W * N),
+           "hypotheses_saved": 1.0 - cells_bounded / (H * W * N),
+           "time_saved": 1.0 - ms_bounded / ms_free}
+    log(f"[bench] bounded: BadPix {res['bounded']['badpix_0.07']:.2f} % in {ms_bounded:.2f} ms; "
+        f"boundary-less: BadPix {res['boundless']['badpix_0.07']:.2f} % in {ms_free:.2f} ms")
+    return res
 
 
 # --------------------------------------------------------------- batches
@@ -459,6 +504,8 @@ def main():
         "roofline": roofline,
         "stage_roofline": roofs,
     }
+    res["quality"] = quality_vs_boundless(lf, lfd, views, hyp, out, ms_per_step, cells_bounded,
+                                          stream)
     del ws
     scenes = None
     if not (args.no_batch and args.no_serve) and args.workload == "paper":

@@ -88,7 +88,9 @@ typedef struct {
     lf_sgm_params sgm_init;    /* SGM of the initial map, Sec. 3.4 */
     lf_sgm_params sgm_final;   /* SGM of the final map, Sec. 3.5 */
     int32_t phi;               /* fusion confidence threshold, in index steps (>= 1) */
-    int32_t lambda;            /* border half-width of Eq. (11), in index steps (>= 0) */
+    int32_t lambda;            /* border half-width of Eq. (11), in index steps (>= 0);
+                                  -1: boundary-less search (Sec. 4.5), every pixel keeps
+                                  the full range and lf_depth skips the initial map */
     int32_t fill_passes;       /* median hole-filling passes (0..8) */
     float edge_tau;            /* Sobel |Gx|+|Gy| threshold in 8-bit units; +inf: off */
     float alpha;               /* cost scale to 8-bit units; <= 0 selects 1 (U8) / 255 (F32) */

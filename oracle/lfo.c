@@ -228,7 +228,8 @@ void lfo_borders(const int16_t* dinit, const uint8_t* edge, int H, int W, int N,
 {
     for (size_t p = 0; p < (size_t)H * W; ++p) {
         int d = dinit[p];
-        if (d < 0 || (edge && edge[p])) {
+        /* lambda < 0: the boundary-less search of Sec. 4.5 -- every pixel keeps T */
+        if (lambda < 0 || d < 0 || (edge && edge[p])) {
             lo[p] = 0;
             hi[p] = (int16_t)(N - 1);
         } else {

@@ -83,7 +83,9 @@ void lfo_fill(const int16_t* in, int H, int W, int16_t* out);
 void lfo_edges(const float* ref, int H, int W, float alpha, float tau, uint8_t* edge);
 
 /* Borders, Eq. (11): valid, non-edge pixel: lo = max(0, D_init - lambda),
- * hi = min(N-1, D_init + lambda); invalid or edge pixel: the full range. */
+ * hi = min(N-1, D_init + lambda); invalid or edge pixel: the full range.
+ * lambda < 0 selects the boundary-less search (Sec. 4.5): the full range for
+ * every pixel (the initial map is then unused). */
 void lfo_borders(const int16_t* dinit, const uint8_t* edge, int H, int W, int N,
                  int lambda, int16_t* lo, int16_t* hi);
 

@@ -184,7 +184,7 @@ lf_status check_params(const lf_params* p) {
         return fail(LF_EINVAL, "initial P2=%d overflows the 16-bit aggregated Census cost",
                     p->sgm_init.P2);
     if (p->phi < 1) return fail(LF_EINVAL, "phi=%d (need >= 1)", p->phi);
-    if (p->lambda < 0) return fail(LF_EINVAL, "lambda=%d (need >= 0)", p->lambda);
+    if (p->lambda < -1) return fail(LF_EINVAL, "lambda=%d (need >= 0, or -1: no bounds)", p->lambda);
     if (p->fill_passes < 0 || p->fill_passes > 8)
         return fail(LF_EINVAL, "fill_passes=%d (0..8)", p->fill_passes);
     if (std::isnan(p->edge_tau)) return fail(LF_EINVAL, "edge_tau is NaN");
@@ -392,7 +392,14 @@ lf_status run_cost(lf::Runner& r, const lf::Jobs& jobs) {
 }
 
 lf_status run_depth(lf::Runner& r, const lf::Jobs& jobs) {
-    LF_CHECK(run_initial(r, jobs));
+    // the boundary-less search (lambda < 0) needs no initial map
+    lf::Jobs bounded, boundless;
+    for (const lf::Job* j : jobs) (j->prm.lambda < 0 ? boundless : bounded).push_back(j);
+    if (!bounded.empty()) LF_CHECK(run_initial(r, bounded));
+    if (!boundless.empty()) {
+        prof::Scope _ps(lf::kStBorders, r);
+        LF_HIP(lf::stage_full_range(r, boundless), "full range");
+    }
     LF_CHECK(run_cost(r, jobs));
     {
         prof::Scope _ps(lf::kStSgmFinal, r);

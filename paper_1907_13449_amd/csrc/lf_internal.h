@@ -183,6 +183,8 @@ hipError_t census_image(Runner& r, const void* img, int dtype, int H, int W, int
 hipError_t stage_sgm_initial(Runner& r, const Jobs& jobs);
 // Fusion, fill passes ending in dinit, edges and borders -> dinit, lo, hi.
 hipError_t stage_borders(Runner& r, const Jobs& jobs);
+// The full hypothesis range for every pixel -> lo, hi (boundary-less search).
+hipError_t stage_full_range(Runner& r, const Jobs& jobs);
 // Exclusive prefix sum of the range widths -> offsets.
 hipError_t stage_offsets(Runner& r, const Jobs& jobs);
 // Bounded matching cost (l2 or Census kind) -> cost (and cost_f32).

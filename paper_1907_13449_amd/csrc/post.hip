@@ -113,7 +113,7 @@ __device__ __forceinline__ void borders_pixel(const BordersArgs& a, int p) {
     const float g = fabsf(gx) + fabsf(gy);
     const bool edge = a.alpha * g > a.tau;
     const int d = a.dinit[p];
-    if (d < 0 || edge) {
+    if (a.lambda < 0 || d < 0 || edge) {          // lambda < 0: boundary-less search
         a.lo[p] = 0;
         a.hi[p] = (int16_t)(a.N - 1);
     } else {
@@ -129,6 +129,25 @@ __global__ __launch_bounds__(kThreads) void borders_kernel(Src src) {
         const BordersArgs& a = member(src, vb, b);
         const int p = (int)b * kThreads + threadIdx.x;
         if (p < a.H * a.W) borders_pixel<T>(a, p);
+    }
+}
+
+// --- boundary-less search (Sec. 4.5): every pixel keeps the full range -------
+struct FullArgs {
+    int16_t* lo;
+    int16_t* hi;
+    int HW, N;
+};
+
+template <class Src>
+__global__ __launch_bounds__(kThreads) void full_range_kernel(Src src) {
+    for (uint32_t vb = blockIdx.x; vb < src.total; vb += gridDim.x) {
+        uint32_t b;
+        const FullArgs& a = member(src, vb, b);
+        const int p = (int)b * kThreads + threadIdx.x;
+        if (p >= a.HW) continue;
+        a.lo[p] = 0;
+        a.hi[p] = (int16_t)(a.N - 1);
     }
 }
 
@@ -378,6 +397,17 @@ hipError_t stage_borders(Runner& r, const Jobs& jobs) {
         e = launch(r, kStBorders, borders_kernel<Single<BordersArgs>, float>,
                    borders_kernel<Group<BordersArgs>, float>, brd[1], brd_blocks[1], kThreads);
     return e;
+}
+
+hipError_t stage_full_range(Runner& r, const Jobs& jobs) {
+    std::vector<FullArgs> args;
+    std::vector<uint32_t> blocks;
+    for (const Job* j : jobs) {
+        args.push_back(FullArgs{j->lo, j->hi, j->H * j->W, j->N});
+        blocks.push_back(blocks_for((int64_t)j->H * j->W));
+    }
+    return launch(r, kStBorders, full_range_kernel<Single<FullArgs>>,
+                  full_range_kernel<Group<FullArgs>>, args, blocks, kThreads);
 }
 
 hipError_t stage_offsets(Runner& r, const Jobs& jobs) {

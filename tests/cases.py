@@ -57,10 +57,14 @@ def case(name):
         lf = lfsynth.workload("paper_s", seed=16, H=30, W=37, S=5, T=5, N=40)
         lf.params.update(npaths=16, sum_bits=16, P1_init=40, P2_init=230)
         return lf
+    if name == "boundless":                  # lambda = -1: full range everywhere (Sec. 4.5)
+        lf = lfsynth.workload("paper_s", seed=17, H=36, W=45, S=5, T=5, N=48)
+        lf.params.update(lam=-1)
+        return lf
     raise KeyError(name)
 
 
 CASES = ["small", "f32_ragged", "u8_n65", "n256", "stage_1x11", "col_7x1", "one_row", "one_col",
-         "u16_paths", "census_cost", "paths16", "paths16_u16"]
+         "u16_paths", "census_cost", "paths16", "paths16_u16", "boundless"]
 
 

@@ -87,7 +87,7 @@ def test_initial_disparity_rejects_bad_shapes(lf, bad):
 
 @pytest.mark.parametrize("bad", [
     dict(win_h=4), dict(win_h=9, win_w=9), dict(win_h=17, win_w=3), dict(P1_init=50, P2_init=40),
-    dict(npaths=4), dict(phi=0), dict(lam=-1), dict(median=5), dict(sum_bits=8),
+    dict(npaths=4), dict(phi=0), dict(lam=-2), dict(median=5), dict(sum_bits=8),
     dict(cost_kind=7), dict(P2_init=9000),
 ])
 def test_params_rejected(lf, bad):

@@ -22,7 +22,7 @@ torch = pytest.importorskip("torch")
 # initial path costs, 16/32-bit sums, 8/16 paths, Census cost kind, median
 # on/off, 0..3 fill passes, 3-D light fields and one-row / one-column images
 MIX = ["small", "f32_ragged", "u8_n65", "n256", "stage_1x11", "col_7x1", "one_row", "one_col",
-       "u16_paths", "census_cost", "paths16", "paths16_u16"]
+       "u16_paths", "census_cost", "paths16", "paths16_u16", "boundless"]
 
 
 @pytest.fixture(scope="module")

@@ -300,6 +300,10 @@ def test_borders_saturate_and_full_range():
     edge[0, 1] = 1
     lo, hi = lfo.borders(dinit, edge, 10, 2)
     assert lo[0, 1] == 0 and hi[0, 1] == 9
+    # lambda = -1: the boundary-less search of Sec. 4.5 keeps the full range everywhere
+    edge[0, 1] = 0
+    lo, hi = lfo.borders(dinit, edge, 10, -1)
+    assert lo.tolist() == [[0, 0, 0, 0]] and hi.tolist() == [[9, 9, 9, 9]]
 
 
 # ------------------------------------------------------------- l2 cost
@@ -450,3 +454,23 @@ def test_depth_recovers_integer_fronto_parallel_plane():
     k_init = int(np.nonzero(shifts == 2 * dstar)[0].min())
     assert k_init < k
     assert (out["maps"][:, m:-m, m:-m] == k_init).all()
+
+
+def test_boundless_search_equals_bounds_wider_than_the_range():
+    # Sec. 4.5's boundary-less search and a border half-width lambda >= N - 1 give
+    # every pixel the full range T, so the final stage -- and the map -- agree; and
+    # the boundary-less map still recovers an integer fronto-parallel plane.
+    S = T = 5
+    H, W = 30, 34
+    views = _shifted_lf(S, T, H, W, 1, seed=12)
+    hyp = lfsynth.hypotheses(-2, 2, 17)
+    wide = lfsynth._params(lam=16)
+    free = lfsynth._params(lam=-1)
+    a = lfo.depth(views, hyp, wide, want_intermediates=True)
+    b = lfo.depth(views, hyp, free, want_intermediates=True)
+    assert (b["lo"] == 0).all() and (b["hi"] == 16).all()
+    assert np.array_equal(a["lo"], b["lo"]) and np.array_equal(a["hi"], b["hi"])
+    assert np.array_equal(a["disparity"], b["disparity"])
+    k = int(np.argmin(np.abs(hyp - 1)))
+    m = 8
+    assert (b["d_index"][m:-m, m:-m] == k).all()
