@@ -231,15 +231,17 @@ size_t plan_initial(Carve& c, int S, int T, int H, int W, int N, const lf_params
 struct CostPlan {
     void* scan;           // prefix-sum scratch
     uint64_t* census_all; // [S*T][HW] (Census kind only)
+    void* padded;         // [S*T][H+2][W+2] edge-replicated views (l2 kind only)
 };
 
 size_t plan_cost(Carve& c, int S, int T, int H, int W, const lf_params* prm, CostPlan* p) {
     const size_t HW = (size_t)H * W;
     CostPlan q;
     q.scan = c.take(lf::scan_scratch_bytes((int64_t)HW));
-    q.census_all = prm && prm->cost_kind == LF_COST_CENSUS
-                       ? (uint64_t*)c.take((size_t)S * T * HW * sizeof(uint64_t))
-                       : nullptr;
+    const bool census = prm && prm->cost_kind == LF_COST_CENSUS;
+    q.census_all = census ? (uint64_t*)c.take((size_t)S * T * HW * sizeof(uint64_t)) : nullptr;
+    // sized for float32 views (uint8 ones use a quarter of it)
+    q.padded = census ? nullptr : c.take((size_t)S * T * (H + 2) * (W + 2) * sizeof(float));
     if (p) *p = q;
     return c.used;
 }
@@ -356,6 +358,7 @@ lf::Job depth_job(const lf_view_set* v, const float* hyp, int N, const lf_params
     j.offsets = pl.offsets;
     j.scan = cp.scan;
     j.census_all = cp.census_all;
+    j.padded = cp.padded;
     j.cost = pl.cost;
     j.cost_f32 = nullptr;
     j.cap_cells = (int64_t)v->H * v->W * N;
@@ -573,6 +576,7 @@ lf_status lf_cost_volume_bounded(const lf_view_set* views, const float* hyp, int
     j.offsets = offsets;
     j.scan = pl.scan;
     j.census_all = pl.census_all;
+    j.padded = pl.padded;
     j.cost = cost;
     j.cost_f32 = cost_f32;
     j.cap_cells = cap_cells;

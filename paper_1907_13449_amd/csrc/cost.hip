@@ -65,15 +65,43 @@ __device__ __forceinline__ Pair<T> ld_pair(const T* p) {
     }
 }
 
+// Views with a replicated one-pixel edge: padded (y', x') holds the view at
+// (clamp(y'-1), clamp(x'-1)).  With it, the two clamped taps of a bilinear row,
+// (clamp(X), clamp(X+1)), are always the two consecutive elements starting at
+// clamp(X, -1, W-1) + 1 -- one 8-byte load, no edge cases, and the same values
+// (so the same float32 sums) as clamping each tap.
+struct PadArgs {
+    const void* src;          // [views][H][pitch]
+    void* dst;                // [views][H+2][W+2]
+    int H, W, pitch;
+    uint32_t per_view;        // blocks per view
+};
+
+template <class Src, typename T>
+__global__ __launch_bounds__(kThreads) void pad_views_kernel(Src src) {
+    for (uint32_t vb = blockIdx.x; vb < src.total; vb += gridDim.x) {
+        uint32_t b;
+        const PadArgs& a = member(src, vb, b);
+        const int z = (int)(b / a.per_view);
+        const int i = (int)(b - (uint32_t)z * a.per_view) * kThreads + threadIdx.x;
+        const int Wp = a.W + 2;
+        if (i >= (a.H + 2) * Wp) continue;
+        const int y = i / Wp, x = i - y * Wp;
+        const T* v = (const T*)a.src + (size_t)z * a.H * a.pitch;
+        ((T*)a.dst)[(size_t)z * (a.H + 2) * Wp + i] =
+            v[(size_t)clampi(y - 1, 0, a.H - 1) * a.pitch + clampi(x - 1, 0, a.W - 1)];
+    }
+}
+
 struct L2Args {
-    const void* views;        // [T][S][H][pitch]
+    const void* views;        // padded: [T][S][H+2][W+2]
     const float* hyp;
     const int16_t* lo;
     const int64_t* off;       // [H*W + 1]
     uint16_t* cost;
     float* cost_f32;          // nullable
     int64_t cap_cells;
-    int S, T, H, W, pitch, N;
+    int S, T, H, W, N;
     float alpha, cap;
     uint32_t nblk;            // workgroups of this light field
 };
@@ -82,16 +110,16 @@ template <typename T, int CPT, bool Walk>
 __device__ __forceinline__ void l2_slices(const L2Args& a, uint32_t b, int64_t* s_off, int* s_lo,
                                           int* s_p) {
     constexpr int kChunk = kThreads * CPT;
-    const int S = a.S, T_ = a.T, H = a.H, W = a.W, pitch = a.pitch, N = a.N;
+    const int S = a.S, T_ = a.T, H = a.H, W = a.W, N = a.N;
+    const int Wp = W + 2;
     const int16_t* __restrict__ lo = a.lo;
     const int64_t* __restrict__ off = a.off;
     const int HW = H * W;
     const int64_t total = min(off[HW], a.cap_cells);
     const int sh = (S - 1) / 2, th = (T_ - 1) / 2;
-    const size_t vstride = (size_t)H * pitch;
+    const uint32_t vstride = (uint32_t)(H + 2) * Wp;
     const T* __restrict__ views = (const T*)a.views;
     const T* __restrict__ refv = views + ((size_t)th * S + sh) * vstride;
-    const bool pairs = W >= 2;
 
     for (int64_t slice = b; slice * kChunk < total; slice += a.nblk) {   // uniform
         const int64_t c0 = slice * kChunk;
@@ -132,39 +160,27 @@ __device__ __forceinline__ void l2_slices(const L2Args& a, uint32_t b, int64_t* 
             const int k = s_lo[i] + (int)(c - s_off[i]);
             if ((unsigned)k >= (unsigned)N) continue;      // only for ranges outside [0, N)
             const float d = a.hyp[k];
-            const float ref = ld(refv + (size_t)v * pitch + u);
+            const float ref = ld(refv + (uint32_t)(v + 1) * Wp + u + 1);
             float acc = 0.0f;
             for (int t = 0; t < T_; ++t) {
                 const float shy = (float)(th - t) * d;
                 const float y0 = floorf(shy);
                 const float fy = shy - y0;
-                const int ya = clampi(v + (int)y0, 0, H - 1), yb = clampi(v + (int)y0 + 1, 0, H - 1);
+                // top tap row in padded coordinates; the bottom one follows it
+                const uint32_t rt = (uint32_t)(clampi(v + (int)y0, -1, H - 1) + 1) * Wp;
                 const T* __restrict__ vt = views + (size_t)t * S * vstride;
                 for (int s = 0; s < S; ++s) {
                     if (s == sh && t == th) continue;        // adds exactly +0
                     const float shx = (float)(sh - s) * d;
                     const float x0 = floorf(shx);
                     const float fx = shx - x0;
-                    const int xa = clampi(u + (int)x0, 0, W - 1), xb = clampi(u + (int)x0 + 1, 0, W - 1);
-                    const T* __restrict__ vs = vt + (size_t)s * vstride;
-                    float ta, tb, bc, be;
-                    if (pairs) {
-                        const int q = min(xa, W - 2);          // xa, xb in {q, q+1}
-                        const Pair<T> top = ld_pair(vs + (size_t)ya * pitch + q);
-                        const Pair<T> bot = ld_pair(vs + (size_t)yb * pitch + q);
-                        ta = xa == q ? top.lo : top.hi;
-                        tb = xb == q ? top.lo : top.hi;
-                        bc = xa == q ? bot.lo : bot.hi;
-                        be = xb == q ? bot.lo : bot.hi;
-                    } else {
-                        ta = ld(vs + (size_t)ya * pitch + xa);
-                        tb = ld(vs + (size_t)ya * pitch + xb);
-                        bc = ld(vs + (size_t)yb * pitch + xa);
-                        be = ld(vs + (size_t)yb * pitch + xb);
-                    }
-                    const float top = fmaf(fx, tb - ta, ta);
-                    const float bot = fmaf(fx, be - bc, bc);
-                    const float val = fmaf(fy, bot - top, top);
+                    const uint32_t o = rt + (uint32_t)(clampi(u + (int)x0, -1, W - 1) + 1);
+                    const T* __restrict__ vs = vt + (uint32_t)s * vstride;
+                    const Pair<T> top = ld_pair(vs + o);
+                    const Pair<T> bot = ld_pair(vs + o + Wp);
+                    const float tv = fmaf(fx, top.hi - top.lo, top.lo);
+                    const float bv = fmaf(fx, bot.hi - bot.lo, bot.lo);
+                    const float val = fmaf(fy, bv - tv, tv);
                     acc = acc + fabsf(ref - val);
                 }
             }
@@ -176,8 +192,6 @@ __device__ __forceinline__ void l2_slices(const L2Args& a, uint32_t b, int64_t* 
     }
 }
 
-// One workgroup per virtual block (the grid is never capped); with Walk a
-// workgroup takes every nblk-th slice of its light field, else exactly one.
 template <class Src, typename T, int CPT, bool Walk>
 __global__ __launch_bounds__(kThreads) void cost_l2_kernel(Src src) {
     __shared__ int64_t s_off[kThreads * CPT + 1];
@@ -274,6 +288,8 @@ hipError_t l2_walk(Runner& r, const std::vector<L2Args>& args,
 hipError_t stage_cost(Runner& r, const Jobs& jobs) {
     std::vector<L2Args> l2[2];
     std::vector<uint32_t> l2_blocks[2];
+    std::vector<PadArgs> pads[2];
+    std::vector<uint32_t> pad_blocks[2];
     std::vector<CensusAllArgs> ca;
     std::vector<uint32_t> ca_blocks;
     Jobs census_jobs;
@@ -282,8 +298,17 @@ hipError_t stage_cost(Runner& r, const Jobs& jobs) {
     for (const Job* j : jobs) {
         const int64_t HW = (int64_t)j->H * j->W;
         if (j->prm.cost_kind == LF_COST_L2) {
+            PadArgs pa{};
+            pa.src = j->views;
+            pa.dst = j->padded;
+            pa.H = j->H;
+            pa.W = j->W;
+            pa.pitch = j->pitch;
+            pa.per_view = (uint32_t)(((int64_t)(j->H + 2) * (j->W + 2) + kThreads - 1) / kThreads);
+            pads[j->dtype == LF_U8 ? 0 : 1].push_back(pa);
+            pad_blocks[j->dtype == LF_U8 ? 0 : 1].push_back(pa.per_view * j->S * j->T);
             L2Args a{};
-            a.views = j->views;
+            a.views = j->padded;
             a.hyp = j->hyp;
             a.lo = j->lo;
             a.off = j->offsets;
@@ -294,7 +319,6 @@ hipError_t stage_cost(Runner& r, const Jobs& jobs) {
             a.T = j->T;
             a.H = j->H;
             a.W = j->W;
-            a.pitch = j->pitch;
             a.N = j->N;
             a.alpha = j->alpha;
             a.cap = (float)j->cap;
@@ -325,6 +349,16 @@ hipError_t stage_cost(Runner& r, const Jobs& jobs) {
         }
     }
     hipError_t e = hipSuccess;
+    if (!pads[0].empty() &&
+        (e = launch(r, kStCost, pad_views_kernel<Single<PadArgs>, uint8_t>,
+                    pad_views_kernel<Group<PadArgs>, uint8_t>, pads[0], pad_blocks[0],
+                    kThreads)) != hipSuccess)
+        return e;
+    if (!pads[1].empty() &&
+        (e = launch(r, kStCost, pad_views_kernel<Single<PadArgs>, float>,
+                    pad_views_kernel<Group<PadArgs>, float>, pads[1], pad_blocks[1],
+                    kThreads)) != hipSuccess)
+        return e;
     if (!l2[0].empty() && (e = l2_walk<uint8_t>(r, l2[0], l2_blocks[0])) != hipSuccess) return e;
     if (!l2[1].empty() && (e = l2_walk<float>(r, l2[1], l2_blocks[1])) != hipSuccess) return e;
     if (!census_jobs.empty()) {

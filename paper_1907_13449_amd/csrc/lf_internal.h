@@ -153,6 +153,7 @@ struct Job {
     int64_t* offsets;         // [H*W + 1]
     void* scan;               // scan_scratch_bytes(H*W)
     uint64_t* census_all;     // [S*T][H*W] (Census cost kind)
+    void* padded;             // [S*T][H+2][W+2] views with a replicated edge (l2 kind)
     uint16_t* cost;           // [cells]
     float* cost_f32;          // [cells] or null
     int64_t cap_cells;
