@@ -357,6 +357,62 @@ __device__ __forceinline__ void sum_wta_block(const SumWtaArgs& a, uint32_t b) {
     if (lane == 0) a.dmap[q] = (int16_t)(key & 0xFF);
 }
 
+// The same for 8-bit path costs with rows of at most 128 bytes (N <= 128): a
+// row of 16 lanes per pixel, 8 bytes (8 hypotheses) per lane, so one 64-lane
+// load reads four pixels' rows of a direction (512 bytes).  The sums are kept
+// two per register in 16-bit fields (at most 16 * 255 per field: no carry
+// between fields); the argmin is a DPP minimum within the row of 16 lanes.
+// Lanes past a row's end read the next row (or the slack after the volume) and
+// drop those hypotheses (k >= N).
+template <int kPaths>
+__device__ __forceinline__ void sum_wta_rows_block(const SumWtaArgs& a, uint32_t b) {
+    const int sub = threadIdx.x & 15;
+    const int64_t nq = a.nv * a.HW;
+    const int64_t q = (int64_t)b * 16 + (threadIdx.x >> 4);       // this row's pixel
+    const int64_t qq = q < nq ? q : nq - 1;                        // rows past the end
+    const int N = a.N;                                             // load in bounds
+    const size_t dir_stride = (size_t)a.nv * a.HW * a.NP;
+    const uint8_t* __restrict__ base = (const uint8_t*)a.Lbuf + (size_t)qq * a.NP + sub * 8;
+    uint32_t x0[kPaths], x1[kPaths];
+#pragma unroll
+    for (int r = 0; r < kPaths; ++r) {
+        uint2 v;
+        __builtin_memcpy(&v, base + (size_t)r * dir_stride, 8);
+        x0[r] = v.x;
+        x1[r] = v.y;
+    }
+    // acc[0]: bytes 0, 2; acc[1]: 1, 3; acc[2]: 4, 6; acc[3]: 5, 7 (low, high field)
+    uint32_t acc[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int r = 0; r < kPaths; ++r) {
+        acc[0] += x0[r] & 0x00FF00FFu;
+        acc[1] += (x0[r] >> 8) & 0x00FF00FFu;
+        acc[2] += x1[r] & 0x00FF00FFu;
+        acc[3] += (x1[r] >> 8) & 0x00FF00FFu;
+    }
+    uint32_t key = UINT_MAX;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const uint32_t t = (acc[(i >> 2) * 2 + (i & 1)] >> (16 * ((i >> 1) & 1))) & 0xFFFFu;
+        const int k = sub * 8 + i;
+        if (k < N) key = min(key, (t << 8) | (uint32_t)k);
+    }
+    key = min(key, dpp<0xB1>(UINT_MAX, key));     // quad_perm [1,0,3,2]
+    key = min(key, dpp<0x4E>(UINT_MAX, key));     // quad_perm [2,3,0,1]
+    key = min(key, dpp<0x141>(UINT_MAX, key));    // row_half_mirror
+    key = min(key, dpp<0x140>(UINT_MAX, key));    // row_mirror: the row's minimum
+    if (sub == 0 && q < nq) a.dmap[q] = (int16_t)(key & 0xFF);
+}
+
+template <class Src, int kPaths>
+__global__ __launch_bounds__(256) void dense_sum_wta_rows_kernel(Src src) {
+    for (uint32_t vb = blockIdx.x; vb < src.total; vb += gridDim.x) {
+        uint32_t b;
+        const SumWtaArgs& a = member(src, vb, b);
+        sum_wta_rows_block<kPaths>(a, b);
+    }
+}
+
 template <class Src, typename LT, int kPaths>
 __global__ __launch_bounds__(256) void dense_sum_wta_kernel(Src src) {
     for (uint32_t vb = blockIdx.x; vb < src.total; vb += gridDim.x) {
@@ -584,7 +640,8 @@ int dense_np(int N) { return (N + 3) / 4 * 4; }
 size_t sgm_dense_scratch_bytes(int nv, int H, int W, int N, int npaths, int bits, int P2) {
     const size_t lt = bits + P2 <= 255 ? 1 : 2;
     const size_t cv = round256((size_t)nv * H * W * dense_np(N));
-    return cv + (size_t)npaths * nv * H * W * dense_np(N) * lt;
+    // + 256: the row-wise sum reads up to 128 bytes past the last pixel's row
+    return cv + (size_t)npaths * nv * H * W * dense_np(N) * lt + 256;
 }
 
 size_t sgm_bounded_scratch_bytes(int H, int W, int N, int npaths) {
@@ -600,6 +657,8 @@ hipError_t stage_sgm_initial(Runner& r, const Jobs& jobs) {
     std::vector<uint32_t> dense_blocks[4][2];
     std::vector<SumWtaArgs> sums[2][2];            // [8/16-bit path costs][8/16 paths]
     std::vector<uint32_t> sum_blocks[2][2];
+    std::vector<SumWtaArgs> rows[2];               // 8-bit rows <= 128 B: [8/16 paths]
+    std::vector<uint32_t> row_blocks[2];
     for (const Job* j : jobs) {
         const int H = j->H, W = j->W, N = j->N, NP = dense_np(N);
         const size_t HW = (size_t)H * W;
@@ -652,8 +711,13 @@ hipError_t stage_sgm_initial(Runner& r, const Jobs& jobs) {
         s.NP = NP;
         s.dmap = j->maps;
         const int np16 = sp.npaths == 16 ? 1 : 0;
-        sums[lt][np16].push_back(s);
-        sum_blocks[lt][np16].push_back(div_up((uint64_t)j->nv * HW, 4));
+        if (lt == 0 && NP <= 128) {
+            rows[np16].push_back(s);
+            row_blocks[np16].push_back(div_up((uint64_t)j->nv * HW, 16));
+        } else {
+            sums[lt][np16].push_back(s);
+            sum_blocks[lt][np16].push_back(div_up((uint64_t)j->nv * HW, 4));
+        }
     }
     hipError_t e = launch(r, kStSgmInit, census_cost_volume_kernel<Single<CcvArgs>>,
                           census_cost_volume_kernel<Group<CcvArgs>>, ccv, ccv_blocks, 256);
@@ -667,6 +731,16 @@ hipError_t stage_sgm_initial(Runner& r, const Jobs& jobs) {
         }
     constexpr uint32_t kSumGrid = 8192;       // persistent: each workgroup walks pixels
     using SA = SumWtaArgs;
+    if (!rows[0].empty() &&
+        (e = launch(r, kStSgmInit, dense_sum_wta_rows_kernel<Single<SA>, 8>,
+                    dense_sum_wta_rows_kernel<Group<SA>, 8>, rows[0], row_blocks[0], 256,
+                    kSumGrid)) != hipSuccess)
+        return e;
+    if (!rows[1].empty() &&
+        (e = launch(r, kStSgmInit, dense_sum_wta_rows_kernel<Single<SA>, 16>,
+                    dense_sum_wta_rows_kernel<Group<SA>, 16>, rows[1], row_blocks[1], 256,
+                    kSumGrid)) != hipSuccess)
+        return e;
     if (!sums[0][0].empty() &&
         (e = launch(r, kStSgmInit, dense_sum_wta_kernel<Single<SA>, uint8_t, 8>,
                     dense_sum_wta_kernel<Group<SA>, uint8_t, 8>, sums[0][0], sum_blocks[0][0],
