@@ -39,7 +39,8 @@ class _Params(C.Structure):
                 ("P1_init", C.c_int), ("P2_init", C.c_int),
                 ("P1_final", C.c_int), ("P2_final", C.c_int),
                 ("npaths", C.c_int), ("phi", C.c_int), ("lambda_", C.c_int),
-                ("fill_passes", C.c_int), ("edge_tau", C.c_float), ("alpha", C.c_float),
+                ("fill_passes", C.c_int), ("lambda_far", C.c_int), ("channels", C.c_int),
+                ("edge_tau", C.c_float), ("alpha", C.c_float),
                 ("cost_kind", C.c_int), ("median", C.c_int), ("cost_cap", C.c_int32)]
 
 
@@ -138,41 +139,57 @@ def fill(d):
     return out
 
 
+def _views(views):
+    """[T][S][H][W] grayscale or [T][S][C][H][W] colour -> (float32 array, T, S, C, H, W)."""
+    views = _f32(views)
+    if views.ndim == 4:
+        T, S, H, W = views.shape
+        return views, T, S, 1, H, W
+    T, S, Cn, H, W = views.shape
+    return views, T, S, Cn, H, W
+
+
 def edges(ref, alpha, tau):
+    """ref: [H][W] or [C][H][W]."""
     ref = _f32(ref)
-    H, W = ref.shape
+    Cn = 1 if ref.ndim == 2 else ref.shape[0]
+    H, W = ref.shape[-2:]
     out = np.zeros((H, W), dtype=np.uint8)
-    lib().lfo_edges(_p(ref), H, W, C.c_float(alpha), C.c_float(tau), _p(out))
+    lib().lfo_edges(_p(ref), Cn, H, W, C.c_float(alpha), C.c_float(tau), _p(out))
     return out
 
 
-def borders(dinit, edge, N, lam):
+def borders(dinit, edge, N, lam, lam_far=0):
     dinit = _i16(dinit)
     H, W = dinit.shape
     edge = None if edge is None else np.ascontiguousarray(edge, dtype=np.uint8)
     lo = np.zeros((H, W), dtype=np.int16)
     hi = np.zeros((H, W), dtype=np.int16)
-    lib().lfo_borders(_p(dinit), _p(edge), H, W, int(N), int(lam), _p(lo), _p(hi))
+    lib().lfo_borders(_p(dinit), _p(edge), H, W, int(N), int(lam), int(lam_far), _p(lo), _p(hi))
     return lo, hi
 
 
+def border_width(lam, lam_far, d, N):
+    return lib().lfo_border_width(int(lam), int(lam_far), int(d), int(N))
+
+
 def cost_l2_f64(views, hyp, lo=None, hi=None):
-    views = _f32(views)
-    T, S, H, W = views.shape
+    views, T, S, Cn, H, W = _views(views)
     hyp = _f32(hyp)
     N = hyp.shape[0]
     out = np.zeros((H, W, N), dtype=np.float64)
-    lib().lfo_cost_l2_f64(_p(views), S, T, H, W, _p(hyp), N, _p(_i16(lo)), _p(_i16(hi)), _p(out))
+    lib().lfo_cost_l2_f64(_p(views), S, T, Cn, H, W, _p(hyp), N, _p(_i16(lo)), _p(_i16(hi)),
+                          _p(out))
     return out
 
 
 def cost_l2_f32(views, hyp, lo=None, hi=None):
-    views = _f32(views)
-    T, S, H, W = views.shape
+    views, T, S, Cn, H, W = _views(views)
     hyp = _f32(hyp)
     N = hyp.shape[0]
     out = np.zeros((H, W, N), dtype=np.float32)
-    lib().lfo_cost_l2_f32(_p(views), S, T, H, W, _p(hyp), N, _p(_i16(lo)), _p(_i16(hi)), _p(out))
+    lib().lfo_cost_l2_f32(_p(views), S, T, Cn, H, W, _p(hyp), N, _p(_i16(lo)), _p(_i16(hi)),
+                          _p(out))
     return out
 
 
@@ -186,13 +203,18 @@ def quantize(s, alpha, cap, lo=None, hi=None):
 
 
 def cost_census_all(census_all, hyp, cap, lo=None, hi=None):
+    """census_all: [T][S][H][W] or [T][S][C][H][W] uint64."""
     census_all = np.ascontiguousarray(census_all, dtype=np.uint64)
-    T, S, H, W = census_all.shape
+    if census_all.ndim == 4:
+        T, S, H, W = census_all.shape
+        Cn = 1
+    else:
+        T, S, Cn, H, W = census_all.shape
     hyp = _f32(hyp)
     N = hyp.shape[0]
     out = np.zeros((H, W, N), dtype=np.int32)
-    lib().lfo_cost_census_all(_p(census_all), S, T, H, W, _p(hyp), N, _p(_i16(lo)), _p(_i16(hi)),
-                              C.c_int32(int(cap)), _p(out))
+    lib().lfo_cost_census_all(_p(census_all), S, T, Cn, H, W, _p(hyp), N, _p(_i16(lo)),
+                              _p(_i16(hi)), C.c_int32(int(cap)), _p(out))
     return out
 
 
@@ -220,13 +242,13 @@ def cost_cap(P2_final, npaths, sum_bits):
 
 def depth(views, hyp, params, want_intermediates=False):
     """The whole method (Sec. 3.3-3.6) on one light field; returns a dict."""
-    views = _f32(views)
-    T, S, H, W = views.shape
+    views, T, S, Cn, H, W = _views(views)
     hyp = _f32(hyp)
     N = hyp.shape[0]
     pr = params
     prm = _Params(pr["win_h"], pr["win_w"], pr["P1_init"], pr["P2_init"], pr["P1_final"],
                   pr["P2_final"], pr["npaths"], pr["phi"], pr["lam"], pr["fill_passes"],
+                  pr.get("lam_far", 0), Cn,
                   pr["edge_tau"], pr["alpha"], pr["cost_kind"], pr["median"],
                   cost_cap(pr["P2_final"], pr["npaths"], pr["sum_bits"]))
     nv = len(cross_views(S, T))

@@ -205,26 +205,39 @@ void lfo_fill(const int16_t* in, int H, int W, int16_t* out)
     }
 }
 
-void lfo_edges(const float* ref, int H, int W, float alpha, float tau, uint8_t* edge)
+void lfo_edges(const float* ref, int C, int H, int W, float alpha, float tau, uint8_t* edge)
 {
     for (int v = 0; v < H; ++v) {
         for (int u = 0; u < W; ++u) {
             int ym = clampi(v - 1, 0, H - 1), yp = clampi(v + 1, 0, H - 1);
             int xm = clampi(u - 1, 0, W - 1), xp = clampi(u + 1, 0, W - 1);
-#define I(y, x) ref[(size_t)(y) * W + (x)]
-            float gx = ((I(ym, xp) + 2.0f * I(v, xp)) + I(yp, xp))
-                     - ((I(ym, xm) + 2.0f * I(v, xm)) + I(yp, xm));
-            float gy = ((I(yp, xm) + 2.0f * I(yp, u)) + I(yp, xp))
-                     - ((I(ym, xm) + 2.0f * I(ym, u)) + I(ym, xp));
+            float g = 0.0f;
+            for (int c = 0; c < C; ++c) {       /* colour: the strongest channel */
+                const float* img = ref + (size_t)c * H * W;
+#define I(y, x) img[(size_t)(y) * W + (x)]
+                float gx = ((I(ym, xp) + 2.0f * I(v, xp)) + I(yp, xp))
+                         - ((I(ym, xm) + 2.0f * I(v, xm)) + I(yp, xm));
+                float gy = ((I(yp, xm) + 2.0f * I(yp, u)) + I(yp, xp))
+                         - ((I(ym, xm) + 2.0f * I(ym, u)) + I(ym, xp));
 #undef I
-            float g = fabsf(gx) + fabsf(gy);
+                float gc = fabsf(gx) + fabsf(gy);
+                if (gc > g) g = gc;
+            }
             edge[(size_t)v * W + u] = (uint8_t)(alpha * g > tau);
         }
     }
 }
 
+int lfo_border_width(int lambda, int lambda_far, int d, int N)
+{
+    /* Sec. 4.6: a wider border for small disparities (far objects).  Linear in
+     * the index from lambda_far at k = 0 to lambda at k = N-1, rounded half up. */
+    if (lambda_far <= lambda || N < 2) return lambda;
+    return lambda + ((lambda_far - lambda) * (N - 1 - d) + (N - 1) / 2) / (N - 1);
+}
+
 void lfo_borders(const int16_t* dinit, const uint8_t* edge, int H, int W, int N,
-                 int lambda, int16_t* lo, int16_t* hi)
+                 int lambda, int lambda_far, int16_t* lo, int16_t* hi)
 {
     for (size_t p = 0; p < (size_t)H * W; ++p) {
         int d = dinit[p];
@@ -233,19 +246,20 @@ void lfo_borders(const int16_t* dinit, const uint8_t* edge, int H, int W, int N,
             lo[p] = 0;
             hi[p] = (int16_t)(N - 1);
         } else {
-            lo[p] = (int16_t)(d - lambda < 0 ? 0 : d - lambda);
-            hi[p] = (int16_t)(d + lambda > N - 1 ? N - 1 : d + lambda);
+            int lam = lfo_border_width(lambda, lambda_far, d, N);
+            lo[p] = (int16_t)(d - lam < 0 ? 0 : d - lam);
+            hi[p] = (int16_t)(d + lam > N - 1 ? N - 1 : d + lam);
         }
     }
 }
 
 /* ----------------------------------------------------- bounded l2 cost */
-void lfo_cost_l2_f64(const float* views, int S, int T, int H, int W, const float* hyp,
+void lfo_cost_l2_f64(const float* views, int S, int T, int C, int H, int W, const float* hyp,
                      int N, const int16_t* lo, const int16_t* hi, double* out)
 {
     int sh = (S - 1) / 2, th = (T - 1) / 2;
     size_t plane = (size_t)H * W;
-    const float* ref = views + ((size_t)th * S + sh) * plane;
+    const float* ref = views + ((size_t)th * S + sh) * C * plane;
     for (int v = 0; v < H; ++v) {
         for (int u = 0; u < W; ++u) {
             size_t p = (size_t)v * W + u;
@@ -254,19 +268,26 @@ void lfo_cost_l2_f64(const float* views, int S, int T, int H, int W, const float
                 double acc = 0.0;
                 for (int t = 0; t < T; ++t) {
                     for (int s = 0; s < S; ++s) {
-                        const float* view = views + ((size_t)t * S + s) * plane;
                         double x = (double)u + (double)(sh - s) * (double)hyp[k];
                         double y = (double)v + (double)(th - t) * (double)hyp[k];
                         double x0 = floor(x), y0 = floor(y);
                         double fx = x - x0, fy = y - y0;
                         int xa = clampi((int)x0, 0, W - 1), xb = clampi((int)x0 + 1, 0, W - 1);
                         int ya = clampi((int)y0, 0, H - 1), yb = clampi((int)y0 + 1, 0, H - 1);
-                        double a = view[(size_t)ya * W + xa], b = view[(size_t)ya * W + xb];
-                        double c = view[(size_t)yb * W + xa], e = view[(size_t)yb * W + xb];
-                        double top = a + fx * (b - a);
-                        double bot = c + fx * (e - c);
-                        double val = top + fy * (bot - top);
-                        acc += fabs((double)ref[p] - val);
+                        double sq = 0.0, dist = 0.0;
+                        for (int ch = 0; ch < C; ++ch) {
+                            const float* view = views + (((size_t)t * S + s) * C + ch) * plane;
+                            double a = view[(size_t)ya * W + xa], b = view[(size_t)ya * W + xb];
+                            double c = view[(size_t)yb * W + xa], e = view[(size_t)yb * W + xb];
+                            double top = a + fx * (b - a);
+                            double bot = c + fx * (e - c);
+                            double val = top + fy * (bot - top);
+                            double dl = (double)ref[ch * plane + p] - val;
+                            dist = fabs(dl);
+                            sq += dl * dl;
+                        }
+                        /* the l2 norm of the colour difference, R16 */
+                        acc += C == 1 ? dist : sqrt(sq);
                     }
                 }
                 out[p * N + k] = acc;
@@ -275,12 +296,12 @@ void lfo_cost_l2_f64(const float* views, int S, int T, int H, int W, const float
     }
 }
 
-void lfo_cost_l2_f32(const float* views, int S, int T, int H, int W, const float* hyp,
+void lfo_cost_l2_f32(const float* views, int S, int T, int C, int H, int W, const float* hyp,
                      int N, const int16_t* lo, const int16_t* hi, float* out)
 {
     int sh = (S - 1) / 2, th = (T - 1) / 2;
     size_t plane = (size_t)H * W;
-    const float* ref = views + ((size_t)th * S + sh) * plane;
+    const float* ref = views + ((size_t)th * S + sh) * C * plane;
     for (int v = 0; v < H; ++v) {
         for (int u = 0; u < W; ++u) {
             size_t p = (size_t)v * W + u;
@@ -293,17 +314,24 @@ void lfo_cost_l2_f32(const float* views, int S, int T, int H, int W, const float
                     float fy = shy - y0;
                     int ya = clampi(v + (int)y0, 0, H - 1), yb = clampi(v + (int)y0 + 1, 0, H - 1);
                     for (int s = 0; s < S; ++s) {
-                        const float* view = views + ((size_t)t * S + s) * plane;
                         float shx = (float)(sh - s) * hyp[k];
                         float x0 = floorf(shx);
                         float fx = shx - x0;
                         int xa = clampi(u + (int)x0, 0, W - 1), xb = clampi(u + (int)x0 + 1, 0, W - 1);
-                        float a = view[(size_t)ya * W + xa], b = view[(size_t)ya * W + xb];
-                        float c = view[(size_t)yb * W + xa], e = view[(size_t)yb * W + xb];
-                        float top = fmaf(fx, b - a, a);
-                        float bot = fmaf(fx, e - c, c);
-                        float val = fmaf(fy, bot - top, top);
-                        acc = acc + fabsf(ref[p] - val);
+                        float sq = 0.0f, dist = 0.0f;
+                        for (int ch = 0; ch < C; ++ch) {
+                            const float* view = views + (((size_t)t * S + s) * C + ch) * plane;
+                            float a = view[(size_t)ya * W + xa], b = view[(size_t)ya * W + xb];
+                            float c = view[(size_t)yb * W + xa], e = view[(size_t)yb * W + xb];
+                            float top = fmaf(fx, b - a, a);
+                            float bot = fmaf(fx, e - c, c);
+                            float val = fmaf(fy, bot - top, top);
+                            float dl = ref[ch * plane + p] - val;
+                            dist = fabsf(dl);
+                            /* channel 0 squared, the others added by fma in order */
+                            sq = ch == 0 ? dl * dl : fmaf(dl, dl, sq);
+                        }
+                        acc = acc + (C == 1 ? dist : sqrtf(sq));
                     }
                 }
                 out[p * N + k] = acc;
@@ -324,13 +352,13 @@ void lfo_quantize(const float* s, int H, int W, int N, const int16_t* lo,
     }
 }
 
-void lfo_cost_census_all(const uint64_t* census_all, int S, int T, int H, int W,
+void lfo_cost_census_all(const uint64_t* census_all, int S, int T, int C, int H, int W,
                          const float* hyp, int N, const int16_t* lo, const int16_t* hi,
                          int32_t cap, int32_t* cost)
 {
     int sh = (S - 1) / 2, th = (T - 1) / 2;
     size_t plane = (size_t)H * W;
-    const uint64_t* cref = census_all + ((size_t)th * S + sh) * plane;
+    const uint64_t* cref = census_all + ((size_t)th * S + sh) * C * plane;
     for (int v = 0; v < H; ++v) {
         for (int u = 0; u < W; ++u) {
             size_t p = (size_t)v * W + u;
@@ -339,10 +367,12 @@ void lfo_cost_census_all(const uint64_t* census_all, int S, int T, int H, int W,
                 int64_t acc = 0;
                 for (int t = 0; t < T; ++t)
                     for (int s = 0; s < S; ++s) {
-                        const uint64_t* cv = census_all + ((size_t)t * S + s) * plane;
                         int x = clampi(u + (int)rintf((float)(sh - s) * hyp[k]), 0, W - 1);
                         int y = clampi(v + (int)rintf((float)(th - t) * hyp[k]), 0, H - 1);
-                        acc += lfo_hamming(cref[p], cv[(size_t)y * W + x]);
+                        for (int ch = 0; ch < C; ++ch) {  /* per-channel Census, summed */
+                            const uint64_t* cv = census_all + (((size_t)t * S + s) * C + ch) * plane;
+                            acc += lfo_hamming(cref[ch * plane + p], cv[(size_t)y * W + x]);
+                        }
                     }
                 cost[p * N + k] = acc > cap ? cap : (int32_t)acc;
             }
@@ -405,26 +435,37 @@ int lfo_depth(const float* views, int S, int T, int H, int W, const float* hyp, 
 {
     if (S < 1 || T < 1 || (S % 2) == 0 || (T % 2) == 0 || S * T < 2 || H < 1 || W < 1 || N < 2)
         return -1;
+    const int C = prm->channels < 1 ? 1 : prm->channels;
     size_t plane = (size_t)H * W, vol = plane * N;
     int sh = (S - 1) / 2, th = (T - 1) / 2;
-    const float* ref = views + ((size_t)th * S + sh) * plane;
+    /* views [T][S][C][H][W]: a view is C planes (one for grayscale) */
+    const float* ref = views + ((size_t)th * S + sh) * C * plane;
 
-    /* Sec. 3.4: Census cost on the cross-lying views, SGM, WTA -> D_1..D_|V| */
+    /* Sec. 3.4: Census cost on the cross-lying views, SGM, WTA -> D_1..D_|V|.
+     * Colour views: Census per channel, Hamming distances summed (Sec. 3.2). */
     int vset[8];
     int nv = lfo_cross_views(S, T, vset);
     int16_t* maps = (int16_t*)malloc((size_t)nv * plane * sizeof(int16_t));
-    uint64_t* cref = (uint64_t*)malloc(plane * sizeof(uint64_t));
+    uint64_t* cref = (uint64_t*)malloc(C * plane * sizeof(uint64_t));
     uint64_t* cview = (uint64_t*)malloc(plane * sizeof(uint64_t));
     int32_t* cost = (int32_t*)malloc(vol * sizeof(int32_t));
+    int32_t* cpart = (int32_t*)malloc(vol * sizeof(int32_t));
     int64_t* csum = (int64_t*)malloc(vol * sizeof(int64_t));
-    lfo_census(ref, H, W, prm->win_h, prm->win_w, cref);
+    for (int ch = 0; ch < C; ++ch)
+        lfo_census(ref + ch * plane, H, W, prm->win_h, prm->win_w, cref + ch * plane);
     for (int i = 0; i < nv; ++i) {
         int s = vset[2 * i], t = vset[2 * i + 1];
-        lfo_census(views + ((size_t)t * S + s) * plane, H, W, prm->win_h, prm->win_w, cview);
-        lfo_cost_census_view(cref, cview, H, W, sh - s, th - t, hyp, N, cost);
+        memset(cost, 0, vol * sizeof(int32_t));
+        for (int ch = 0; ch < C; ++ch) {
+            lfo_census(views + (((size_t)t * S + s) * C + ch) * plane, H, W, prm->win_h,
+                       prm->win_w, cview);
+            lfo_cost_census_view(cref + ch * plane, cview, H, W, sh - s, th - t, hyp, N, cpart);
+            for (size_t e = 0; e < vol; ++e) cost[e] += cpart[e];
+        }
         lfo_sgm(cost, NULL, NULL, H, W, N, prm->P1_init, prm->P2_init, prm->npaths, csum);
         lfo_wta(csum, NULL, NULL, H, W, N, maps + (size_t)i * plane);
     }
+    free(cpart);
 
     /* fusion, hole filling, edges, borders (Sec. 3.4, Eq. 11) */
     int16_t* dinit = (int16_t*)malloc(plane * sizeof(int16_t));
@@ -435,23 +476,23 @@ int lfo_depth(const float* views, int S, int T, int H, int W, const float* hyp, 
         memcpy(dinit, tmp, plane * sizeof(int16_t));
     }
     uint8_t* edge = (uint8_t*)malloc(plane);
-    lfo_edges(ref, H, W, prm->alpha, prm->edge_tau, edge);
+    lfo_edges(ref, C, H, W, prm->alpha, prm->edge_tau, edge);
     int16_t* lo = (int16_t*)malloc(plane * sizeof(int16_t));
     int16_t* hi = (int16_t*)malloc(plane * sizeof(int16_t));
-    lfo_borders(dinit, edge, H, W, N, prm->lambda, lo, hi);
+    lfo_borders(dinit, edge, H, W, N, prm->lambda, prm->lambda_far, lo, hi);
 
     /* Sec. 3.5: bounded cost over all views (Eq. 12 or Eq. 15), bounded SGM, WTA */
     memset(cost, 0, vol * sizeof(int32_t));
     if (prm->cost_kind == 0) {
         float* s32 = (float*)malloc(vol * sizeof(float));
-        lfo_cost_l2_f32(views, S, T, H, W, hyp, N, lo, hi, s32);
+        lfo_cost_l2_f32(views, S, T, C, H, W, hyp, N, lo, hi, s32);
         lfo_quantize(s32, H, W, N, lo, hi, prm->alpha, prm->cost_cap, cost);
         free(s32);
     } else {
-        uint64_t* call = (uint64_t*)malloc((size_t)S * T * plane * sizeof(uint64_t));
-        for (int v = 0; v < S * T; ++v)
+        uint64_t* call = (uint64_t*)malloc((size_t)S * T * C * plane * sizeof(uint64_t));
+        for (int v = 0; v < S * T * C; ++v)
             lfo_census(views + (size_t)v * plane, H, W, prm->win_h, prm->win_w, call + (size_t)v * plane);
-        lfo_cost_census_all(call, S, T, H, W, hyp, N, lo, hi, prm->cost_cap, cost);
+        lfo_cost_census_all(call, S, T, C, H, W, hyp, N, lo, hi, prm->cost_cap, cost);
         free(call);
     }
     lfo_sgm(cost, lo, hi, H, W, N, prm->P1_final, prm->P2_final, prm->npaths, csum);

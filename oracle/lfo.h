@@ -79,27 +79,37 @@ void lfo_fuse(const int16_t* maps, int nv, int H, int W, int phi, int16_t* dinit
 void lfo_fill(const int16_t* in, int H, int W, int16_t* out);
 
 /* Sobel edge mask on the reference view (Sec. 3.4): G = |Gx| + |Gy| of the 3x3
- * Sobel operator, clamp-to-edge, float32; edge iff alpha*G > tau. */
-void lfo_edges(const float* ref, int H, int W, float alpha, float tau, uint8_t* edge);
+ * Sobel operator, clamp-to-edge, float32; edge iff alpha*G > tau.  ref: C planes;
+ * colour takes the largest G over the channels. */
+void lfo_edges(const float* ref, int C, int H, int W, float alpha, float tau, uint8_t* edge);
 
 /* Borders, Eq. (11): valid, non-edge pixel: lo = max(0, D_init - lambda),
  * hi = min(N-1, D_init + lambda); invalid or edge pixel: the full range.
  * lambda < 0 selects the boundary-less search (Sec. 4.5): the full range for
  * every pixel (the initial map is then unused). */
 void lfo_borders(const int16_t* dinit, const uint8_t* edge, int H, int W, int N,
-                 int lambda, int16_t* lo, int16_t* hi);
+                 int lambda, int lambda_far, int16_t* lo, int16_t* hi);
+
+/* Border half-width at initial index d (Sec. 4.6, adaptive by depth): lambda_far
+ * at k = 0 (the smallest disparity, the farthest point) falling linearly to
+ * lambda at k = N-1, rounded half up; lambda_far <= lambda keeps lambda. */
+int lfo_border_width(int lambda, int lambda_far, int d, int N);
 
 /* Bounded l2 matching cost over all views, Eq. (12), in double precision:
  * S(p,k) = sum_t sum_s |L_ref(p) - B_{s,t}(u + cs*d_k, v + ct*d_k)| with B the
- * bilinear interpolation of view (s,t), taps clamped to the image. */
-void lfo_cost_l2_f64(const float* views, int S, int T, int H, int W, const float* hyp,
+ * bilinear interpolation of view (s,t), taps clamped to the image.  views:
+ * [T][S][C][H][W]; with C > 1 channels the term is the l2 norm of the colour
+ * difference, sqrt(sum_c (ref_c - B_c)^2). */
+void lfo_cost_l2_f64(const float* views, int S, int T, int C, int H, int W, const float* hyp,
                      int N, const int16_t* lo, const int16_t* hi, double* out);
 
 /* The same sum in float32, in the order t outer, s inner, starting from +0:
  * shift sh = (float)cs * d_k rounded once, x0 = floor(sh), fx = sh - x0 (exact);
  * top = fma(fx, b-a, a), bot = fma(fx, e-c, c), val = fma(fy, bot-top, top);
- * acc += |ref - val|.  This is the precision the quantised cost is decided in. */
-void lfo_cost_l2_f32(const float* views, int S, int T, int H, int W, const float* hyp,
+ * acc += |ref - val| (C = 1) or, with dl_c = ref_c - val_c,
+ * acc += sqrtf(fma(dl_2, dl_2, fma(dl_1, dl_1, dl_0 * dl_0))) (C = 3).  This is the
+ * precision the quantised cost is decided in. */
+void lfo_cost_l2_f32(const float* views, int S, int T, int C, int H, int W, const float* hyp,
                      int N, const int16_t* lo, const int16_t* hi, float* out);
 
 /* Quantisation to the integer SGM domain: C = min(rint(alpha*S), cap), with the
@@ -108,8 +118,9 @@ void lfo_quantize(const float* s, int H, int W, int N, const int16_t* lo,
                   const int16_t* hi, float alpha, int32_t cap, int32_t* cost);
 
 /* Census cost over all views, Eq. (15): S(p,k) = sum_t sum_s HD(Lc_ref(p),
- * Lc_{s,t}(p + rounded shift)), then C = min(S, cap).  census_all: [T][S][H][W]. */
-void lfo_cost_census_all(const uint64_t* census_all, int S, int T, int H, int W,
+ * Lc_{s,t}(p + rounded shift)), then C = min(S, cap).  census_all: [T][S][C][H][W];
+ * colour: the Hamming distances of the C channels are summed. */
+void lfo_cost_census_all(const uint64_t* census_all, int S, int T, int C, int H, int W,
                          const float* hyp, int N, const int16_t* lo, const int16_t* hi,
                          int32_t cap, int32_t* cost);
 
@@ -135,6 +146,8 @@ typedef struct {
     int P1_final, P2_final;   /* SGM penalties, final stage */
     int npaths;               /* 8 or 16 */
     int phi, lambda, fill_passes;
+    int lambda_far;           /* adaptive border (Sec. 4.6); <= lambda: off */
+    int channels;             /* planes per view: 1 (grayscale) or 3 (colour) */
     float edge_tau;           /* +inf disables the edge exclusion */
     float alpha;              /* cost scale to 8-bit units */
     int cost_kind;            /* 0 = l2 (Eq. 12), 1 = Census (Eq. 15) */

@@ -474,3 +474,90 @@ def test_boundless_search_equals_bounds_wider_than_the_range():
     k = int(np.argmin(np.abs(hyp - 1)))
     m = 8
     assert (b["d_index"][m:-m, m:-m] == k).all()
+
+
+# ------------------------------------------------ adaptive borders (Sec. 4.6)
+def test_adaptive_border_width_hand_cases():
+    # lambda_far at k = 0 (the farthest point) down to lambda at k = N-1, linear in
+    # the index, rounded half up; lambda_far <= lambda keeps lambda everywhere
+    N = 101
+    assert [lfo.border_width(3, 7, d, N) for d in (0, 25, 50, 87, 88, 100)] == [7, 6, 5, 4, 3, 3]
+    assert [lfo.border_width(3, 3, d, N) for d in (0, 50, 100)] == [3, 3, 3]
+    assert [lfo.border_width(3, 2, d, N) for d in (0, 100)] == [3, 3]
+    dinit = np.array([[0, 50, 100, -1]], np.int16)
+    lo, hi = lfo.borders(dinit, None, N, 3, 7)
+    assert lo.tolist() == [[0, 45, 97, 0]] and hi.tolist() == [[7, 55, 100, 100]]
+
+
+def test_adaptive_borders_contain_the_constant_ones():
+    # a wider border never drops a hypothesis the constant one keeps
+    rng_ = np.random.default_rng(3)
+    dinit = rng_.integers(-1, 64, size=(9, 11)).astype(np.int16)
+    lo0, hi0 = lfo.borders(dinit, None, 64, 2)
+    lo1, hi1 = lfo.borders(dinit, None, 64, 2, 9)
+    assert (lo1 <= lo0).all() and (hi1 >= hi0).all()
+
+
+# ------------------------------------------------------- colour (Sec. 3.2)
+def test_colour_census_cost_sums_the_channels():
+    # three identical channels: every Hamming distance counts three times
+    S = T = 3
+    views = _shifted_lf(S, T, 14, 17, 1, seed=4)
+    hyp = lfsynth.hypotheses(-2, 2, 9)
+    gray = np.stack([[lfo.census(views[t, s], 5, 5) for s in range(S)] for t in range(T)])
+    colour = np.stack([gray] * 3, axis=2)                        # [T][S][C][H][W]
+    a = lfo.cost_census_all(gray, hyp, 1 << 20)
+    b = lfo.cost_census_all(colour, hyp, 1 << 20)
+    assert np.array_equal(b, 3 * a)
+
+
+def test_colour_l2_with_constant_extra_channels_equals_gray():
+    # channels (g, c1, c2) with c1, c2 constant in every view: their differences are
+    # exactly 0 and sqrt(x*x) == |x| in IEEE arithmetic, so the colour cost is the
+    # gray one bit for bit (float32) and to the last place (float64)
+    views = _shifted_lf(3, 5, 18, 21, -1, seed=5) / 255.0
+    colour = np.stack([views, np.full_like(views, 0.25), np.full_like(views, 0.75)], axis=2)
+    hyp = np.array([-1.6, -1.0, -0.35, 0.8], np.float32)
+    assert np.array_equal(lfo.cost_l2_f32(colour, hyp), lfo.cost_l2_f32(views, hyp))
+    assert np.array_equal(lfo.cost_l2_f64(colour, hyp), lfo.cost_l2_f64(views, hyp))
+
+
+def test_colour_l2_linear_ramp_closed_form():
+    # channel c is a_c*u + b_c on a plane at d*: every view's colour difference is
+    # (s_hat-s)(d - d*) * (a_0, a_1, a_2), so S(d) = |a| |d - d*| T sum_s |s_hat-s|
+    S, T, H, W = 5, 3, 16, 40
+    a = np.array([0.01, -0.004, 0.007])
+    b = np.array([0.2, 0.6, 0.4])
+    dstar = 0.3
+    sh = (S - 1) // 2
+    xx = np.broadcast_to(np.arange(W, dtype=np.float64), (H, W))
+    views = np.empty((T, S, 3, H, W), np.float32)
+    for t in range(T):
+        for s in range(S):
+            for c in range(3):
+                views[t, s, c] = a[c] * (xx - (sh - s) * dstar) + b[c]
+    hyp = np.array([-1.1, 0.3, 0.55, 1.2], np.float32)
+    closed = np.linalg.norm(a) * np.abs(hyp.astype(np.float64) - dstar) * T * \
+        sum(abs(sh - s) for s in range(S))
+    s64 = lfo.cost_l2_f64(views, hyp)[:, 6:-6]
+    s32 = lfo.cost_l2_f32(views, hyp)[:, 6:-6]
+    np.testing.assert_allclose(s64, np.broadcast_to(closed, s64.shape), rtol=0, atol=5e-6)
+    np.testing.assert_allclose(s32, np.broadcast_to(closed, s32.shape), rtol=0, atol=5e-5)
+
+
+def test_colour_depth_recovers_integer_plane_and_gray_channels_match_gray_maps():
+    S = T = 5
+    H, W = 36, 40
+    g = _shifted_lf(S, T, H, W, 1, seed=13)
+    r = _shifted_lf(S, T, H, W, 1, seed=14)
+    colour = np.stack([g, r, 255.0 - g], axis=2)
+    hyp = lfsynth.hypotheses(-2, 2, 17)
+    prm = lfsynth._params(census=(3, 3), p_init=(10, 40), p_final=(10, 40))
+    out = lfo.depth(colour, hyp, prm, want_intermediates=True)
+    k = int(np.argmin(np.abs(hyp - 1)))
+    m = 8
+    assert (out["d_index"][m:-m, m:-m] == k).all()
+    # the Sobel mask of identical channels is the gray one
+    e1 = lfo.edges(g[2, 2], 1.0, 200.0)
+    e3 = lfo.edges(np.stack([g[2, 2]] * 3), 1.0, 200.0)
+    assert np.array_equal(e1, e3)
