@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define LF_ABI_VERSION 2
+#define LF_ABI_VERSION 3
 #define LF_MAX_HYPOTHESES 256
 
 typedef enum {
@@ -63,10 +63,13 @@ typedef enum { LF_COST_L2 = 0, LF_COST_CENSUS = 1 } lf_cost_kind;
 
 /* A light field resident in device memory. */
 typedef struct {
-    const void* data;   /* [T][S][H][pitch] elements of `dtype` */
+    const void* data;   /* [T][S][C][H][pitch] elements of `dtype` */
     int32_t S, T, H, W;
-    int32_t pitch;      /* elements between rows, >= W; views are H*pitch apart */
+    int32_t pitch;      /* elements between rows, >= W; planes are H*pitch apart */
     int32_t dtype;      /* lf_dtype */
+    int32_t channels;   /* C: 1 (or 0) grayscale, 3 colour (Sec. 3.3: Census per
+                           channel with the Hamming distances summed; the l2 cost
+                           is the Euclidean norm of the colour difference) */
 } lf_view_set;
 
 /* Census window, Sec. 3.2 Eq. (2): win_h rows x win_w columns, both odd and at
@@ -97,6 +100,11 @@ typedef struct {
     int32_t cost_kind;         /* lf_cost_kind of the final stage */
     int32_t median;            /* 0: off, 3: 3x3 median of the final map */
     int32_t sum_bits;          /* 16 or 32: width of the final aggregated cost */
+    int32_t lambda_far;        /* depth-adaptive border (Sec. 4.6): if > lambda, the
+                                  half-width is lambda_far at index 0 (the smallest
+                                  disparity) falling linearly to lambda at N-1,
+                                  lambda + ((lambda_far-lambda)(N-1-d) + (N-1)/2)/(N-1);
+                                  0 (or <= lambda): lambda everywhere */
 } lf_params;
 
 /* ------------------------------------------------------------ utilities */
@@ -138,9 +146,9 @@ const char* lf_profile_stage_name(int32_t i);
 lf_status lf_census(const void* img, int32_t dtype, int32_t H, int32_t W, int32_t pitch,
                     lf_census_window win, uint64_t* out, hipStream_t stream);
 
-/* Bytes of workspace lf_initial_disparity needs. */
-size_t lf_initial_workspace_size(int32_t S, int32_t T, int32_t H, int32_t W, int32_t N,
-                                 const lf_params* prm);
+/* Bytes of workspace lf_initial_disparity needs (C: channels, 1 or 3). */
+size_t lf_initial_workspace_size(int32_t S, int32_t T, int32_t C, int32_t H, int32_t W,
+                                 int32_t N, const lf_params* prm);
 
 /* Initial disparity map and borders, Sec. 3.4:
  *  1. Census of the reference and cross views;
@@ -161,8 +169,8 @@ lf_status lf_initial_disparity(const lf_view_set* views, const float* hyp, int32
 
 /* Bytes of workspace lf_cost_volume_bounded needs (prefix-sum scratch, and the
  * Census strings of every view for LF_COST_CENSUS). */
-size_t lf_cost_workspace_size(int32_t S, int32_t T, int32_t H, int32_t W, int32_t N,
-                              const lf_params* prm);
+size_t lf_cost_workspace_size(int32_t S, int32_t T, int32_t C, int32_t H, int32_t W,
+                              int32_t N, const lf_params* prm);
 
 /* Bounded matching cost over all views, Sec. 3.5:
  *  offsets <- exclusive prefix sum of the widths d_hi - d_lo + 1 ([H*W+1] int64);
@@ -222,8 +230,8 @@ lf_status lf_wta_subpixel(const void* csum, int32_t sum_bits, const int64_t* off
 
 /* Bytes of workspace lf_depth needs (every stage's buffers, including a
  * worst-case H*W*N bounded volume). */
-size_t lf_depth_workspace_size(int32_t S, int32_t T, int32_t H, int32_t W, int32_t N,
-                               const lf_params* prm);
+size_t lf_depth_workspace_size(int32_t S, int32_t T, int32_t C, int32_t H, int32_t W,
+                               int32_t N, const lf_params* prm);
 
 /* The whole method on one light field: lf_initial_disparity ->
  * lf_cost_volume_bounded -> lf_sgm_aggregate -> lf_wta_subpixel.

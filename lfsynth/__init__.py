@@ -103,7 +103,7 @@ class Scene:
 
 @dataclasses.dataclass
 class LightField:
-    views: np.ndarray          # [T][S][H][W], uint8 or float32
+    views: np.ndarray          # [T][S][H][W] or [T][S][C][H][W], uint8 or float32
     hyp: np.ndarray            # [N] float32, strictly increasing
     gt: np.ndarray             # [H][W] float32 ground-truth disparity (reference view)
     params: dict               # method parameters for this workload
@@ -118,12 +118,16 @@ class LightField:
         return self.views.shape[0]
 
     @property
+    def C(self):
+        return 1 if self.views.ndim == 4 else self.views.shape[2]
+
+    @property
     def H(self):
-        return self.views.shape[2]
+        return self.views.shape[-2]
 
     @property
     def W(self):
-        return self.views.shape[3]
+        return self.views.shape[-1]
 
     @property
     def N(self):
@@ -155,11 +159,22 @@ def _bilinear(raster, x, y):
 
 
 def render(scene: Scene, S: int, T: int, dtype=np.float32, noise_sigma=0.0, rng=None):
-    """Render all S x T views of a plane scene; returns (views[T][S][H][W], gt[H][W]).
+    """Render all S x T views of a plane scene; returns (views[T][S][H][W], gt[H][W]),
+    or views[T][S][C][H][W] when the textures have C channels ([C][rows][cols]).
 
     uint8 output takes texture values in 0..255 units (rounded half to even); float32
     output takes them in [0, 1].
     """
+    tex0 = scene.planes[0].texture
+    if tex0.ndim == 3:                           # colour: one pass per channel plane
+        planes = []
+        gt = None
+        for c in range(tex0.shape[0]):
+            sc = Scene(scene.H, scene.W, [dataclasses.replace(pl, texture=pl.texture[c])
+                                          for pl in scene.planes])
+            v, gt = render(sc, S, T, dtype, noise_sigma, rng)
+            planes.append(v)
+        return np.ascontiguousarray(np.stack(planes, axis=2)), gt
     H, W = scene.H, scene.W
     sh, th = (S - 1) / 2.0, (T - 1) / 2.0
     yy, xx = np.meshgrid(np.arange(H, dtype=np.float64), np.arange(W, dtype=np.float64),
@@ -244,9 +259,16 @@ def _perlin_texture(rng, H, W, margin):
     return np.clip(0.5 + 0.35 * f + 0.15 * (noise - 0.5), 0.0, 1.0)
 
 
-def slanted_scene(seed, H, W, d_min, d_max, n_planes=12, S=9, T=9):
-    """Background plane plus (n_planes - 1) slanted elliptical planes, Perlin+noise textures."""
+def slanted_scene(seed, H, W, d_min, d_max, n_planes=12, S=9, T=9, channels=1):
+    """Background plane plus (n_planes - 1) slanted elliptical planes, Perlin+noise textures
+    (channels = 3: an independent texture per colour channel)."""
     rng = np.random.default_rng(seed)
+
+    def texture():
+        if channels == 1:
+            return _perlin_texture(rng, H, W, margin)
+        return np.stack([_perlin_texture(rng, H, W, margin) for _ in range(channels)])
+
     span = d_max - d_min
     margin = int(np.ceil(max(S, T) / 2.0 * max(abs(d_min), abs(d_max)))) + 3
     planes = []
@@ -255,7 +277,7 @@ def slanted_scene(seed, H, W, d_min, d_max, n_planes=12, S=9, T=9):
     room = min(a0 - d_min, d_max - a0)
     b0, c0 = rng.uniform(-1, 1, size=2) * room / (W + H)
     planes.append(Plane(a=a0, b=b0, c=c0, uc=W / 2.0, vc=H / 2.0,
-                        texture=_perlin_texture(rng, H, W, margin), margin=margin))
+                        texture=texture(), margin=margin))
     scale = min(H, W) / 512.0
     for _ in range(n_planes - 1):
         uc, vc = rng.uniform(0, W), rng.uniform(0, H)
@@ -268,7 +290,7 @@ def slanted_scene(seed, H, W, d_min, d_max, n_planes=12, S=9, T=9):
             f = room / reach if reach > 0 else 0.0
             b, c = b * f, c * f
         planes.append(Plane(a=a, b=b, c=c, uc=uc, vc=vc, ax=ax, ay=ay,
-                            texture=_perlin_texture(rng, H, W, margin), margin=margin))
+                            texture=texture(), margin=margin))
     return Scene(H, W, planes)
 
 
@@ -289,8 +311,9 @@ def _small_plain(seed=1, H=96, W=96, S=5, T=5, N=32):
     return LightField(views, hypotheses(-2.0, 2.0, N), gt, _params(), name="lf5x5_96_u8")
 
 
-def _paper_shape(seed=2, H=512, W=512, S=9, T=9, N=100, d_min=-4.0, d_max=4.0, noise=0.0):
-    scene = slanted_scene(seed, H, W, d_min, d_max, S=S, T=T)
+def _paper_shape(seed=2, H=512, W=512, S=9, T=9, N=100, d_min=-4.0, d_max=4.0, noise=0.0,
+                 channels=1):
+    scene = slanted_scene(seed, H, W, d_min, d_max, S=S, T=T, channels=channels)
     rng = np.random.default_rng(seed + 7919)
     views, gt = render(scene, S, T, dtype=np.float32, noise_sigma=noise, rng=rng)
     p = _params(census=(7, 9), p_init=(21, 45), p_final=(17, 35), lam=3, phi=3, fill=2,

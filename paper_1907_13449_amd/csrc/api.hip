@@ -148,8 +148,12 @@ lf_status check_views(const lf_view_set* v) {
     if (!v->data) return fail(LF_EINVAL, "views->data is NULL");
     if (v->dtype != LF_U8 && v->dtype != LF_F32) return fail(LF_EINVAL, "dtype %d", v->dtype);
     if (v->pitch < v->W) return fail(LF_EINVAL, "pitch %d < W %d", v->pitch, v->W);
+    if (v->channels != 0 && v->channels != 1 && v->channels != 3)
+        return fail(LF_EINVAL, "channels=%d (1 or 3)", v->channels);
     return LF_OK;
 }
+
+int channels_of(const lf_view_set* v) { return v->channels == 3 ? 3 : 1; }
 
 lf_status check_window(lf_census_window w) {
     if (w.win_h < 1 || w.win_w < 1 || w.win_h % 2 == 0 || w.win_w % 2 == 0)
@@ -180,9 +184,10 @@ lf_status check_params(const lf_params* p) {
     LF_CHECK(check_window(p->census));
     LF_CHECK(check_sgm(p->sgm_init, "initial"));
     LF_CHECK(check_sgm(p->sgm_final, "final"));
-    if (p->sgm_init.npaths * (64 + p->sgm_init.P2) > 65535)
+    if (p->sgm_init.npaths * (3 * 64 + p->sgm_init.P2) > 65535)
         return fail(LF_EINVAL, "initial P2=%d overflows the 16-bit aggregated Census cost",
                     p->sgm_init.P2);
+    if (p->lambda_far < 0) return fail(LF_EINVAL, "lambda_far=%d (need >= 0)", p->lambda_far);
     if (p->phi < 1) return fail(LF_EINVAL, "phi=%d (need >= 1)", p->phi);
     if (p->lambda < -1) return fail(LF_EINVAL, "lambda=%d (need >= 0, or -1: no bounds)", p->lambda);
     if (p->fill_passes < 0 || p->fill_passes > 8)
@@ -199,28 +204,25 @@ lf_status check_params(const lf_params* p) {
     return LF_OK;
 }
 
-const void* view_ptr(const lf_view_set* v, int s, int t) {
-    const size_t elem = v->dtype == LF_U8 ? 1 : 4;
-    return (const char*)v->data + ((size_t)t * v->S + s) * v->H * v->pitch * elem;
-}
+
 
 // Workspace plans -----------------------------------------------------------
 struct InitPlan {
-    uint64_t* census;     // [1 + nv][HW]
+    uint64_t* census;     // [1 + nv][C][HW]
     void* paths;          // per-direction path costs of the SGM
     int16_t* maps;        // [nv][HW]
     int16_t* tmp;         // [HW]
 };
 
-size_t plan_initial(Carve& c, int S, int T, int H, int W, int N, const lf_params* prm,
+size_t plan_initial(Carve& c, int S, int T, int C, int H, int W, int N, const lf_params* prm,
                     InitPlan* p) {
     int st[8];
     const int nv = lf::cross_views(S, T, st);
     const size_t HW = (size_t)H * W;
     InitPlan q;
-    q.census = (uint64_t*)c.take((1 + nv) * HW * sizeof(uint64_t));
+    q.census = (uint64_t*)c.take((1 + nv) * C * HW * sizeof(uint64_t));
     q.paths = c.take(lf::sgm_dense_scratch_bytes(nv, H, W, N, prm->sgm_init.npaths,
-                                                 prm->census.win_h * prm->census.win_w - 1,
+                                                 C * (prm->census.win_h * prm->census.win_w - 1),
                                                  prm->sgm_init.P2));
     q.maps = (int16_t*)c.take(nv * HW * sizeof(int16_t));
     q.tmp = (int16_t*)c.take(HW * sizeof(int16_t));
@@ -230,18 +232,21 @@ size_t plan_initial(Carve& c, int S, int T, int H, int W, int N, const lf_params
 
 struct CostPlan {
     void* scan;           // prefix-sum scratch
-    uint64_t* census_all; // [S*T][HW] (Census kind only)
-    void* padded;         // [S*T][H+2][W+2] edge-replicated views (l2 kind only)
+    uint64_t* census_all; // [S*T][C][HW] (Census kind only)
+    void* padded;         // [S*T][C][H+2][W+2] edge-replicated views (l2 kind only)
 };
 
-size_t plan_cost(Carve& c, int S, int T, int H, int W, const lf_params* prm, CostPlan* p) {
+size_t plan_cost(Carve& c, int S, int T, int C, int H, int W, const lf_params* prm,
+                 CostPlan* p) {
     const size_t HW = (size_t)H * W;
     CostPlan q;
     q.scan = c.take(lf::scan_scratch_bytes((int64_t)HW));
     const bool census = prm && prm->cost_kind == LF_COST_CENSUS;
-    q.census_all = census ? (uint64_t*)c.take((size_t)S * T * HW * sizeof(uint64_t)) : nullptr;
+    q.census_all =
+        census ? (uint64_t*)c.take((size_t)S * T * C * HW * sizeof(uint64_t)) : nullptr;
     // sized for float32 views (uint8 ones use a quarter of it)
-    q.padded = census ? nullptr : c.take((size_t)S * T * (H + 2) * (W + 2) * sizeof(float));
+    q.padded =
+        census ? nullptr : c.take((size_t)S * T * C * (H + 2) * (W + 2) * sizeof(float));
     if (p) *p = q;
     return c.used;
 }
@@ -260,7 +265,7 @@ struct DepthPlan {
     size_t sgm_bytes;
 };
 
-size_t plan_depth(void* base, int S, int T, int H, int W, int N, const lf_params* prm,
+size_t plan_depth(void* base, int S, int T, int C, int H, int W, int N, const lf_params* prm,
                   DepthPlan* p) {
     Carve c(base);
     const size_t HW = (size_t)H * W, cells = HW * N;
@@ -275,8 +280,8 @@ size_t plan_depth(void* base, int S, int T, int H, int W, int N, const lf_params
     q.pre_median = (float*)c.take(lf_wta_workspace_size(H, W));
     // the initial and the cost stage never run at once: they share one region
     Carve ci(nullptr), cc(nullptr);
-    q.init_bytes = plan_initial(ci, S, T, H, W, N, prm, nullptr);
-    q.cost_bytes = plan_cost(cc, S, T, H, W, prm, nullptr);
+    q.init_bytes = plan_initial(ci, S, T, C, H, W, N, prm, nullptr);
+    q.cost_bytes = plan_cost(cc, S, T, C, H, W, prm, nullptr);
     q.sgm_bytes = lf_sgm_workspace_size(H, W, N, prm->sgm_final.npaths);
     size_t shared = q.init_bytes > q.cost_bytes ? q.init_bytes : q.cost_bytes;
     if (q.sgm_bytes > shared) shared = q.sgm_bytes;
@@ -296,7 +301,8 @@ lf_status check_initial_size(int H, int W, int N) {
 }
 
 lf_status check_views_size(const lf_view_set* v) {
-    const int64_t bytes = (int64_t)v->S * v->T * v->H * v->pitch * (v->dtype == LF_U8 ? 1 : 4);
+    const int64_t bytes = (int64_t)v->S * v->T * channels_of(v) * v->H * v->pitch *
+                          (v->dtype == LF_U8 ? 1 : 4);
     if (bytes >= ((int64_t)1 << 31))
         return fail(LF_EUNSUPPORTED, "light field of %lld bytes (max 2 GiB)", (long long)bytes);
     return LF_OK;
@@ -311,7 +317,8 @@ lf_status check_depth_args(const lf_view_set* views, const float* hyp, int N,
     LF_CHECK(check_initial_size(views->H, views->W, N));
     LF_CHECK(check_views_size(views));
     if (!hyp || !disparity || !ws) return fail(LF_EINVAL, "NULL argument");
-    const size_t need = plan_depth(nullptr, views->S, views->T, views->H, views->W, N, prm, nullptr);
+    const size_t need = plan_depth(nullptr, views->S, views->T, channels_of(views), views->H,
+                                   views->W, N, prm, nullptr);
     if (ws_bytes < need) return fail(LF_ENOSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
     if ((uintptr_t)ws % kAlign) return fail(LF_EINVAL, "workspace not 256-byte aligned");
     return LF_OK;
@@ -327,6 +334,7 @@ lf::Job base_job(const lf_view_set* v, const float* hyp, int N, const lf_params*
     j.H = v->H;
     j.W = v->W;
     j.pitch = v->pitch;
+    j.C = channels_of(v);
     j.N = N;
     j.hyp = hyp;
     j.prm = *prm;
@@ -340,14 +348,15 @@ lf::Job base_job(const lf_view_set* v, const float* hyp, int N, const lf_params*
 lf::Job depth_job(const lf_view_set* v, const float* hyp, int N, const lf_params* prm,
                   float* disparity, int16_t* d_index, void* ws) {
     DepthPlan pl;
-    plan_depth(ws, v->S, v->T, v->H, v->W, N, prm, &pl);
+    const int C = channels_of(v);
+    plan_depth(ws, v->S, v->T, C, v->H, v->W, N, prm, &pl);
     lf::Job j = base_job(v, hyp, N, prm);
     Carve ci(pl.init_ws);
     InitPlan ip;
-    plan_initial(ci, v->S, v->T, v->H, v->W, N, prm, &ip);
+    plan_initial(ci, v->S, v->T, C, v->H, v->W, N, prm, &ip);
     Carve cc(pl.cost_ws);
     CostPlan cp;
-    plan_cost(cc, v->S, v->T, v->H, v->W, prm, &cp);
+    plan_cost(cc, v->S, v->T, C, v->H, v->W, prm, &cp);
     j.census = ip.census;
     j.paths = ip.paths;
     j.maps = ip.maps;
@@ -498,12 +507,12 @@ lf_status lf_census(const void* img, int32_t dtype, int32_t H, int32_t W, int32_
     return LF_OK;
 }
 
-size_t lf_initial_workspace_size(int32_t S, int32_t T, int32_t H, int32_t W, int32_t N,
-                                 const lf_params* prm) {
+size_t lf_initial_workspace_size(int32_t S, int32_t T, int32_t C, int32_t H, int32_t W,
+                                 int32_t N, const lf_params* prm) {
     if (S < 1 || T < 1 || H < 1 || W < 1 || N < 1) return 0;
-    if (!prm) return 0;
+    if (!prm || (C != 1 && C != 3)) return 0;
     Carve c(nullptr);
-    return plan_initial(c, S, T, H, W, N, prm, nullptr);
+    return plan_initial(c, S, T, C, H, W, N, prm, nullptr);
 }
 
 lf_status lf_initial_disparity(const lf_view_set* views, const float* hyp, int32_t N,
@@ -517,12 +526,13 @@ lf_status lf_initial_disparity(const lf_view_set* views, const float* hyp, int32
     if (!hyp || !d_init || !d_lo || !d_hi || !ws) return fail(LF_EINVAL, "NULL argument");
     const int S = views->S, T = views->T, H = views->H, W = views->W;
     Carve sizer(nullptr);
-    const size_t need = plan_initial(sizer, S, T, H, W, N, prm, nullptr);
+    const int C = channels_of(views);
+    const size_t need = plan_initial(sizer, S, T, C, H, W, N, prm, nullptr);
     if (ws_bytes < need) return fail(LF_ENOSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
     if ((uintptr_t)ws % kAlign) return fail(LF_EINVAL, "workspace not 256-byte aligned");
     Carve c(ws);
     InitPlan pl;
-    plan_initial(c, S, T, H, W, N, prm, &pl);
+    plan_initial(c, S, T, C, H, W, N, prm, &pl);
 
     lf::Job j = base_job(views, hyp, N, prm);
     j.census = pl.census;
@@ -538,12 +548,12 @@ lf_status lf_initial_disparity(const lf_view_set* views, const float* hyp, int32
     return LF_OK;
 }
 
-size_t lf_cost_workspace_size(int32_t S, int32_t T, int32_t H, int32_t W, int32_t N,
-                              const lf_params* prm) {
+size_t lf_cost_workspace_size(int32_t S, int32_t T, int32_t C, int32_t H, int32_t W,
+                              int32_t N, const lf_params* prm) {
     (void)N;
-    if (S < 1 || T < 1 || H < 1 || W < 1) return 0;
+    if (S < 1 || T < 1 || H < 1 || W < 1 || (C != 1 && C != 3)) return 0;
     Carve c(nullptr);
-    return plan_cost(c, S, T, H, W, prm, nullptr);
+    return plan_cost(c, S, T, C, H, W, prm, nullptr);
 }
 
 lf_status lf_cost_volume_bounded(const lf_view_set* views, const float* hyp, int32_t N,
@@ -563,12 +573,13 @@ lf_status lf_cost_volume_bounded(const lf_view_set* views, const float* hyp, int
         return fail(LF_ENOSPACE, "cap_cells %lld < H*W*N = %lld", (long long)cap_cells,
                     (long long)(HW * N));
     Carve sizer(nullptr);
-    const size_t need = plan_cost(sizer, S, T, H, W, prm, nullptr);
+    const int C = channels_of(views);
+    const size_t need = plan_cost(sizer, S, T, C, H, W, prm, nullptr);
     if (ws_bytes < need) return fail(LF_ENOSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
     if ((uintptr_t)ws % kAlign) return fail(LF_EINVAL, "workspace not 256-byte aligned");
     Carve c(ws);
     CostPlan pl;
-    plan_cost(c, S, T, H, W, prm, &pl);
+    plan_cost(c, S, T, C, H, W, prm, &pl);
 
     lf::Job j = base_job(views, hyp, N, prm);
     j.lo = const_cast<int16_t*>(d_lo);
@@ -667,10 +678,10 @@ lf_status lf_wta_subpixel(const void* csum, int32_t sum_bits, const int64_t* off
     return LF_OK;
 }
 
-size_t lf_depth_workspace_size(int32_t S, int32_t T, int32_t H, int32_t W, int32_t N,
-                               const lf_params* prm) {
-    if (!prm || S < 1 || T < 1 || H < 1 || W < 1 || N < 1) return 0;
-    return plan_depth(nullptr, S, T, H, W, N, prm, nullptr);
+size_t lf_depth_workspace_size(int32_t S, int32_t T, int32_t C, int32_t H, int32_t W,
+                               int32_t N, const lf_params* prm) {
+    if (!prm || S < 1 || T < 1 || H < 1 || W < 1 || N < 1 || (C != 1 && C != 3)) return 0;
+    return plan_depth(nullptr, S, T, C, H, W, N, prm, nullptr);
 }
 
 lf_status lf_depth(const lf_view_set* views, const float* hyp, int32_t N, const lf_params* prm,
@@ -703,8 +714,8 @@ lf_status validate_request(const lf_request* q, size_t ws_bytes, const void* ws)
 }
 
 size_t request_workspace_bytes(const lf_request* q) {
-    return lf_depth_workspace_size(q->views.S, q->views.T, q->views.H, q->views.W, q->N,
-                                   &q->params);
+    return lf_depth_workspace_size(q->views.S, q->views.T, channels_of(&q->views), q->views.H,
+                                   q->views.W, q->N, &q->params);
 }
 
 Job request_job(const lf_request* q, void* ws) {

@@ -114,19 +114,25 @@ hipError_t census_image(Runner& r, const void* img, int dtype, int H, int W, int
 hipError_t stage_census(Runner& r, const Jobs& jobs, bool all_views) {
     std::vector<CensusArgs> by_type[2];
     for (const Job* j : jobs) {
-        const int64_t vs = (int64_t)j->H * j->pitch;
+        // a view is C planes of H x pitch; image z of the output is plane z % C of
+        // view z / C (reference first, then the cross views; or all views)
+        const int C = j->C;
+        const int64_t ps = (int64_t)j->H * j->pitch;            // plane stride
         CensusArgs a = census_args(j->views, j->H, j->W, j->pitch, j->prm.census.win_h,
                                    j->prm.census.win_w, all_views ? j->census_all : j->census);
         if (all_views) {
-            a.n = j->S * j->T;
-            a.stride = vs;
-            for (int z = 0; z < a.n && z < kMaxBatchImages; ++z) a.off[z] = z * vs;
+            a.n = j->S * j->T * C;
+            a.stride = ps;
+            for (int z = 0; z < a.n && z < kMaxBatchImages; ++z) a.off[z] = z * ps;
         } else {
             const int sh = (j->S - 1) / 2, th = (j->T - 1) / 2;
-            a.n = 1 + j->nv;
-            a.off[0] = ((int64_t)th * j->S + sh) * vs;
-            for (int i = 0; i < j->nv; ++i)
-                a.off[1 + i] = ((int64_t)j->st[2 * i + 1] * j->S + j->st[2 * i]) * vs;
+            a.n = (1 + j->nv) * C;                               // <= 5 * 3 images
+            for (int c = 0; c < C; ++c) {
+                a.off[c] = (((int64_t)th * j->S + sh) * C + c) * ps;
+                for (int i = 0; i < j->nv; ++i)
+                    a.off[(1 + i) * C + c] =
+                        (((int64_t)j->st[2 * i + 1] * j->S + j->st[2 * i]) * C + c) * ps;
+            }
         }
         by_type[j->dtype == LF_U8 ? 0 : 1].push_back(a);
     }

@@ -71,10 +71,10 @@ __device__ __forceinline__ Pair<T> ld_pair(const T* p) {
 // clamp(X, -1, W-1) + 1 -- one 8-byte load, no edge cases, and the same values
 // (so the same float32 sums) as clamping each tap.
 struct PadArgs {
-    const void* src;          // [views][H][pitch]
-    void* dst;                // [views][H+2][W+2]
+    const void* src;          // [planes][H][pitch] (a view is C planes)
+    void* dst;                // [planes][H+2][W+2]
     int H, W, pitch;
-    uint32_t per_view;        // blocks per view
+    uint32_t per_view;        // blocks per plane
 };
 
 template <class Src, typename T>
@@ -94,7 +94,7 @@ __global__ __launch_bounds__(kThreads) void pad_views_kernel(Src src) {
 }
 
 struct L2Args {
-    const void* views;        // padded: [T][S][H+2][W+2]
+    const void* views;        // padded: [T][S][C][H+2][W+2]
     const float* hyp;
     const int16_t* lo;
     const int64_t* off;       // [H*W + 1]
@@ -106,7 +106,7 @@ struct L2Args {
     uint32_t nblk;            // workgroups of this light field
 };
 
-template <typename T, int CPT, bool Walk>
+template <typename T, int CPT, bool Walk, int C>
 __device__ __forceinline__ void l2_slices(const L2Args& a, uint32_t b, int64_t* s_off, int* s_lo,
                                           int* s_p) {
     constexpr int kChunk = kThreads * CPT;
@@ -119,7 +119,7 @@ __device__ __forceinline__ void l2_slices(const L2Args& a, uint32_t b, int64_t* 
     const int sh = (S - 1) / 2, th = (T_ - 1) / 2;
     const uint32_t vstride = (uint32_t)(H + 2) * Wp;
     const T* __restrict__ views = (const T*)a.views;
-    const T* __restrict__ refv = views + ((size_t)th * S + sh) * vstride;
+    const T* __restrict__ refv = views + ((size_t)th * S + sh) * C * vstride;
 
     for (int64_t slice = b; slice * kChunk < total; slice += a.nblk) {   // uniform
         const int64_t c0 = slice * kChunk;
@@ -160,7 +160,10 @@ __device__ __forceinline__ void l2_slices(const L2Args& a, uint32_t b, int64_t* 
             const int k = s_lo[i] + (int)(c - s_off[i]);
             if ((unsigned)k >= (unsigned)N) continue;      // only for ranges outside [0, N)
             const float d = a.hyp[k];
-            const float ref = ld(refv + (uint32_t)(v + 1) * Wp + u + 1);
+            float ref[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+                ref[c] = ld(refv + (uint32_t)c * vstride + (uint32_t)(v + 1) * Wp + u + 1);
             float acc = 0.0f;
             for (int t = 0; t < T_; ++t) {
                 const float shy = (float)(th - t) * d;
@@ -168,20 +171,27 @@ __device__ __forceinline__ void l2_slices(const L2Args& a, uint32_t b, int64_t* 
                 const float fy = shy - y0;
                 // top tap row in padded coordinates; the bottom one follows it
                 const uint32_t rt = (uint32_t)(clampi(v + (int)y0, -1, H - 1) + 1) * Wp;
-                const T* __restrict__ vt = views + (size_t)t * S * vstride;
+                const T* __restrict__ vt = views + (size_t)t * S * C * vstride;
                 for (int s = 0; s < S; ++s) {
                     if (s == sh && t == th) continue;        // adds exactly +0
                     const float shx = (float)(sh - s) * d;
                     const float x0 = floorf(shx);
                     const float fx = shx - x0;
                     const uint32_t o = rt + (uint32_t)(clampi(u + (int)x0, -1, W - 1) + 1);
-                    const T* __restrict__ vs = vt + (uint32_t)s * vstride;
-                    const Pair<T> top = ld_pair(vs + o);
-                    const Pair<T> bot = ld_pair(vs + o + Wp);
-                    const float tv = fmaf(fx, top.hi - top.lo, top.lo);
-                    const float bv = fmaf(fx, bot.hi - bot.lo, bot.lo);
-                    const float val = fmaf(fy, bv - tv, tv);
-                    acc = acc + fabsf(ref - val);
+                    float sq = 0.0f, dist = 0.0f;
+#pragma unroll
+                    for (int c = 0; c < C; ++c) {
+                        const T* __restrict__ vs = vt + (uint32_t)(s * C + c) * vstride;
+                        const Pair<T> top = ld_pair(vs + o);
+                        const Pair<T> bot = ld_pair(vs + o + Wp);
+                        const float tv = fmaf(fx, top.hi - top.lo, top.lo);
+                        const float bv = fmaf(fx, bot.hi - bot.lo, bot.lo);
+                        const float val = fmaf(fy, bv - tv, tv);
+                        const float dl = ref[c] - val;
+                        dist = fabsf(dl);
+                        sq = c == 0 ? dl * dl : fmaf(dl, dl, sq);   // colour: l2 norm
+                    }
+                    acc = acc + (C == 1 ? dist : sqrtf(sq));
                 }
             }
             const float q = rintf(a.alpha * acc);
@@ -192,28 +202,28 @@ __device__ __forceinline__ void l2_slices(const L2Args& a, uint32_t b, int64_t* 
     }
 }
 
-template <class Src, typename T, int CPT, bool Walk>
+template <class Src, typename T, int CPT, bool Walk, int C>
 __global__ __launch_bounds__(kThreads) void cost_l2_kernel(Src src) {
     __shared__ int64_t s_off[kThreads * CPT + 1];
     __shared__ int s_lo[kThreads * CPT];
     __shared__ int s_p[2];
     uint32_t b;
     const L2Args& a = member(src, blockIdx.x, b);
-    l2_slices<T, CPT, Walk>(a, b, s_off, s_lo, s_p);
+    l2_slices<T, CPT, Walk, C>(a, b, s_off, s_lo, s_p);
 }
 
 // ---------------------------------------------------------------------------
 // Census kind, Eq. (15): 64 pixels per workgroup, their cells strided over the
 // threads.
 struct CensusAllArgs {
-    const uint64_t* census;   // [S*T][H*W]
+    const uint64_t* census;   // [S*T][C][H*W]
     const float* hyp;
     const int16_t* lo;
     const int64_t* off;
     uint16_t* cost;
     float* cost_f32;
     int64_t cap_cells;
-    int S, T, H, W, N;
+    int S, T, C, H, W, N;
     uint32_t cap;
 };
 
@@ -235,8 +245,9 @@ __global__ __launch_bounds__(kThreads) void cost_census_all_kernel(Src src) {
         }
         __syncthreads();
         const int sh = (S - 1) / 2, th = (T_ - 1) / 2;
+        const int C = a.C;
         const uint64_t* __restrict__ census = a.census;
-        const uint64_t* __restrict__ cref = census + ((size_t)th * S + sh) * HW;
+        const uint64_t* __restrict__ cref = census + ((size_t)th * S + sh) * C * HW;
         for (int64_t c = s_off[0] + threadIdx.x; c < s_off[np]; c += kThreads) {
             if (c >= a.cap_cells) break;
             const int i = find_pixel(s_off, np, c);
@@ -245,13 +256,15 @@ __global__ __launch_bounds__(kThreads) void cost_census_all_kernel(Src src) {
             const int k = s_lo[i] + (int)(c - s_off[i]);
             if ((unsigned)k >= (unsigned)N) continue;
             const float d = a.hyp[k];
-            const uint64_t r = cref[p];
             uint32_t acc = 0;
             for (int t = 0; t < T_; ++t) {
                 const int y = clampi(v + (int)rintf((float)(th - t) * d), 0, H - 1);
                 for (int s = 0; s < S; ++s) {
                     const int x = clampi(u + (int)rintf((float)(sh - s) * d), 0, W - 1);
-                    acc += (uint32_t)__popcll(r ^ census[((size_t)t * S + s) * HW + (size_t)y * W + x]);
+                    for (int c = 0; c < C; ++c)             // colour: summed per channel
+                        acc += (uint32_t)__popcll(
+                            cref[(size_t)c * HW + p] ^
+                            census[(((size_t)t * S + s) * C + c) * HW + (size_t)y * W + x]);
                 }
             }
             a.cost[c] = (uint16_t)min(acc, a.cap);
@@ -260,34 +273,34 @@ __global__ __launch_bounds__(kThreads) void cost_census_all_kernel(Src src) {
     }
 }
 
-template <typename T, bool Walk>
+template <typename T, bool Walk, int C>
 hipError_t l2_variant(Runner& r, const std::vector<L2Args>& args,
                       const std::vector<uint32_t>& blocks) {
     switch (r.tune.cost_cpt) {
         case 2:
-            return launch(r, kStCost, cost_l2_kernel<Single<L2Args>, T, 2, Walk>,
-                          cost_l2_kernel<Group<L2Args>, T, 2, Walk>, args, blocks, kThreads);
+            return launch(r, kStCost, cost_l2_kernel<Single<L2Args>, T, 2, Walk, C>,
+                          cost_l2_kernel<Group<L2Args>, T, 2, Walk, C>, args, blocks, kThreads);
         case 8:
-            return launch(r, kStCost, cost_l2_kernel<Single<L2Args>, T, 8, Walk>,
-                          cost_l2_kernel<Group<L2Args>, T, 8, Walk>, args, blocks, kThreads);
+            return launch(r, kStCost, cost_l2_kernel<Single<L2Args>, T, 8, Walk, C>,
+                          cost_l2_kernel<Group<L2Args>, T, 8, Walk, C>, args, blocks, kThreads);
         default:
-            return launch(r, kStCost, cost_l2_kernel<Single<L2Args>, T, 4, Walk>,
-                          cost_l2_kernel<Group<L2Args>, T, 4, Walk>, args, blocks, kThreads);
+            return launch(r, kStCost, cost_l2_kernel<Single<L2Args>, T, 4, Walk, C>,
+                          cost_l2_kernel<Group<L2Args>, T, 4, Walk, C>, args, blocks, kThreads);
     }
 }
 
-template <typename T>
+template <typename T, int C>
 hipError_t l2_walk(Runner& r, const std::vector<L2Args>& args,
                    const std::vector<uint32_t>& blocks) {
-    return r.tune.cost_stride > 1 ? l2_variant<T, true>(r, args, blocks)
-                                  : l2_variant<T, false>(r, args, blocks);
+    return r.tune.cost_stride > 1 ? l2_variant<T, true, C>(r, args, blocks)
+                                  : l2_variant<T, false, C>(r, args, blocks);
 }
 
 }  // namespace
 
 hipError_t stage_cost(Runner& r, const Jobs& jobs) {
-    std::vector<L2Args> l2[2];
-    std::vector<uint32_t> l2_blocks[2];
+    std::vector<L2Args> l2[2][2];                  // [u8/f32][gray/colour]
+    std::vector<uint32_t> l2_blocks[2][2];
     std::vector<PadArgs> pads[2];
     std::vector<uint32_t> pad_blocks[2];
     std::vector<CensusAllArgs> ca;
@@ -306,7 +319,7 @@ hipError_t stage_cost(Runner& r, const Jobs& jobs) {
             pa.pitch = j->pitch;
             pa.per_view = (uint32_t)(((int64_t)(j->H + 2) * (j->W + 2) + kThreads - 1) / kThreads);
             pads[j->dtype == LF_U8 ? 0 : 1].push_back(pa);
-            pad_blocks[j->dtype == LF_U8 ? 0 : 1].push_back(pa.per_view * j->S * j->T);
+            pad_blocks[j->dtype == LF_U8 ? 0 : 1].push_back(pa.per_view * j->S * j->T * j->C);
             L2Args a{};
             a.views = j->padded;
             a.hyp = j->hyp;
@@ -325,9 +338,9 @@ hipError_t stage_cost(Runner& r, const Jobs& jobs) {
             // worst-case slices; those past the device-side cell count are skipped
             const int64_t slices = (HW * j->N + kThreads * cpt - 1) / (kThreads * cpt);
             a.nblk = (uint32_t)std::max<int64_t>(1, (slices + stride - 1) / stride);
-            const int t = j->dtype == LF_U8 ? 0 : 1;
-            l2[t].push_back(a);
-            l2_blocks[t].push_back(a.nblk);
+            const int t = j->dtype == LF_U8 ? 0 : 1, col = j->C == 3 ? 1 : 0;
+            l2[t][col].push_back(a);
+            l2_blocks[t][col].push_back(a.nblk);
         } else {
             census_jobs.push_back(j);
             CensusAllArgs a{};
@@ -340,6 +353,7 @@ hipError_t stage_cost(Runner& r, const Jobs& jobs) {
             a.cap_cells = j->cap_cells;
             a.S = j->S;
             a.T = j->T;
+            a.C = j->C;
             a.H = j->H;
             a.W = j->W;
             a.N = j->N;
@@ -359,8 +373,14 @@ hipError_t stage_cost(Runner& r, const Jobs& jobs) {
                     pad_views_kernel<Group<PadArgs>, float>, pads[1], pad_blocks[1],
                     kThreads)) != hipSuccess)
         return e;
-    if (!l2[0].empty() && (e = l2_walk<uint8_t>(r, l2[0], l2_blocks[0])) != hipSuccess) return e;
-    if (!l2[1].empty() && (e = l2_walk<float>(r, l2[1], l2_blocks[1])) != hipSuccess) return e;
+    if (!l2[0][0].empty() && (e = l2_walk<uint8_t, 1>(r, l2[0][0], l2_blocks[0][0])) != hipSuccess)
+        return e;
+    if (!l2[1][0].empty() && (e = l2_walk<float, 1>(r, l2[1][0], l2_blocks[1][0])) != hipSuccess)
+        return e;
+    if (!l2[0][1].empty() && (e = l2_walk<uint8_t, 3>(r, l2[0][1], l2_blocks[0][1])) != hipSuccess)
+        return e;
+    if (!l2[1][1].empty() && (e = l2_walk<float, 3>(r, l2[1][1], l2_blocks[1][1])) != hipSuccess)
+        return e;
     if (!census_jobs.empty()) {
         if ((e = stage_census(r, census_jobs, true)) != hipSuccess) return e;
         e = launch(r, kStCost, cost_census_all_kernel<Single<CensusAllArgs>>,

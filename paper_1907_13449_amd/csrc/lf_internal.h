@@ -25,7 +25,7 @@ namespace lf {
 
 constexpr uint32_t kInf = 0x3FFFFFFFu;   // +inf of the SGM path recurrences
 constexpr int kMaxCensusRadius = 7;      // windows up to 15 x 15
-constexpr int kMaxBatchImages = 8;
+constexpr int kMaxBatchImages = 16;
 
 __device__ __forceinline__ int clampi(int x, int lo, int hi) { return min(max(x, lo), hi); }
 
@@ -133,8 +133,8 @@ hipError_t launch(Runner& r, int stage, void (*ks)(Single<A>), void (*kg)(Group<
 // Inputs, parameters and the device buffers every stage reads or writes.  A stage
 // uses only the buffers it needs; the others may be null.
 struct Job {
-    const void* views;        // [T][S][H][pitch]
-    int dtype, S, T, H, W, pitch, N;
+    const void* views;        // [T][S][C][H][pitch]
+    int dtype, S, T, C, H, W, pitch, N;
     const float* hyp;         // [N]
     lf_params prm;
     float alpha;              // effective cost scale
@@ -142,7 +142,7 @@ struct Job {
     int nv;                   // cross views
     int st[8];                // (s, t) of each cross view
     // initial stage
-    uint64_t* census;         // [1 + nv][H*W]: reference, then the cross views
+    uint64_t* census;         // [1 + nv][C][H*W]: reference, then the cross views
     void* paths;              // initial SGM scratch (sgm_dense_scratch_bytes)
     int16_t* maps;            // [nv][H*W] D_i
     int16_t* fill_tmp;        // [H*W]
@@ -152,8 +152,8 @@ struct Job {
     // bounded stage
     int64_t* offsets;         // [H*W + 1]
     void* scan;               // scan_scratch_bytes(H*W)
-    uint64_t* census_all;     // [S*T][H*W] (Census cost kind)
-    void* padded;             // [S*T][H+2][W+2] views with a replicated edge (l2 kind)
+    uint64_t* census_all;     // [S*T][C][H*W] (Census cost kind)
+    void* padded;             // [S*T][C][H+2][W+2] views with a replicated edge (l2 kind)
     uint16_t* cost;           // [cells]
     float* cost_f32;          // [cells] or null
     int64_t cap_cells;

@@ -91,12 +91,20 @@ __global__ __launch_bounds__(kThreads) void fill_kernel(Src src) {
 // --- Sobel edge exclusion and borders, Eq. (11) -----------------------------
 struct BordersArgs {
     const int16_t* dinit;
-    const void* ref;
+    const void* ref;          // C planes of H x pitch
     int16_t* lo;
     int16_t* hi;
-    int pitch, H, W, N, lambda;
+    int pitch, H, W, N, lambda, lambda_far, C;
     float alpha, tau;
 };
+
+// Half-width at initial index d (Sec. 4.6): lambda_far at index 0 (the smallest
+// disparity, the farthest point) falling linearly to lambda at N-1, rounded
+// half up; lambda_far <= lambda keeps lambda.
+__device__ __forceinline__ int border_width(int lambda, int lambda_far, int d, int N) {
+    if (lambda_far <= lambda || N < 2) return lambda;
+    return lambda + ((lambda_far - lambda) * (N - 1 - d) + (N - 1) / 2) / (N - 1);
+}
 
 template <typename T>
 __device__ __forceinline__ void borders_pixel(const BordersArgs& a, int p) {
@@ -105,20 +113,26 @@ __device__ __forceinline__ void borders_pixel(const BordersArgs& a, int p) {
     const int v = p / W, u = p - v * W;
     const int ym = max(v - 1, 0), yp = min(v + 1, H - 1);
     const int xm = max(u - 1, 0), xp = min(u + 1, W - 1);
-    auto I = [&](int y, int x) { return ld(ref + (size_t)y * a.pitch + x); };
-    const float gx = ((I(ym, xp) + 2.0f * I(v, xp)) + I(yp, xp)) -
-                     ((I(ym, xm) + 2.0f * I(v, xm)) + I(yp, xm));
-    const float gy = ((I(yp, xm) + 2.0f * I(yp, u)) + I(yp, xp)) -
-                     ((I(ym, xm) + 2.0f * I(ym, u)) + I(ym, xp));
-    const float g = fabsf(gx) + fabsf(gy);
+    float g = 0.0f;                               // colour: the strongest channel
+    for (int c = 0; c < a.C; ++c) {
+        const T* __restrict__ img = ref + (size_t)c * H * a.pitch;
+        auto I = [&](int y, int x) { return ld(img + (size_t)y * a.pitch + x); };
+        const float gx = ((I(ym, xp) + 2.0f * I(v, xp)) + I(yp, xp)) -
+                         ((I(ym, xm) + 2.0f * I(v, xm)) + I(yp, xm));
+        const float gy = ((I(yp, xm) + 2.0f * I(yp, u)) + I(yp, xp)) -
+                         ((I(ym, xm) + 2.0f * I(ym, u)) + I(ym, xp));
+        const float gc = fabsf(gx) + fabsf(gy);
+        g = gc > g ? gc : g;
+    }
     const bool edge = a.alpha * g > a.tau;
     const int d = a.dinit[p];
     if (a.lambda < 0 || d < 0 || edge) {          // lambda < 0: boundary-less search
         a.lo[p] = 0;
         a.hi[p] = (int16_t)(a.N - 1);
     } else {
-        a.lo[p] = (int16_t)max(d - a.lambda, 0);
-        a.hi[p] = (int16_t)min(d + a.lambda, a.N - 1);
+        const int lam = border_width(a.lambda, a.lambda_far, d, a.N);
+        a.lo[p] = (int16_t)max(d - lam, 0);
+        a.hi[p] = (int16_t)min(d + lam, a.N - 1);
     }
 }
 
@@ -358,7 +372,7 @@ hipError_t stage_borders(Runner& r, const Jobs& jobs) {
         const size_t elem = j->dtype == LF_U8 ? 1 : 4;
         BordersArgs b{};
         b.dinit = j->dinit;
-        b.ref = (const char*)j->views + ((size_t)th * j->S + sh) * j->H * j->pitch * elem;
+        b.ref = (const char*)j->views + ((size_t)th * j->S + sh) * j->C * j->H * j->pitch * elem;
         b.lo = j->lo;
         b.hi = j->hi;
         b.pitch = j->pitch;
@@ -366,6 +380,8 @@ hipError_t stage_borders(Runner& r, const Jobs& jobs) {
         b.W = j->W;
         b.N = j->N;
         b.lambda = j->prm.lambda;
+        b.lambda_far = j->prm.lambda_far;
+        b.C = j->C;
         b.alpha = j->alpha;
         b.tau = j->prm.edge_tau;
         brd[j->dtype == LF_U8 ? 0 : 1].push_back(b);

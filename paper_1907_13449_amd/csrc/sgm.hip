@@ -164,11 +164,11 @@ __device__ __forceinline__ uint32_t lane_min(const uint32_t (&L)[K]) {
 constexpr int kTilePix = 64;
 
 struct CcvArgs {
-    const uint64_t* cref;     // [H*W]
-    const uint64_t* cview;    // [nv][H*W]
+    const uint64_t* cref;     // [C][H*W]
+    const uint64_t* cview;    // [nv][C][H*W]
     const float* hyp;
     int cs[4], ct[4];         // s_hat - s, t_hat - t of each cross view
-    int nv, H, W, N, NP;
+    int nv, C, H, W, N, NP;
     uint32_t tiles;           // pixel tiles per view
     uint8_t* cvol;            // [nv][H*W][NP]
 };
@@ -190,14 +190,22 @@ __device__ __forceinline__ void ccv_block(const CcvArgs& a, uint32_t b, uint32_t
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint32_t p = p0 + (uint32_t)min(lane, npix - 1);
     const int v = (int)(p / W), u = (int)(p - (uint32_t)v * W);
-    const uint64_t r = a.cref[p];
-    const uint64_t* __restrict__ cv = a.cview + (size_t)z * HW;
+    // colour: one Census string per channel, Hamming distances summed (<= 3*64)
+    const int C = a.C;
+    uint64_t r[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) r[c] = c < C ? a.cref[(size_t)c * HW + p] : 0;
+    const uint64_t* __restrict__ cv = a.cview + (size_t)z * C * HW;
     uint8_t* t8 = (uint8_t*)tile;
     for (int k = wave; k < NP; k += 4) {          // k is wave-uniform
         const int sh = s_sh[k];
         const uint32_t q = along_u ? (uint32_t)(v * W + clampi(u + sh, 0, W - 1))
                                    : (uint32_t)(clampi(v + sh, 0, H - 1) * W + u);
-        t8[lane * NP + k] = k < N ? (uint8_t)__popcll(r ^ cv[q]) : (uint8_t)0;
+        uint32_t hd = 0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            if (c < C) hd += (uint32_t)__popcll(r[c] ^ cv[(size_t)c * HW + q]);
+        t8[lane * NP + k] = k < N ? (uint8_t)hd : (uint8_t)0;
     }
     __syncthreads();
     // the tile is npix * NP contiguous bytes of C (NP is a multiple of 4)
@@ -663,7 +671,7 @@ hipError_t stage_sgm_initial(Runner& r, const Jobs& jobs) {
         const int H = j->H, W = j->W, N = j->N, NP = dense_np(N);
         const size_t HW = (size_t)H * W;
         const lf_sgm_params& sp = j->prm.sgm_init;
-        const int bits = j->prm.census.win_h * j->prm.census.win_w - 1;
+        const int bits = j->C * (j->prm.census.win_h * j->prm.census.win_w - 1);
         const int lt = bits + sp.P2 <= 255 ? 0 : 1;
         uint8_t* cvol = (uint8_t*)j->paths;
         void* Lbuf = (char*)j->paths + round256((size_t)j->nv * HW * NP);
@@ -671,13 +679,14 @@ hipError_t stage_sgm_initial(Runner& r, const Jobs& jobs) {
 
         CcvArgs c{};
         c.cref = j->census;
-        c.cview = j->census + HW;
+        c.cview = j->census + (size_t)j->C * HW;
         c.hyp = j->hyp;
         for (int i = 0; i < j->nv; ++i) {
             c.cs[i] = sh - j->st[2 * i];
             c.ct[i] = th - j->st[2 * i + 1];
         }
         c.nv = j->nv;
+        c.C = j->C;
         c.H = H;
         c.W = W;
         c.N = N;

@@ -43,7 +43,8 @@ class LFError(RuntimeError):
 
 class ViewSet(C.Structure):
     _fields_ = [("data", C.c_void_p), ("S", C.c_int32), ("T", C.c_int32), ("H", C.c_int32),
-                ("W", C.c_int32), ("pitch", C.c_int32), ("dtype", C.c_int32)]
+                ("W", C.c_int32), ("pitch", C.c_int32), ("dtype", C.c_int32),
+                ("channels", C.c_int32)]
 
 
 class CensusWindow(C.Structure):
@@ -58,7 +59,7 @@ class Params(C.Structure):
     _fields_ = [("census", CensusWindow), ("sgm_init", SgmParams), ("sgm_final", SgmParams),
                 ("phi", C.c_int32), ("lambda_", C.c_int32), ("fill_passes", C.c_int32),
                 ("edge_tau", C.c_float), ("alpha", C.c_float), ("cost_kind", C.c_int32),
-                ("median", C.c_int32), ("sum_bits", C.c_int32)]
+                ("median", C.c_int32), ("sum_bits", C.c_int32), ("lambda_far", C.c_int32)]
 
 
 class Request(C.Structure):
@@ -99,15 +100,15 @@ def _load():
         getattr(lib, name).restype = C.c_size_t
     P, i32, i64, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
     lib.lf_census.argtypes = [P, i32, i32, i32, i32, CensusWindow, P, P]
-    lib.lf_initial_workspace_size.argtypes = [i32, i32, i32, i32, i32, P]
+    lib.lf_initial_workspace_size.argtypes = [i32, i32, i32, i32, i32, i32, P]
     lib.lf_initial_disparity.argtypes = [P, P, i32, P, P, P, P, P, P, sz, P]
-    lib.lf_cost_workspace_size.argtypes = [i32, i32, i32, i32, i32, P]
+    lib.lf_cost_workspace_size.argtypes = [i32, i32, i32, i32, i32, i32, P]
     lib.lf_cost_volume_bounded.argtypes = [P, P, i32, P, P, P, P, P, i64, P, P, sz, P]
     lib.lf_sgm_workspace_size.argtypes = [i32, i32, i32, i32]
     lib.lf_sgm_aggregate.argtypes = [P, P, P, P, i32, i32, i32, SgmParams, i32, P, P, sz, P]
     lib.lf_wta_workspace_size.argtypes = [i32, i32]
     lib.lf_wta_subpixel.argtypes = [P, i32, P, P, P, i32, i32, P, i32, i32, P, P, P, sz, P]
-    lib.lf_depth_workspace_size.argtypes = [i32, i32, i32, i32, i32, P]
+    lib.lf_depth_workspace_size.argtypes = [i32, i32, i32, i32, i32, i32, P]
     lib.lf_depth.argtypes = [P, P, i32, P, P, P, P, sz, P]
     lib.lf_validate_hypotheses.argtypes = [P, i32]
     lib.lf_cost_cap.argtypes = [i32, i32, i32]
@@ -166,21 +167,24 @@ def make_params(p: dict) -> Params:
                   SgmParams(p["P1_init"], p["P2_init"], p["npaths"]),
                   SgmParams(p["P1_final"], p["P2_final"], p["npaths"]),
                   p["phi"], p["lam"], p["fill_passes"], float(p["edge_tau"]), float(p["alpha"]),
-                  p["cost_kind"], p["median"], p["sum_bits"])
+                  p["cost_kind"], p["median"], p["sum_bits"], p.get("lam_far", 0))
 
 
 def view_set(views: torch.Tensor) -> ViewSet:
-    """lf_view_set of a [T][S][H][W] uint8/float32 tensor on the GPU."""
-    if views.dim() != 4 or not views.is_cuda or not views.is_contiguous():
-        raise ValueError("views: expected a contiguous [T][S][H][W] CUDA tensor")
+    """lf_view_set of a [T][S][H][W] (grayscale) or [T][S][C][H][W] (colour)
+    uint8/float32 tensor on the GPU."""
+    if views.dim() not in (4, 5) or not views.is_cuda or not views.is_contiguous():
+        raise ValueError("views: expected a contiguous [T][S]([C])[H][W] CUDA tensor")
     if views.dtype == torch.uint8:
         dt = LF_U8
     elif views.dtype == torch.float32:
         dt = LF_F32
     else:
         raise ValueError("views: uint8 or float32")
-    T, S, H, W = views.shape
-    return ViewSet(views.data_ptr(), S, T, H, W, W, dt)
+    T, S = views.shape[:2]
+    H, W = views.shape[-2:]
+    channels = 1 if views.dim() == 4 else views.shape[2]
+    return ViewSet(views.data_ptr(), S, T, H, W, W, dt, channels)
 
 
 def workspace(nbytes: int, device) -> torch.Tensor:
@@ -233,7 +237,7 @@ def lf_initial_disparity(views: torch.Tensor, hyp: torch.Tensor, params: dict, w
     d_init = torch.empty((H, W), dtype=torch.int16, device=dev)
     d_lo = torch.empty((H, W), dtype=torch.int16, device=dev)
     d_hi = torch.empty((H, W), dtype=torch.int16, device=dev)
-    need = lib.lf_initial_workspace_size(vs.S, vs.T, H, W, N, C.byref(prm))
+    need = lib.lf_initial_workspace_size(vs.S, vs.T, vs.channels, H, W, N, C.byref(prm))
     if ws is None:
         ws = workspace(need, dev)
     _check(lib.lf_initial_disparity(C.byref(vs), _ptr(hyp), N, C.byref(prm), _ptr(maps),
@@ -257,7 +261,7 @@ def lf_cost_volume_bounded(views: torch.Tensor, hyp: torch.Tensor, params: dict,
     offsets = torch.empty(HW + 1, dtype=torch.int64, device=dev)
     cost = torch.empty(cells, dtype=torch.int16, device=dev)        # uint16 bits
     cost_f32 = torch.empty(cells, dtype=torch.float32, device=dev) if want_f32 else None
-    need = lib.lf_cost_workspace_size(vs.S, vs.T, vs.H, vs.W, N, C.byref(prm))
+    need = lib.lf_cost_workspace_size(vs.S, vs.T, vs.channels, vs.H, vs.W, N, C.byref(prm))
     if ws is None:
         ws = workspace(need, dev)
     _check(lib.lf_cost_volume_bounded(C.byref(vs), _ptr(hyp), N, C.byref(prm), _ptr(d_lo),
@@ -313,9 +317,9 @@ def profile_read():
     return {lib.lf_profile_stage_name(i).decode(): (ms[i], la[i]) for i in range(k)}
 
 
-def depth_workspace_bytes(S, T, H, W, N, params: dict) -> int:
+def depth_workspace_bytes(S, T, H, W, N, params: dict, channels: int = 1) -> int:
     prm = make_params(params)
-    return lib.lf_depth_workspace_size(S, T, H, W, N, C.byref(prm))
+    return lib.lf_depth_workspace_size(S, T, channels, H, W, N, C.byref(prm))
 
 
 def lf_depth(views: torch.Tensor, hyp: torch.Tensor, params: dict, ws=None, out=None,
@@ -328,7 +332,8 @@ def lf_depth(views: torch.Tensor, hyp: torch.Tensor, params: dict, ws=None, out=
     if out is None:
         out = torch.empty((vs.H, vs.W), dtype=torch.float32, device=dev)
     if ws is None:
-        ws = workspace(lib.lf_depth_workspace_size(vs.S, vs.T, vs.H, vs.W, N, C.byref(prm)), dev)
+        ws = workspace(lib.lf_depth_workspace_size(vs.S, vs.T, vs.channels, vs.H, vs.W, N,
+                                                   C.byref(prm)), dev)
     _check(lib.lf_depth(C.byref(vs), _ptr(hyp), N, C.byref(prm), _ptr(out), _ptr(d_index),
                         _ptr(ws), ws.numel(), _stream(stream)))
     return out

@@ -61,10 +61,23 @@ def case(name):
         lf = lfsynth.workload("paper_s", seed=17, H=36, W=45, S=5, T=5, N=48)
         lf.params.update(lam=-1)
         return lf
+    if name == "rgb_f32":                    # colour views (Sec. 3.3), l2 over colour
+        return lfsynth.workload("paper_s", seed=18, H=38, W=45, S=5, T=5, N=48, channels=3)
+    if name == "rgb_u8_census":              # colour u8, Census cost kind, 16-bit sums
+        lf = lfsynth.workload("paper_s", seed=19, H=30, W=41, S=3, T=3, N=40, channels=3)
+        lf.views = np.clip(np.rint(lf.views * 255.0), 0, 255).astype(np.uint8)
+        lf.params.update(cost_kind=1, win_h=5, win_w=5, sum_bits=16, alpha=1.0,
+                         edge_tau=60.0)
+        return lf
+    if name == "adaptive":                   # depth-adaptive borders (Sec. 4.6)
+        lf = lfsynth.workload("paper_s", seed=20, H=44, W=50, S=7, T=7, N=80)
+        lf.params.update(lam=2, lam_far=6)
+        return lf
     raise KeyError(name)
 
 
 CASES = ["small", "f32_ragged", "u8_n65", "n256", "stage_1x11", "col_7x1", "one_row", "one_col",
-         "u16_paths", "census_cost", "paths16", "paths16_u16", "boundless"]
+         "u16_paths", "census_cost", "paths16", "paths16_u16", "boundless", "rgb_f32",
+         "rgb_u8_census", "adaptive"]
 
 

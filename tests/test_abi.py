@@ -35,13 +35,14 @@ def test_library_exports_every_declared_symbol(lf):
     for name in declared_functions():
         assert hasattr(lf.lib, name), name
     assert set(declared_functions()) == set(lf.EXPORTS)
-    assert lf.lib.lf_abi_version() == 2
+    assert lf.lib.lf_abi_version() == 3
 
 
 def test_struct_layouts_match_header(lf):
-    # lf_view_set: pointer + 6 int32; lf_params: 2 + 3 + 3 + 3 int32 + 2 float + 3 int32
-    assert C.sizeof(lf.ViewSet) == 8 + 6 * 4
-    assert C.sizeof(lf.Params) == (2 + 3 + 3 + 3) * 4 + 2 * 4 + 3 * 4
+    # lf_view_set: pointer + 7 int32 (+ 4 bytes of tail padding);
+    # lf_params: 2 + 3 + 3 + 3 int32 + 2 float + 4 int32
+    assert C.sizeof(lf.ViewSet) == 8 + 7 * 4 + 4
+    assert C.sizeof(lf.Params) == (2 + 3 + 3 + 3) * 4 + 2 * 4 + 4 * 4
 
 
 def test_validate_hypotheses(lf):
@@ -71,12 +72,13 @@ def _params(lf, **kw):
 
 
 @pytest.mark.parametrize("bad", [
-    dict(S=4, T=5), dict(S=1, T=1), dict(N=1), dict(N=300), dict(H=0),
+    dict(S=4, T=5), dict(S=1, T=1), dict(N=1), dict(N=300), dict(H=0), dict(C=2), dict(C=4),
 ])
 def test_initial_disparity_rejects_bad_shapes(lf, bad):
-    shape = dict(S=5, T=5, H=16, W=16, N=8)
+    shape = dict(S=5, T=5, H=16, W=16, N=8, C=1)
     shape.update(bad)
-    vs = lf.ViewSet(0x1000, shape["S"], shape["T"], shape["H"], shape["W"], shape["W"], lf.LF_U8)
+    vs = lf.ViewSet(0x1000, shape["S"], shape["T"], shape["H"], shape["W"], shape["W"], lf.LF_U8,
+                    shape["C"])
     prm = _params(lf)
     st = lf.lib.lf_initial_disparity(C.byref(vs), C.c_void_p(0x1000), shape["N"], C.byref(prm),
                                      None, C.c_void_p(0x1000), C.c_void_p(0x1000),
@@ -88,10 +90,10 @@ def test_initial_disparity_rejects_bad_shapes(lf, bad):
 @pytest.mark.parametrize("bad", [
     dict(win_h=4), dict(win_h=9, win_w=9), dict(win_h=17, win_w=3), dict(P1_init=50, P2_init=40),
     dict(npaths=4), dict(phi=0), dict(lam=-2), dict(median=5), dict(sum_bits=8),
-    dict(cost_kind=7), dict(P2_init=9000),
+    dict(cost_kind=7), dict(P2_init=9000), dict(lam_far=-1),
 ])
 def test_params_rejected(lf, bad):
-    vs = lf.ViewSet(0x1000, 5, 5, 16, 16, 16, lf.LF_U8)
+    vs = lf.ViewSet(0x1000, 5, 5, 16, 16, 16, lf.LF_U8, 1)
     prm = _params(lf, **bad)
     st = lf.lib.lf_depth(C.byref(vs), C.c_void_p(0x1000), 8, C.byref(prm), C.c_void_p(0x1000),
                          None, C.c_void_p(0x1000), 1 << 40, None)
@@ -99,7 +101,7 @@ def test_params_rejected(lf, bad):
 
 
 def test_workspace_too_small_is_enospace(lf):
-    vs = lf.ViewSet(0x1000, 5, 5, 16, 16, 16, lf.LF_U8)
+    vs = lf.ViewSet(0x1000, 5, 5, 16, 16, 16, lf.LF_U8, 1)
     prm = _params(lf)
     st = lf.lib.lf_depth(C.byref(vs), C.c_void_p(0x1000), 8, C.byref(prm), C.c_void_p(0x1000),
                          None, C.c_void_p(0x1000), 1024, None)
@@ -107,7 +109,7 @@ def test_workspace_too_small_is_enospace(lf):
 
 
 def test_cost_volume_capacity_is_checked(lf):
-    vs = lf.ViewSet(0x1000, 5, 5, 16, 16, 16, lf.LF_U8)
+    vs = lf.ViewSet(0x1000, 5, 5, 16, 16, 16, lf.LF_U8, 1)
     prm = _params(lf)
     p = C.c_void_p(0x1000)
     st = lf.lib.lf_cost_volume_bounded(C.byref(vs), p, 8, C.byref(prm), p, p, p, p,
@@ -117,8 +119,10 @@ def test_cost_volume_capacity_is_checked(lf):
 
 def test_workspace_sizes_are_positive_and_monotone(lf):
     prm = _params(lf)
-    a = lf.lib.lf_depth_workspace_size(5, 5, 96, 96, 32, C.byref(prm))
-    b = lf.lib.lf_depth_workspace_size(9, 9, 512, 512, 100, C.byref(prm))
-    assert 0 < a < b
+    a = lf.lib.lf_depth_workspace_size(5, 5, 1, 96, 96, 32, C.byref(prm))
+    b = lf.lib.lf_depth_workspace_size(9, 9, 1, 512, 512, 100, C.byref(prm))
+    c = lf.lib.lf_depth_workspace_size(9, 9, 3, 512, 512, 100, C.byref(prm))
+    assert 0 < a < b < c
+    assert lf.lib.lf_depth_workspace_size(9, 9, 2, 512, 512, 100, C.byref(prm)) == 0
     # 9x9x512^2, N=100: dominated by the four 16-bit initial volumes (4*512*512*100*2 B)
     assert b > 4 * 512 * 512 * 100 * 2

@@ -22,7 +22,8 @@ torch = pytest.importorskip("torch")
 # initial path costs, 16/32-bit sums, 8/16 paths, Census cost kind, median
 # on/off, 0..3 fill passes, 3-D light fields and one-row / one-column images
 MIX = ["small", "f32_ragged", "u8_n65", "n256", "stage_1x11", "col_7x1", "one_row", "one_col",
-       "u16_paths", "census_cost", "paths16", "paths16_u16", "boundless"]
+       "u16_paths", "census_cost", "paths16", "paths16_u16", "boundless", "rgb_f32",
+       "rgb_u8_census", "adaptive"]
 
 
 @pytest.fixture(scope="module")
@@ -45,7 +46,7 @@ def items(lf):
         lfd = case(name)
         views = torch.from_numpy(np.ascontiguousarray(lfd.views)).cuda()
         hyp = torch.from_numpy(lfd.hyp).cuda()
-        H, W = lfd.views.shape[2:]
+        H, W = lfd.views.shape[-2:]
         d_index = torch.empty((H, W), dtype=torch.int16, device="cuda")
         disp = lf.lf_depth(views, hyp, lfd.params, d_index=d_index)
         torch.cuda.synchronize()

@@ -22,7 +22,7 @@ def _req(lf, S=5, T=5, H=32, W=40, N=16, data=FAKE, dtype=1, **prm):
     p = lfsynth._params(census=(5, 5), p_init=(10, 120), p_final=(10, 120), lam=2,
                         edge_tau=float("inf"), alpha=255.0, sum_bits=32)
     p.update(prm)
-    vs = lf.ViewSet(data, S, T, H, W, W, dtype)
+    vs = lf.ViewSet(data, S, T, H, W, W, dtype, 1)
     return lf.Request(vs, FAKE, N, lf.make_params(p), FAKE, 0)
 
 
@@ -41,7 +41,7 @@ def test_batch_workspace_is_the_sum_plus_tables(lf):
     one_a = lf.batch_workspace_bytes([a])
     one_b = lf.batch_workspace_bytes([b])
     both = lf.batch_workspace_bytes([a, b])
-    da = lf.lib.lf_depth_workspace_size(5, 5, 32, 40, 16, C.byref(a.params))
+    da = lf.lib.lf_depth_workspace_size(5, 5, 1, 32, 40, 16, C.byref(a.params))
     assert one_a > da
     assert both >= lf.batch_workspace_bytes([a]) + da - 1
     assert both < one_a + one_b
