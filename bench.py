@@ -386,6 +386,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device-to-device copy (counter calibration)")
+    ap.add_argument("--no-quality", action="store_true",
+                    help="skip the accuracy / boundary-less comparison")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched measurement")
     ap.add_argument("--no-serve", action="store_true", help="skip the request-loop measurement")
     ap.add_argument("--batch-n", type=int, default=64)
@@ -504,8 +506,9 @@ def main():
         "roofline": roofline,
         "stage_roofline": roofs,
     }
-    res["quality"] = quality_vs_boundless(lf, lfd, views, hyp, out, ms_per_step, cells_bounded,
-                                          stream)
+    if not args.no_quality:
+        res["quality"] = quality_vs_boundless(lf, lfd, views, hyp, out, ms_per_step,
+                                              cells_bounded, stream)
     del ws
     scenes = None
     if not (args.no_batch and args.no_serve) and args.workload == "paper":

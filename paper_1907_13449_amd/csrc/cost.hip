@@ -74,22 +74,21 @@ struct PadArgs {
     const void* src;          // [planes][H][pitch] (a view is C planes)
     void* dst;                // [planes][H+2][W+2]
     int H, W, pitch;
-    uint32_t per_view;        // blocks per plane
 };
 
+// One workgroup per padded row: block b is row b % (H+2) of plane b / (H+2).
 template <class Src, typename T>
 __global__ __launch_bounds__(kThreads) void pad_views_kernel(Src src) {
     for (uint32_t vb = blockIdx.x; vb < src.total; vb += gridDim.x) {
         uint32_t b;
         const PadArgs& a = member(src, vb, b);
-        const int z = (int)(b / a.per_view);
-        const int i = (int)(b - (uint32_t)z * a.per_view) * kThreads + threadIdx.x;
-        const int Wp = a.W + 2;
-        if (i >= (a.H + 2) * Wp) continue;
-        const int y = i / Wp, x = i - y * Wp;
-        const T* v = (const T*)a.src + (size_t)z * a.H * a.pitch;
-        ((T*)a.dst)[(size_t)z * (a.H + 2) * Wp + i] =
-            v[(size_t)clampi(y - 1, 0, a.H - 1) * a.pitch + clampi(x - 1, 0, a.W - 1)];
+        const int Hp = a.H + 2, Wp = a.W + 2;
+        const int z = (int)(b / (uint32_t)Hp);
+        const int y = (int)b - z * Hp;
+        const T* __restrict__ row =
+            (const T*)a.src + ((size_t)z * a.H + clampi(y - 1, 0, a.H - 1)) * a.pitch;
+        T* __restrict__ out = (T*)a.dst + ((size_t)z * Hp + y) * Wp;
+        for (int x = threadIdx.x; x < Wp; x += kThreads) out[x] = row[clampi(x - 1, 0, a.W - 1)];
     }
 }
 
@@ -317,9 +316,9 @@ hipError_t stage_cost(Runner& r, const Jobs& jobs) {
             pa.H = j->H;
             pa.W = j->W;
             pa.pitch = j->pitch;
-            pa.per_view = (uint32_t)(((int64_t)(j->H + 2) * (j->W + 2) + kThreads - 1) / kThreads);
             pads[j->dtype == LF_U8 ? 0 : 1].push_back(pa);
-            pad_blocks[j->dtype == LF_U8 ? 0 : 1].push_back(pa.per_view * j->S * j->T * j->C);
+            pad_blocks[j->dtype == LF_U8 ? 0 : 1].push_back((uint32_t)(j->H + 2) * j->S * j->T *
+                                                            j->C);
             L2Args a{};
             a.views = j->padded;
             a.hyp = j->hyp;
