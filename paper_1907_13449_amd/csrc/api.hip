@@ -64,9 +64,9 @@ lf_status device_status(hipError_t e, const char* where) {
 // Opt-in stage timing: a HIP event pair recorded on the call's stream around
 // each group of launches.  Off by default; when off nothing is recorded.
 namespace prof {
-const char* const kNames[lf::kNumStages] = {"census", "sgm_initial", "fuse_fill_borders",
-                                            "offsets", "cost_bounded", "sgm_bounded",
-                                            "wta_subpixel_median"};
+const char* const kNames[lf::kNumStages] = {"census",      "sgm_initial",  "fuse_fill_borders",
+                                            "offsets",     "cost_inputs",  "cost_bounded",
+                                            "sgm_bounded", "wta_subpixel_median"};
 struct Rec {
     int stage, launches;
     hipEvent_t a, b;
@@ -397,6 +397,10 @@ lf_status run_cost(lf::Runner& r, const lf::Jobs& jobs) {
     {
         prof::Scope _ps(lf::kStOffsets, r);
         LF_HIP(lf::stage_offsets(r, jobs), "offsets");
+    }
+    {
+        prof::Scope _ps(lf::kStCostInputs, r);
+        LF_HIP(lf::stage_cost_inputs(r, jobs), "cost inputs");
     }
     prof::Scope _ps(lf::kStCost, r);
     LF_HIP(lf::stage_cost(r, jobs), "bounded cost");

@@ -23,7 +23,46 @@ struct CensusArgs {
     uint64_t* out;            // [n][H*W]
 };
 
-template <typename T>
+// The bit string of one pixel from its window in the LDS tile (win points at the
+// window's top-left element, rows tw apart): bit n = [centre > neighbour n],
+// neighbours in row-major order, centre skipped.
+__device__ __forceinline__ uint64_t census_any(const float* win, int wh, int ww, int tw) {
+    const int rh = wh / 2, rw = ww / 2;
+    const float c = win[rh * tw + rw];
+    uint64_t bits = 0;
+    int n = 0;
+    for (int i = 0; i < wh; ++i) {
+        const float* row = win + i * tw;
+        for (int j = 0; j < ww; ++j) {
+            if (i == rh && j == rw) continue;
+            bits |= (uint64_t)(c > row[j]) << n;
+            ++n;
+        }
+    }
+    return bits;
+}
+
+// The same for a window size known at compile time: every shift and LDS offset
+// is a constant, and the two 32-bit halves are built separately.
+template <int WH, int WW>
+__device__ __forceinline__ uint64_t census_fixed(const float* win) {
+    constexpr int tw = kBX + 2 * (WW / 2), rh = WH / 2, rw = WW / 2;
+    const float c = win[rh * tw + rw];
+    uint32_t lo = 0, hi = 0;
+#pragma unroll
+    for (int i = 0, n = 0; i < WH; ++i)
+#pragma unroll
+        for (int j = 0; j < WW; ++j) {
+            if (i == rh && j == rw) continue;
+            const uint32_t bit = c > win[i * tw + j] ? 1u : 0u;
+            if (n < 32) lo |= bit << n;
+            else hi |= bit << (n - 32);
+            ++n;
+        }
+    return ((uint64_t)hi << 32) | lo;
+}
+
+template <typename T, int WH, int WW>
 __device__ __forceinline__ void census_block(const CensusArgs& a, uint32_t b, float* tile) {
     const int per = a.bx * a.by;
     const int z = (int)b / per;
@@ -34,7 +73,7 @@ __device__ __forceinline__ void census_block(const CensusArgs& a, uint32_t b, fl
     const T* __restrict__ img = reinterpret_cast<const T*>(a.base) + off;
     uint64_t* __restrict__ dst = a.out + (size_t)z * H * W;
 
-    const int rh = a.win_h / 2, rw = a.win_w / 2;
+    const int rh = (WH > 0 ? WH : a.win_h) / 2, rw = (WW > 0 ? WW : a.win_w) / 2;
     const int tw = kBX + 2 * rw, th = kBY + 2 * rh;
     const int x0 = bx * kBX - rw, y0 = by * kBY - rh;
     for (int i = threadIdx.x; i < tw * th; i += 256) {
@@ -47,28 +86,22 @@ __device__ __forceinline__ void census_block(const CensusArgs& a, uint32_t b, fl
     const int lx = threadIdx.x % kBX, ly = threadIdx.x / kBX;
     const int u = bx * kBX + lx, v = by * kBY + ly;
     if (u >= W || v >= H) return;
-    const float c = tile[(ly + rh) * tw + lx + rw];
-    uint64_t bits = 0;
-    int n = 0;
-    for (int i = 0; i < a.win_h; ++i) {
-        const float* row = tile + (ly + i) * tw + lx;
-        for (int j = 0; j < a.win_w; ++j) {
-            if (i == rh && j == rw) continue;
-            bits |= (uint64_t)(c > row[j]) << n;
-            ++n;
-        }
-    }
+    const float* win = tile + ly * tw + lx;
+    uint64_t bits;
+    if constexpr (WH > 0) bits = census_fixed<WH, WW>(win);
+    else bits = census_any(win, a.win_h, a.win_w, tw);
     dst[(size_t)v * W + u] = bits;
 }
 
-template <class Src, typename T>
+// WH = WW = 0: any window (sizes from the arguments)
+template <class Src, typename T, int WH, int WW>
 __global__ __launch_bounds__(256) void census_kernel(Src src) {
     __shared__ float tile[(kBY + 2 * kMaxCensusRadius) * (kBX + 2 * kMaxCensusRadius)];
     for (uint32_t vb = blockIdx.x; vb < src.total; vb += gridDim.x) {
         uint32_t b;
         const CensusArgs& a = member(src, vb, b);
         __syncthreads();                          // the tile of the previous block is read
-        census_block<T>(a, b, tile);
+        census_block<T, WH, WW>(a, b, tile);
     }
 }
 
@@ -91,14 +124,36 @@ CensusArgs census_args(const void* base, int H, int W, int pitch, int win_h, int
     return a;
 }
 
+template <typename T, int WH, int WW>
+hipError_t census_variant(Runner& r, int stage, const std::vector<CensusArgs>& args,
+                          const std::vector<uint32_t>& blocks) {
+    return launch(r, stage, census_kernel<Single<CensusArgs>, T, WH, WW>,
+                  census_kernel<Group<CensusArgs>, T, WH, WW>, args, blocks, 256);
+}
+
+// One launch per input type and window size (the 5x5 and 7x9 windows of the
+// workloads compiled for their size, any other through the general loop).
+template <typename T>
+hipError_t census_windows(Runner& r, int stage, const std::vector<CensusArgs>& args) {
+    std::vector<CensusArgs> by[3];
+    std::vector<uint32_t> blocks[3];
+    for (const CensusArgs& a : args) {
+        const int w = a.win_h == 5 && a.win_w == 5 ? 0 : a.win_h == 7 && a.win_w == 9 ? 1 : 2;
+        by[w].push_back(a);
+        blocks[w].push_back(census_blocks(a));
+    }
+    hipError_t e = hipSuccess;
+    if (!by[0].empty() && (e = census_variant<T, 5, 5>(r, stage, by[0], blocks[0])) != hipSuccess)
+        return e;
+    if (!by[1].empty() && (e = census_variant<T, 7, 9>(r, stage, by[1], blocks[1])) != hipSuccess)
+        return e;
+    if (!by[2].empty()) e = census_variant<T, 0, 0>(r, stage, by[2], blocks[2]);
+    return e;
+}
+
 hipError_t launch_census(Runner& r, int stage, int dtype, const std::vector<CensusArgs>& args) {
-    std::vector<uint32_t> blocks;
-    for (const CensusArgs& a : args) blocks.push_back(census_blocks(a));
-    if (dtype == LF_U8)
-        return launch(r, stage, census_kernel<Single<CensusArgs>, uint8_t>,
-                      census_kernel<Group<CensusArgs>, uint8_t>, args, blocks, 256);
-    return launch(r, stage, census_kernel<Single<CensusArgs>, float>,
-                  census_kernel<Group<CensusArgs>, float>, args, blocks, 256);
+    return dtype == LF_U8 ? census_windows<uint8_t>(r, stage, args)
+                          : census_windows<float>(r, stage, args);
 }
 
 }  // namespace
@@ -136,7 +191,7 @@ hipError_t stage_census(Runner& r, const Jobs& jobs, bool all_views) {
         }
         by_type[j->dtype == LF_U8 ? 0 : 1].push_back(a);
     }
-    const int stage = all_views ? kStCost : kStCensus;
+    const int stage = all_views ? kStCostInputs : kStCensus;
     for (int t = 0; t < 2; ++t) {
         if (by_type[t].empty()) continue;
         hipError_t e = launch_census(r, stage, t == 0 ? LF_U8 : LF_F32, by_type[t]);

@@ -297,28 +297,51 @@ hipError_t l2_walk(Runner& r, const std::vector<L2Args>& args,
 
 }  // namespace
 
+hipError_t stage_cost_inputs(Runner& r, const Jobs& jobs) {
+    // l2 cost: the edge-replicated copy of every view plane; Eq. (15) cost: the
+    // Census strings of every view
+    std::vector<PadArgs> pads[2];
+    std::vector<uint32_t> pad_blocks[2];
+    Jobs census_jobs;
+    for (const Job* j : jobs) {
+        if (j->prm.cost_kind != LF_COST_L2) {
+            census_jobs.push_back(j);
+            continue;
+        }
+        PadArgs pa{};
+        pa.src = j->views;
+        pa.dst = j->padded;
+        pa.H = j->H;
+        pa.W = j->W;
+        pa.pitch = j->pitch;
+        pads[j->dtype == LF_U8 ? 0 : 1].push_back(pa);
+        pad_blocks[j->dtype == LF_U8 ? 0 : 1].push_back((uint32_t)(j->H + 2) * j->S * j->T * j->C);
+    }
+    hipError_t e = hipSuccess;
+    if (!pads[0].empty() &&
+        (e = launch(r, kStCostInputs, pad_views_kernel<Single<PadArgs>, uint8_t>,
+                    pad_views_kernel<Group<PadArgs>, uint8_t>, pads[0], pad_blocks[0],
+                    kThreads)) != hipSuccess)
+        return e;
+    if (!pads[1].empty() &&
+        (e = launch(r, kStCostInputs, pad_views_kernel<Single<PadArgs>, float>,
+                    pad_views_kernel<Group<PadArgs>, float>, pads[1], pad_blocks[1],
+                    kThreads)) != hipSuccess)
+        return e;
+    if (!census_jobs.empty()) e = stage_census(r, census_jobs, true);
+    return e;
+}
+
 hipError_t stage_cost(Runner& r, const Jobs& jobs) {
     std::vector<L2Args> l2[2][2];                  // [u8/f32][gray/colour]
     std::vector<uint32_t> l2_blocks[2][2];
-    std::vector<PadArgs> pads[2];
-    std::vector<uint32_t> pad_blocks[2];
     std::vector<CensusAllArgs> ca;
     std::vector<uint32_t> ca_blocks;
-    Jobs census_jobs;
     const int cpt = r.tune.cost_cpt == 2 || r.tune.cost_cpt == 8 ? r.tune.cost_cpt : 4;
     const int stride = std::max(1, r.tune.cost_stride);
     for (const Job* j : jobs) {
         const int64_t HW = (int64_t)j->H * j->W;
         if (j->prm.cost_kind == LF_COST_L2) {
-            PadArgs pa{};
-            pa.src = j->views;
-            pa.dst = j->padded;
-            pa.H = j->H;
-            pa.W = j->W;
-            pa.pitch = j->pitch;
-            pads[j->dtype == LF_U8 ? 0 : 1].push_back(pa);
-            pad_blocks[j->dtype == LF_U8 ? 0 : 1].push_back((uint32_t)(j->H + 2) * j->S * j->T *
-                                                            j->C);
             L2Args a{};
             a.views = j->padded;
             a.hyp = j->hyp;
@@ -341,7 +364,6 @@ hipError_t stage_cost(Runner& r, const Jobs& jobs) {
             l2[t][col].push_back(a);
             l2_blocks[t][col].push_back(a.nblk);
         } else {
-            census_jobs.push_back(j);
             CensusAllArgs a{};
             a.census = j->census_all;
             a.hyp = j->hyp;
@@ -362,16 +384,6 @@ hipError_t stage_cost(Runner& r, const Jobs& jobs) {
         }
     }
     hipError_t e = hipSuccess;
-    if (!pads[0].empty() &&
-        (e = launch(r, kStCost, pad_views_kernel<Single<PadArgs>, uint8_t>,
-                    pad_views_kernel<Group<PadArgs>, uint8_t>, pads[0], pad_blocks[0],
-                    kThreads)) != hipSuccess)
-        return e;
-    if (!pads[1].empty() &&
-        (e = launch(r, kStCost, pad_views_kernel<Single<PadArgs>, float>,
-                    pad_views_kernel<Group<PadArgs>, float>, pads[1], pad_blocks[1],
-                    kThreads)) != hipSuccess)
-        return e;
     if (!l2[0][0].empty() && (e = l2_walk<uint8_t, 1>(r, l2[0][0], l2_blocks[0][0])) != hipSuccess)
         return e;
     if (!l2[1][0].empty() && (e = l2_walk<float, 1>(r, l2[1][0], l2_blocks[1][0])) != hipSuccess)
@@ -380,11 +392,9 @@ hipError_t stage_cost(Runner& r, const Jobs& jobs) {
         return e;
     if (!l2[1][1].empty() && (e = l2_walk<float, 3>(r, l2[1][1], l2_blocks[1][1])) != hipSuccess)
         return e;
-    if (!census_jobs.empty()) {
-        if ((e = stage_census(r, census_jobs, true)) != hipSuccess) return e;
+    if (!ca.empty())
         e = launch(r, kStCost, cost_census_all_kernel<Single<CensusAllArgs>>,
                    cost_census_all_kernel<Group<CensusAllArgs>>, ca, ca_blocks, kThreads);
-    }
     return e;
 }
 

@@ -71,8 +71,8 @@ struct Tuning {
 };
 
 // Stages of the method, in order (also the profiling buckets).
-enum Stage { kStCensus, kStSgmInit, kStBorders, kStOffsets, kStCost, kStSgmFinal, kStWta,
-             kNumStages };
+enum Stage { kStCensus, kStSgmInit, kStBorders, kStOffsets, kStCostInputs, kStCost, kStSgmFinal,
+             kStWta, kNumStages };
 
 // Receives the launches of a batch plan.  table() copies host records into the
 // plan's device table and returns their device address.
@@ -189,6 +189,7 @@ hipError_t stage_full_range(Runner& r, const Jobs& jobs);
 // Exclusive prefix sum of the range widths -> offsets.
 hipError_t stage_offsets(Runner& r, const Jobs& jobs);
 // Bounded matching cost (l2 or Census kind) -> cost (and cost_f32).
+hipError_t stage_cost_inputs(Runner& r, const Jobs& jobs);
 hipError_t stage_cost(Runner& r, const Jobs& jobs);
 // Bounded SGM -> csum.
 hipError_t stage_sgm_final(Runner& r, const Jobs& jobs);

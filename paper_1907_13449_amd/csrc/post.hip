@@ -54,27 +54,36 @@ __device__ __forceinline__ void fill_pixel(const FillArgs& a, int p) {
         a.out[p] = (int16_t)d0;
         return;
     }
-    // rank-based selection: the lower median of n values is the one with
-    // (n-1)/2 values strictly below it and at least (n-1)/2 + 1 at or below it
-    int vals[8], n = 0;
-    for (int i = -1; i <= 1; ++i)
-        for (int j = -1; j <= 1; ++j) {
-            if (i == 0 && j == 0) continue;
-            const int y = v + i, x = u + j;
-            if (y < 0 || y >= H || x < 0 || x >= W) continue;
-            const int d = a.in[(size_t)y * W + x];
-            if (d >= 0) vals[n++] = d;
+    // the 8 neighbours in fixed slots, invalid or outside ones as a sentinel above
+    // every index; a sorting network (Batcher's odd-even merge, 19 comparators)
+    // moves the n valid values to the front in order, and the lower median is
+    // the one at (n-1)/2
+    constexpr int kNone = 0x7FFF;
+    int s[8], n = 0;
+#pragma unroll
+    for (int i = 0, q = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            if (i == 1 && j == 1) continue;
+            const int y = v + i - 1, x = u + j - 1;
+            const int d = y < 0 || y >= H || x < 0 || x >= W ? -1 : a.in[(size_t)y * W + x];
+            s[q++] = d >= 0 ? d : kNone;
+            n += d >= 0;
         }
-    int res = -1;
-    const int want = (n - 1) / 2;
-    for (int x = 0; x < n; ++x) {
-        int below = 0, atmost = 0;
-        for (int y = 0; y < n; ++y) {
-            below += vals[y] < vals[x];
-            atmost += vals[y] <= vals[x];
-        }
-        if (below <= want && want < atmost) res = vals[x];
+    constexpr int kNet[19][2] = {{0, 1}, {2, 3}, {4, 5}, {6, 7}, {0, 2}, {1, 3}, {4, 6},
+                                 {5, 7}, {1, 2}, {5, 6}, {0, 4}, {1, 5}, {2, 6}, {3, 7},
+                                 {2, 4}, {3, 5}, {1, 2}, {3, 4}, {5, 6}};
+#pragma unroll
+    for (int c = 0; c < 19; ++c) {
+        const int x = s[kNet[c][0]], y = s[kNet[c][1]];
+        s[kNet[c][0]] = min(x, y);
+        s[kNet[c][1]] = max(x, y);
     }
+    const int want = (n - 1) / 2;
+    int res = -1;
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+        if (n > 0 && i == want) res = s[i];
     a.out[p] = (int16_t)res;
 }
 
@@ -277,14 +286,20 @@ __device__ __forceinline__ void wta_pixel(const WtaArgs& a, int p) {
     const int l = a.lo[p], h = a.hi[p];
     const SumT* c = (const SumT*)a.csum + a.off[p] - l;     // c[k] for k in [l, h]
     const float* hyp = a.hyp;
+    // in increasing k, strict <, so the lowest index wins ties; eight loads in
+    // flight per round (indices past h re-read c[h] and are not compared)
     int best = l;
     uint32_t bv = c[l];
-    for (int k = l + 1; k <= h; ++k) {
-        const uint32_t x = c[k];
-        if (x < bv) {
-            bv = x;
-            best = k;
-        }
+    for (int k0 = l + 1; k0 <= h; k0 += 8) {
+        uint32_t x[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) x[i] = c[min(k0 + i, h)];
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+            if (k0 + i <= h && x[i] < bv) {
+                bv = x[i];
+                best = k0 + i;
+            }
     }
     a.d_index[p] = (int16_t)best;
     float d = hyp[best];
