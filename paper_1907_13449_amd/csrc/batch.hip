@@ -48,7 +48,7 @@ bool valid_tuning(const lf::Tuning& u) {
         return std::find(ok.begin(), ok.end(), v) != ok.end();
     };
     return in(u.cost_cpt, {2, 4, 8}) && in(u.cost_stride, {1, 2, 4}) &&
-           in(u.dense_depth, {4, 8, 16}) && in(u.bounded_depth, {4, 8});
+           in(u.dense_depth, {4, 8, 16}) && in(u.bounded_depth, {4, 8, 16});
 }
 
 }  // namespace
@@ -226,7 +226,7 @@ lf_status lf_plan_autotune(lf_plan* p, hipStream_t stream, int32_t reps, lf_tuni
     };
     // Phase 1: candidate i takes the i-th value of every list; the stages are
     // timed separately, so each stage's parameter is chosen on its own.
-    const int cpt[3] = {2, 4, 8}, dd[3] = {4, 8, 16}, bd[3] = {4, 8, 8};
+    const int cpt[3] = {2, 4, 8}, dd[3] = {4, 8, 16}, bd[3] = {8, 16, 16};
     double best_cost = 1e30, best_dense = 1e30, best_bounded = 1e30;
     lf::Tuning best = p->tune;
     best.cost_stride = 1;

@@ -622,8 +622,12 @@ hipError_t bounded_variant(Runner& r, const std::vector<BoundedArgs>& args,
         return launch(r, kStSgmFinal, sgm_bounded_paths_kernel<Single<BoundedArgs>, K, 4>,
                       sgm_bounded_paths_kernel<Group<BoundedArgs>, K, 4>, args, blocks,
                       64 * kWavesPerBlock);
-    return launch(r, kStSgmFinal, sgm_bounded_paths_kernel<Single<BoundedArgs>, K, 8>,
-                  sgm_bounded_paths_kernel<Group<BoundedArgs>, K, 8>, args, blocks,
+    if (r.tune.bounded_depth == 8)
+        return launch(r, kStSgmFinal, sgm_bounded_paths_kernel<Single<BoundedArgs>, K, 8>,
+                      sgm_bounded_paths_kernel<Group<BoundedArgs>, K, 8>, args, blocks,
+                      64 * kWavesPerBlock);
+    return launch(r, kStSgmFinal, sgm_bounded_paths_kernel<Single<BoundedArgs>, K, 16>,
+                  sgm_bounded_paths_kernel<Group<BoundedArgs>, K, 16>, args, blocks,
                   64 * kWavesPerBlock);
 }
 

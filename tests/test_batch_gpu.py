@@ -91,7 +91,7 @@ def test_batch_equals_alone(lf, items):
 
 @pytest.mark.parametrize("tuning", [
     dict(cost_cells_per_thread=2, dense_prefetch=4, bounded_prefetch=4),
-    dict(cost_cells_per_thread=8, cost_stride=4, dense_prefetch=16),
+    dict(cost_cells_per_thread=8, cost_stride=4, dense_prefetch=16, bounded_prefetch=8),
     dict(cost_stride=2),
 ])
 def test_batch_every_tuning(lf, items, tuning):
@@ -139,7 +139,7 @@ def test_autotune_keeps_results(lf, items):
     assert chosen["cost_cells_per_thread"] in (2, 4, 8)
     assert chosen["cost_stride"] in (1, 2, 4)
     assert chosen["dense_prefetch"] in (4, 8, 16)
-    assert chosen["bounded_prefetch"] in (4, 8)
+    assert chosen["bounded_prefetch"] in (4, 8, 16)
     assert plan.tuning == chosen
     torch.cuda.synchronize()
     _check(items, order, outs)
