@@ -63,7 +63,8 @@ typedef enum { LF_COST_L2 = 0, LF_COST_CENSUS = 1 } lf_cost_kind;
 
 /* A light field resident in device memory. */
 typedef struct {
-    const void* data;   /* [T][S][C][H][pitch] elements of `dtype` */
+    const void* data;   /* [T][S][C][H][pitch] elements of `dtype`; float32 views
+                           must be finite (results for NaN or inf are unspecified) */
     int32_t S, T, H, W;
     int32_t pitch;      /* elements between rows, >= W; planes are H*pitch apart */
     int32_t dtype;      /* lf_dtype */

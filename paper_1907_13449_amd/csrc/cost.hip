@@ -164,15 +164,14 @@ __device__ __forceinline__ void l2_slices(const L2Args& a, uint32_t b, int64_t* 
             for (int c = 0; c < C; ++c)
                 ref[c] = ld(refv + (uint32_t)c * vstride + (uint32_t)(v + 1) * Wp + u + 1);
             float acc = 0.0f;
-            for (int t = 0; t < T_; ++t) {
-                const float shy = (float)(th - t) * d;
-                const float y0 = floorf(shy);
-                const float fy = shy - y0;
-                // top tap row in padded coordinates; the bottom one follows it
-                const uint32_t rt = (uint32_t)(clampi(v + (int)y0, -1, H - 1) + 1) * Wp;
-                const T* __restrict__ vt = views + (size_t)t * S * C * vstride;
+            // one row of views: taps for every s at vertical fraction fy from the
+            // rows rt and rt + Wp of row t.  The reference row of views (t = t_hat)
+            // has no vertical shift: fy = 0, and fma(0, b - t, t) is t exactly, so
+            // there the bottom taps are not loaded (a separate, branch-free loop)
+            auto view_row = [&](const T* __restrict__ vt, uint32_t rt, float fy, bool flat,
+                                bool skip_ref) {
                 for (int s = 0; s < S; ++s) {
-                    if (s == sh && t == th) continue;        // adds exactly +0
+                    if (skip_ref && s == sh) continue;       // adds exactly +0
                     const float shx = (float)(sh - s) * d;
                     const float x0 = floorf(shx);
                     const float fx = shx - x0;
@@ -182,16 +181,29 @@ __device__ __forceinline__ void l2_slices(const L2Args& a, uint32_t b, int64_t* 
                     for (int c = 0; c < C; ++c) {
                         const T* __restrict__ vs = vt + (uint32_t)(s * C + c) * vstride;
                         const Pair<T> top = ld_pair(vs + o);
-                        const Pair<T> bot = ld_pair(vs + o + Wp);
                         const float tv = fmaf(fx, top.hi - top.lo, top.lo);
-                        const float bv = fmaf(fx, bot.hi - bot.lo, bot.lo);
-                        const float val = fmaf(fy, bv - tv, tv);
+                        float val = tv;
+                        if (!flat) {
+                            const Pair<T> bot = ld_pair(vs + o + Wp);
+                            const float bv = fmaf(fx, bot.hi - bot.lo, bot.lo);
+                            val = fmaf(fy, bv - tv, tv);
+                        }
                         const float dl = ref[c] - val;
                         dist = fabsf(dl);
                         sq = c == 0 ? dl * dl : fmaf(dl, dl, sq);   // colour: l2 norm
                     }
                     acc = acc + (C == 1 ? dist : sqrtf(sq));
                 }
+            };
+            for (int t = 0; t < T_; ++t) {
+                const float shy = (float)(th - t) * d;
+                const float y0 = floorf(shy);
+                const float fy = shy - y0;
+                // top tap row in padded coordinates; the bottom one follows it
+                const uint32_t rt = (uint32_t)(clampi(v + (int)y0, -1, H - 1) + 1) * Wp;
+                const T* __restrict__ vt = views + (size_t)t * S * C * vstride;
+                if (t == th) view_row(vt, rt, fy, true, true);
+                else view_row(vt, rt, fy, false, false);
             }
             const float q = rintf(a.alpha * acc);
             a.cost[c] = (uint16_t)(q > a.cap ? a.cap : q);
