@@ -164,36 +164,47 @@ __device__ __forceinline__ void l2_slices(const L2Args& a, uint32_t b, int64_t* 
             for (int c = 0; c < C; ++c)
                 ref[c] = ld(refv + (uint32_t)c * vstride + (uint32_t)(v + 1) * Wp + u + 1);
             float acc = 0.0f;
-            // one row of views: taps for every s at vertical fraction fy from the
-            // rows rt and rt + Wp of row t.  The reference row of views (t = t_hat)
-            // has no vertical shift: fy = 0, and fma(0, b - t, t) is t exactly, so
-            // there the bottom taps are not loaded (a separate, branch-free loop)
-            auto view_row = [&](const T* __restrict__ vt, uint32_t rt, float fy, bool flat,
-                                bool skip_ref) {
-                for (int s = 0; s < S; ++s) {
-                    if (skip_ref && s == sh) continue;       // adds exactly +0
-                    const float shx = (float)(sh - s) * d;
-                    const float x0 = floorf(shx);
-                    const float fx = shx - x0;
-                    const uint32_t o = rt + (uint32_t)(clampi(u + (int)x0, -1, W - 1) + 1);
-                    float sq = 0.0f, dist = 0.0f;
+            // one view of row t: taps at horizontal fraction fx from the rows rt and
+            // rt + Wp.  Two cases skip taps that are weighted by an exact 0, since
+            // fma(0, b - a, a) is a exactly: the reference row of views (t = t_hat,
+            // flat: fy = 0, no bottom taps) and the reference column (s = s_hat,
+            // col: fx = 0, only the left tap of each row).  Each case is its own
+            // branch-free copy of the loop body.
+            auto view = [&](const T* __restrict__ vt, uint32_t rt, float fy, int s, bool flat,
+                            bool col) {
+                const float shx = (float)(sh - s) * d;
+                const float x0 = floorf(shx);
+                const float fx = shx - x0;
+                const uint32_t o = rt + (uint32_t)(clampi(u + (int)x0, -1, W - 1) + 1);
+                float sq = 0.0f, dist = 0.0f;
 #pragma unroll
-                    for (int c = 0; c < C; ++c) {
-                        const T* __restrict__ vs = vt + (uint32_t)(s * C + c) * vstride;
+                for (int c = 0; c < C; ++c) {
+                    const T* __restrict__ vs = vt + (uint32_t)(s * C + c) * vstride;
+                    float tv, val;
+                    if (col) {
+                        tv = ld(vs + o);
+                        val = flat ? tv : fmaf(fy, ld(vs + o + Wp) - tv, tv);
+                    } else {
                         const Pair<T> top = ld_pair(vs + o);
-                        const float tv = fmaf(fx, top.hi - top.lo, top.lo);
-                        float val = tv;
+                        tv = fmaf(fx, top.hi - top.lo, top.lo);
+                        val = tv;
                         if (!flat) {
                             const Pair<T> bot = ld_pair(vs + o + Wp);
                             const float bv = fmaf(fx, bot.hi - bot.lo, bot.lo);
                             val = fmaf(fy, bv - tv, tv);
                         }
-                        const float dl = ref[c] - val;
-                        dist = fabsf(dl);
-                        sq = c == 0 ? dl * dl : fmaf(dl, dl, sq);   // colour: l2 norm
                     }
-                    acc = acc + (C == 1 ? dist : sqrtf(sq));
+                    const float dl = ref[c] - val;
+                    dist = fabsf(dl);
+                    sq = c == 0 ? dl * dl : fmaf(dl, dl, sq);   // colour: l2 norm
                 }
+                acc = acc + (C == 1 ? dist : sqrtf(sq));
+            };
+            // s ascending; the reference view itself adds exactly +0 and is skipped
+            auto view_row = [&](const T* __restrict__ vt, uint32_t rt, float fy, bool flat) {
+                for (int s = 0; s < sh; ++s) view(vt, rt, fy, s, flat, false);
+                if (!flat) view(vt, rt, fy, sh, false, true);
+                for (int s = sh + 1; s < S; ++s) view(vt, rt, fy, s, flat, false);
             };
             for (int t = 0; t < T_; ++t) {
                 const float shy = (float)(th - t) * d;
@@ -202,8 +213,8 @@ __device__ __forceinline__ void l2_slices(const L2Args& a, uint32_t b, int64_t* 
                 // top tap row in padded coordinates; the bottom one follows it
                 const uint32_t rt = (uint32_t)(clampi(v + (int)y0, -1, H - 1) + 1) * Wp;
                 const T* __restrict__ vt = views + (size_t)t * S * C * vstride;
-                if (t == th) view_row(vt, rt, fy, true, true);
-                else view_row(vt, rt, fy, false, false);
+                if (t == th) view_row(vt, rt, fy, true);
+                else view_row(vt, rt, fy, false);
             }
             const float q = rintf(a.alpha * acc);
             a.cost[c] = (uint16_t)(q > a.cap ? a.cap : q);
