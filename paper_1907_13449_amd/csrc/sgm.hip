@@ -136,13 +136,13 @@ __device__ __forceinline__ void sgm_step(const uint32_t (&Lp)[K], uint32_t m, ui
                                          uint32_t P2, const uint32_t (&C)[K], uint32_t (&L)[K]) {
     const uint32_t left = dpp<0x138>(UINT_MAX, Lp[K - 1]);   // wave_shr:1 -> from lane l-1
     const uint32_t right = dpp<0x130>(UINT_MAX, Lp[0]);      // wave_shl:1 -> from lane l+1
-    const uint32_t mP2 = m + P2;
+    const uint32_t mP2 = m + P2, negm = 0u - m;
 #pragma unroll
     for (int j = 0; j < K; ++j) {
         const uint32_t lm = j == 0 ? left : Lp[j - 1];
         const uint32_t lp = j == K - 1 ? right : Lp[j + 1];
         const uint32_t t = min(min(Lp[j], mP2), min(lm, lp) + P1);
-        L[j] = C[j] + (t - m);
+        L[j] = C[j] + t + negm;              // C + t - m as one three-input add
     }
 }
 
@@ -155,9 +155,9 @@ __device__ __forceinline__ uint32_t lane_min(const uint32_t (&L)[K]) {
 }
 
 // ---------------------------------------------------------------------------
-// Initial stage, Eq. (7): the Census cost volume C[z][p][NP] (8-bit, NP = N
-// rounded up to 4) of every cross view, computed once and read by all path
-// directions.  A workgroup builds the tile of 64 consecutive pixels x NP
+// Initial stage, Eq. (7): the Census cost volume C[z][p][NPc] (8-bit; NPc = N + 2
+// rounded up to 4, at most 256) of every cross view, computed once and read by
+// all path directions.  Bytes k >= N of a row hold 255.  A workgroup builds the tile of 64 consecutive pixels x NP
 // hypotheses in LDS with lanes over pixels -- for a fixed hypothesis the 64
 // gathered Census strings are consecutive in memory for both shift axes -- and
 // then writes the tile, which is contiguous in C, with 32-bit stores.
@@ -168,9 +168,9 @@ struct CcvArgs {
     const uint64_t* cview;    // [nv][C][H*W]
     const float* hyp;
     int cs[4], ct[4];         // s_hat - s, t_hat - t of each cross view
-    int nv, C, H, W, N, NP;
+    int nv, C, H, W, N, NP;   // NP: the row stride NPc
     uint32_t tiles;           // pixel tiles per view
-    uint8_t* cvol;            // [nv][H*W][NP]
+    uint8_t* cvol;            // [nv][H*W][NPc]
 };
 
 __device__ __forceinline__ void ccv_block(const CcvArgs& a, uint32_t b, uint32_t* tile,
@@ -205,7 +205,7 @@ __device__ __forceinline__ void ccv_block(const CcvArgs& a, uint32_t b, uint32_t
 #pragma unroll
         for (int c = 0; c < 3; ++c)
             if (c < C) hd += (uint32_t)__popcll(r[c] ^ cv[(size_t)c * HW + q]);
-        t8[lane * NP + k] = k < N ? (uint8_t)hd : (uint8_t)0;
+        t8[lane * NP + k] = k < N ? (uint8_t)hd : (uint8_t)255;
     }
     __syncthreads();
     // the tile is npix * NP contiguous bytes of C (NP is a multiple of 4)
@@ -229,38 +229,47 @@ __global__ __launch_bounds__(256) void census_cost_volume_kernel(Src src) {
 // SGM over the Census cost volume, every direction of every view in one launch.
 // Output: Lbuf[r][z][p][NP], storage type LT.
 struct DenseArgs {
-    const uint8_t* cvol;
+    const uint8_t* cvol;      // [nv][H*W][NPc]
     void* Lbuf;
     Lines lines;
-    int nv, H, W, N, NP;
+    int nv, H, W, N, NP, NPc;
     uint32_t P1, P2;
     uint32_t wblocks;         // blocks per view
 };
 
-template <int K, typename LT, int D>
+// kPad (8-bit path costs, K <= 2, and B + 2 P2 <= 255 + P1 for the largest Census
+// cost B): hypotheses k >= N read the 255 that pads each cost row instead of
+// adding kInf.  Their path costs then stay >= 255 while every real one stays
+// <= B + P2 <= 255, so they never lower the minimum m, and as the neighbour of
+// k = N-1 their 255 + P1 >= m + P2 (m <= B + P2) never wins the min of Eq. (8):
+// the real path costs are those of the exact recurrence.
+template <int K, typename LT, int D, bool kPad>
 __device__ __forceinline__ void dense_wave(const DenseArgs& a, uint32_t b) {
     const int lane = threadIdx.x & 63;
     const int z = (int)(b / a.wblocks);
     const uint32_t wb = b - (uint32_t)z * a.wblocks;
     const int g = __builtin_amdgcn_readfirstlane(wb * kWavesPerBlock + (threadIdx.x >> 6));
     if (g >= a.lines.base[a.lines.npaths]) return;        // wave-uniform exit
-    const int H = a.H, W = a.W, N = a.N, NP = a.NP;
+    const int H = a.H, W = a.W, N = a.N, NP = a.NP, NPc = a.NPc;
     const uint32_t P1 = a.P1, P2 = a.P2;
     const LineInfo li = locate(a.lines, H, W, g);
     const uint32_t HW = (uint32_t)H * W;
-    const uint8_t* __restrict__ cz = a.cvol + (size_t)z * HW * NP;
+    const uint8_t* __restrict__ cz = a.cvol + (size_t)z * HW * NPc;
     LT* __restrict__ out = (LT*)a.Lbuf + ((size_t)li.r * a.nv + z) * HW * NP;
 
-    // the lane's K bytes of a pixel row; lanes past N read in-row bytes and add kInf
-    const uint32_t lofs = (uint32_t)min(lane * K, NP - K);
+    // the lane's K bytes of a pixel row; lanes past N read the row's last bytes
+    // (with kPad: its 255 padding, since NPc >= N + 2) and, without kPad, add kInf
+    const uint32_t lofs = (uint32_t)min(lane * K, NPc - K);
     uint32_t cinit[K];
 #pragma unroll
-    for (int j = 0; j < K; ++j) cinit[j] = lane * K + j < N ? 0u : kInf;
+    for (int j = 0; j < K; ++j) cinit[j] = kPad || lane * K + j < N ? 0u : kInf;
     const int last = li.len - 1;
+    // one load per step for the K bytes (the texture units, shared by the CU's
+    // four SIMDs, would otherwise bound the kernel)
     auto load = [&](int step) -> uint32_t {
         step = min(step, last);
         const uint32_t p = (uint32_t)((li.v0 + step * li.dv) * W + li.u0 + step * li.du);
-        const uint32_t o = p * (uint32_t)NP + lofs;      // 32-bit offset off a scalar base
+        const uint32_t o = p * (uint32_t)NPc + lofs;     // 32-bit offset off a scalar base
         if constexpr (K == 1) return cz[o];
         else if constexpr (K == 2) return *(const uint16_t*)(cz + o);
         else if constexpr (K == 4) return *(const uint32_t*)(cz + o);
@@ -279,7 +288,10 @@ __device__ __forceinline__ void dense_wave(const DenseArgs& a, uint32_t b) {
             const int step = base + i;           // steps past the line end are computed
             uint32_t C[K];                       // and not stored
 #pragma unroll
-            for (int j = 0; j < K; ++j) C[j] = ((cb[i] >> (8 * j)) & 0xFFu) + cinit[j];
+            for (int j = 0; j < K; ++j) {
+                const uint32_t byte = (cb[i] >> (8 * j)) & 0xFFu;
+                C[j] = kPad ? byte : byte + cinit[j];
+            }
             cb[i] = load(step + D);              // refill the slot just consumed
             uint32_t L[K];
             if (step == 0) {
@@ -312,12 +324,12 @@ __device__ __forceinline__ void dense_wave(const DenseArgs& a, uint32_t b) {
     }
 }
 
-template <class Src, int K, typename LT, int D>
+template <class Src, int K, typename LT, int D, bool kPad>
 __global__ __launch_bounds__(64 * kWavesPerBlock) void sgm_dense_paths_kernel(Src src) {
     for (uint32_t vb = blockIdx.x; vb < src.total; vb += gridDim.x) {
         uint32_t b;
         const DenseArgs& a = member(src, vb, b);
-        dense_wave<K, LT, D>(a, b);
+        dense_wave<K, LT, D, kPad>(a, b);
     }
 }
 
@@ -585,33 +597,44 @@ __global__ __launch_bounds__(256) void bounded_sum_kernel(Src src) {
 }
 
 // --- host-side dispatch of the kernel variants ---------------------------------
-template <int K, typename LT>
+template <int K, typename LT, bool kPad>
 hipError_t dense_variant(Runner& r, const std::vector<DenseArgs>& args,
                          const std::vector<uint32_t>& blocks) {
     switch (r.tune.dense_depth) {
         case 4:
-            return launch(r, kStSgmInit, sgm_dense_paths_kernel<Single<DenseArgs>, K, LT, 4>,
-                          sgm_dense_paths_kernel<Group<DenseArgs>, K, LT, 4>, args, blocks,
+            return launch(r, kStSgmInit, sgm_dense_paths_kernel<Single<DenseArgs>, K, LT, 4, kPad>,
+                          sgm_dense_paths_kernel<Group<DenseArgs>, K, LT, 4, kPad>, args, blocks,
                           64 * kWavesPerBlock);
         case 16:
-            return launch(r, kStSgmInit, sgm_dense_paths_kernel<Single<DenseArgs>, K, LT, 16>,
-                          sgm_dense_paths_kernel<Group<DenseArgs>, K, LT, 16>, args, blocks,
+            return launch(r, kStSgmInit, sgm_dense_paths_kernel<Single<DenseArgs>, K, LT, 16, kPad>,
+                          sgm_dense_paths_kernel<Group<DenseArgs>, K, LT, 16, kPad>, args, blocks,
                           64 * kWavesPerBlock);
         default:
-            return launch(r, kStSgmInit, sgm_dense_paths_kernel<Single<DenseArgs>, K, LT, 8>,
-                          sgm_dense_paths_kernel<Group<DenseArgs>, K, LT, 8>, args, blocks,
+            return launch(r, kStSgmInit, sgm_dense_paths_kernel<Single<DenseArgs>, K, LT, 8, kPad>,
+                          sgm_dense_paths_kernel<Group<DenseArgs>, K, LT, 8, kPad>, args, blocks,
                           64 * kWavesPerBlock);
     }
 }
 
-template <typename LT>
-hipError_t dense_k(Runner& r, int K, const std::vector<DenseArgs>& args,
+// v: 0 8-bit path costs, 1 16-bit, 2 8-bit with the padded rows standing in for
+// kInf (K <= 2 only)
+hipError_t dense_k(Runner& r, int K, int v, const std::vector<DenseArgs>& args,
                    const std::vector<uint32_t>& blocks) {
+    if (v == 2) return K == 1 ? dense_variant<1, uint8_t, true>(r, args, blocks)
+                              : dense_variant<2, uint8_t, true>(r, args, blocks);
+    if (v == 1) {
+        switch (K) {
+            case 1: return dense_variant<1, uint16_t, false>(r, args, blocks);
+            case 2: return dense_variant<2, uint16_t, false>(r, args, blocks);
+            case 3: return dense_variant<3, uint16_t, false>(r, args, blocks);
+            default: return dense_variant<4, uint16_t, false>(r, args, blocks);
+        }
+    }
     switch (K) {
-        case 1: return dense_variant<1, LT>(r, args, blocks);
-        case 2: return dense_variant<2, LT>(r, args, blocks);
-        case 3: return dense_variant<3, LT>(r, args, blocks);
-        default: return dense_variant<4, LT>(r, args, blocks);
+        case 1: return dense_variant<1, uint8_t, false>(r, args, blocks);
+        case 2: return dense_variant<2, uint8_t, false>(r, args, blocks);
+        case 3: return dense_variant<3, uint8_t, false>(r, args, blocks);
+        default: return dense_variant<4, uint8_t, false>(r, args, blocks);
     }
 }
 
@@ -649,9 +672,13 @@ uint32_t div_up(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
 
 int dense_np(int N) { return (N + 3) / 4 * 4; }
 
+// Row stride of the initial Census cost volume: room for two bytes of 255 after
+// the N costs (hypotheses past N read them), within the 256-byte LDS tile rows.
+int dense_cvol_np(int N) { return min(dense_np(N + 2), LF_MAX_HYPOTHESES); }
+
 size_t sgm_dense_scratch_bytes(int nv, int H, int W, int N, int npaths, int bits, int P2) {
     const size_t lt = bits + P2 <= 255 ? 1 : 2;
-    const size_t cv = round256((size_t)nv * H * W * dense_np(N));
+    const size_t cv = round256((size_t)nv * H * W * dense_cvol_np(N));
     // + 256: the row-wise sum reads up to 128 bytes past the last pixel's row
     return cv + (size_t)npaths * nv * H * W * dense_np(N) * lt + 256;
 }
@@ -664,21 +691,21 @@ size_t sgm_bounded_scratch_bytes(int H, int W, int N, int npaths) {
 hipError_t stage_sgm_initial(Runner& r, const Jobs& jobs) {
     std::vector<CcvArgs> ccv;
     std::vector<uint32_t> ccv_blocks;
-    // variants: K in 1..4 x path-cost storage (8 or 16 bit)
-    std::vector<DenseArgs> dense[4][2];
-    std::vector<uint32_t> dense_blocks[4][2];
+    // variants: K in 1..4 x (8-bit, 16-bit, 8-bit with padded rows)
+    std::vector<DenseArgs> dense[4][3];
+    std::vector<uint32_t> dense_blocks[4][3];
     std::vector<SumWtaArgs> sums[2][2];            // [8/16-bit path costs][8/16 paths]
     std::vector<uint32_t> sum_blocks[2][2];
     std::vector<SumWtaArgs> rows[2];               // 8-bit rows <= 128 B: [8/16 paths]
     std::vector<uint32_t> row_blocks[2];
     for (const Job* j : jobs) {
-        const int H = j->H, W = j->W, N = j->N, NP = dense_np(N);
+        const int H = j->H, W = j->W, N = j->N, NP = dense_np(N), NPc = dense_cvol_np(N);
         const size_t HW = (size_t)H * W;
         const lf_sgm_params& sp = j->prm.sgm_init;
         const int bits = j->C * (j->prm.census.win_h * j->prm.census.win_w - 1);
         const int lt = bits + sp.P2 <= 255 ? 0 : 1;
         uint8_t* cvol = (uint8_t*)j->paths;
-        void* Lbuf = (char*)j->paths + round256((size_t)j->nv * HW * NP);
+        void* Lbuf = (char*)j->paths + round256((size_t)j->nv * HW * NPc);
         const int sh = (j->S - 1) / 2, th = (j->T - 1) / 2;
 
         CcvArgs c{};
@@ -694,7 +721,7 @@ hipError_t stage_sgm_initial(Runner& r, const Jobs& jobs) {
         c.H = H;
         c.W = W;
         c.N = N;
-        c.NP = NP;
+        c.NP = NPc;
         c.tiles = div_up(HW, kTilePix);
         c.cvol = cvol;
         ccv.push_back(c);
@@ -709,12 +736,14 @@ hipError_t stage_sgm_initial(Runner& r, const Jobs& jobs) {
         d.W = W;
         d.N = N;
         d.NP = NP;
+        d.NPc = NPc;
         d.P1 = (uint32_t)sp.P1;
         d.P2 = (uint32_t)sp.P2;
         d.wblocks = div_up(d.lines.base[d.lines.npaths], kWavesPerBlock);
         const int K = (N + 63) / 64 - 1;
-        dense[K][lt].push_back(d);
-        dense_blocks[K][lt].push_back(d.wblocks * j->nv);
+        const int v = lt == 0 && K <= 1 && bits + 2 * sp.P2 <= 255 + sp.P1 ? 2 : lt;
+        dense[K][v].push_back(d);
+        dense_blocks[K][v].push_back(d.wblocks * j->nv);
 
         SumWtaArgs s{};
         s.Lbuf = Lbuf;
@@ -736,11 +765,9 @@ hipError_t stage_sgm_initial(Runner& r, const Jobs& jobs) {
                           census_cost_volume_kernel<Group<CcvArgs>>, ccv, ccv_blocks, 256);
     if (e != hipSuccess) return e;
     for (int K = 0; K < 4; ++K)
-        for (int lt = 0; lt < 2; ++lt) {
-            if (dense[K][lt].empty()) continue;
-            e = lt == 0 ? dense_k<uint8_t>(r, K + 1, dense[K][lt], dense_blocks[K][lt])
-                        : dense_k<uint16_t>(r, K + 1, dense[K][lt], dense_blocks[K][lt]);
-            if (e != hipSuccess) return e;
+        for (int v = 0; v < 3; ++v) {
+            if (dense[K][v].empty()) continue;
+            if ((e = dense_k(r, K + 1, v, dense[K][v], dense_blocks[K][v])) != hipSuccess) return e;
         }
     constexpr uint32_t kSumGrid = 8192;       // persistent: each workgroup walks pixels
     using SA = SumWtaArgs;
