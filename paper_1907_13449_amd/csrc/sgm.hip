@@ -197,16 +197,27 @@ __device__ __forceinline__ void ccv_block(const CcvArgs& a, uint32_t b, uint32_t
     for (int c = 0; c < 3; ++c) r[c] = c < C ? a.cref[(size_t)c * HW + p] : 0;
     const uint64_t* __restrict__ cv = a.cview + (size_t)z * C * HW;
     uint8_t* t8 = (uint8_t*)tile;
-    for (int k = wave; k < NP; k += 4) {          // k is wave-uniform
-        const int sh = s_sh[k];
-        const uint32_t q = along_u ? (uint32_t)(v * W + clampi(u + sh, 0, W - 1))
-                                   : (uint32_t)(clampi(v + sh, 0, H - 1) * W + u);
-        uint32_t hd = 0;
+    // The rounded shift is monotone in k, so consecutive hypotheses mostly share
+    // it (at |s_hat - s| * (d_k+1 - d_k) < 1 a shift spans several k): wave w
+    // walks the quarter [wN/4, (w+1)N/4) of the hypotheses in order and gathers
+    // and counts a Census string only when the shift changes.
+    const int kb = N * wave / 4, ke = N * (wave + 1) / 4;
+    int prev = INT_MIN;
+    uint32_t hd = 0;
+    for (int k = kb; k < ke; ++k) {                  // k is wave-uniform
+        const int sh = __builtin_amdgcn_readfirstlane(s_sh[k]);
+        if (sh != prev) {
+            prev = sh;
+            const uint32_t q = along_u ? (uint32_t)(v * W + clampi(u + sh, 0, W - 1))
+                                       : (uint32_t)(clampi(v + sh, 0, H - 1) * W + u);
+            hd = 0;
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
-            if (c < C) hd += (uint32_t)__popcll(r[c] ^ cv[(size_t)c * HW + q]);
-        t8[lane * NP + k] = k < N ? (uint8_t)hd : (uint8_t)255;
+            for (int c = 0; c < 3; ++c)
+                if (c < C) hd += (uint32_t)__popcll(r[c] ^ cv[(size_t)c * HW + q]);
+        }
+        t8[lane * NP + k] = (uint8_t)hd;
     }
+    for (int k = N + wave; k < NP; k += 4) t8[lane * NP + k] = (uint8_t)255;
     __syncthreads();
     // the tile is npix * NP contiguous bytes of C (NP is a multiple of 4)
     uint32_t* dst = (uint32_t*)(a.cvol + ((size_t)z * HW + p0) * NP);
