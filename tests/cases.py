@@ -69,6 +69,11 @@ def case(name):
         lf.params.update(cost_kind=1, win_h=5, win_w=5, sum_bits=16, alpha=1.0,
                          edge_tau=60.0)
         return lf
+    if name == "u8_inf_add":                 # 8-bit path costs, but B + 2 P2 > 255 + P1:
+        # hypotheses past N carry +inf by an add, not through the padded cost rows
+        lf = lfsynth.workload("paper_s", seed=21, H=29, W=37, S=5, T=5, N=99)
+        lf.params.update(P1_init=10, P2_init=190)
+        return lf
     if name == "adaptive":                   # depth-adaptive borders (Sec. 4.6)
         lf = lfsynth.workload("paper_s", seed=20, H=44, W=50, S=7, T=7, N=80)
         lf.params.update(lam=2, lam_far=6)
@@ -78,6 +83,6 @@ def case(name):
 
 CASES = ["small", "f32_ragged", "u8_n65", "n256", "stage_1x11", "col_7x1", "one_row", "one_col",
          "u16_paths", "census_cost", "paths16", "paths16_u16", "boundless", "rgb_f32",
-         "rgb_u8_census", "adaptive"]
+         "rgb_u8_census", "adaptive", "u8_inf_add"]
 
 
