@@ -26,12 +26,16 @@ __global__ __launch_bounds__(kThreads) void fuse_kernel(Src src) {
         const FuseArgs& a = member(src, vb, b);
         const int p = (int)b * kThreads + threadIdx.x;
         if (p >= a.HW) continue;
-        int acc = a.maps[p];
+        int d[4];                                 // |V| <= 4: all loads in flight at once
+#pragma unroll
+        for (int i = 0; i < 4; ++i) d[i] = i < a.nv ? a.maps[(size_t)i * a.HW + p] : 0;
+        int acc = d[0];
         bool valid = true;
-        for (int i = 1; i < a.nv; ++i) {
-            const int di = a.maps[(size_t)i * a.HW + p];
-            if (valid && abs(acc - di) < a.phi)
-                acc = (acc + di) >> 1;
+#pragma unroll
+        for (int i = 1; i < 4; ++i) {
+            if (i >= a.nv) break;
+            if (valid && abs(acc - d[i]) < a.phi)
+                acc = (acc + d[i]) >> 1;
             else
                 valid = false;
         }
