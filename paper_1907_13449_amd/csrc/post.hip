@@ -119,8 +119,9 @@ __device__ __forceinline__ int border_width(int lambda, int lambda_far, int d, i
     return lambda + ((lambda_far - lambda) * (N - 1 - d) + (N - 1) / 2) / (N - 1);
 }
 
+// d: the filled initial index of pixel p (dinit[p])
 template <typename T>
-__device__ __forceinline__ void borders_pixel(const BordersArgs& a, int p) {
+__device__ __forceinline__ void borders_pixel(const BordersArgs& a, int p, int d) {
     const int H = a.H, W = a.W;
     const T* __restrict__ ref = (const T*)a.ref;
     const int v = p / W, u = p - v * W;
@@ -138,7 +139,6 @@ __device__ __forceinline__ void borders_pixel(const BordersArgs& a, int p) {
         g = gc > g ? gc : g;
     }
     const bool edge = a.alpha * g > a.tau;
-    const int d = a.dinit[p];
     if (a.lambda < 0 || d < 0 || edge) {          // lambda < 0: boundary-less search
         a.lo[p] = 0;
         a.hi[p] = (int16_t)(a.N - 1);
@@ -155,7 +155,118 @@ __global__ __launch_bounds__(kThreads) void borders_kernel(Src src) {
         uint32_t b;
         const BordersArgs& a = member(src, vb, b);
         const int p = (int)b * kThreads + threadIdx.x;
-        if (p < a.H * a.W) borders_pixel<T>(a, p);
+        if (p < a.H * a.W) borders_pixel<T>(a, p, a.dinit[p]);
+    }
+}
+
+// --- fusion, hole filling and borders in one launch -------------------------
+// A workgroup owns a 32 x 8 tile of pixels.  It fuses the cross views' maps over
+// the tile plus a halo of F = fill_passes pixels into LDS, runs the F Jacobi
+// fill passes there (pass f is exact on the tile grown by F - f, since a pass
+// reads only the 8 neighbours), and then applies the Sobel test and Eq. (11) to
+// its own pixels: the same values as the fuse / fill / borders kernels, with no
+// round trips of the intermediate maps and one launch instead of 2 + F.
+// Halo positions outside the image read as invalid (-1), which the fill treats
+// as it treats a missing neighbour.
+constexpr int kPrepTX = 32, kPrepTY = 8, kMaxPrepFill = 3;
+constexpr int kPrepMax = (kPrepTX + 2 * kMaxPrepFill) * (kPrepTY + 2 * kMaxPrepFill);
+
+struct PrepArgs {
+    FuseArgs fuse;            // fuse.dinit: the filled map (dinit)
+    BordersArgs brd;
+    int fill;                 // passes, <= kMaxPrepFill
+    int tx;                   // tiles along x
+};
+
+template <class Src, typename T>
+__global__ __launch_bounds__(kThreads) void prep_kernel(Src src) {
+    __shared__ int16_t buf[2][kPrepMax];
+    for (uint32_t vb = blockIdx.x; vb < src.total; vb += gridDim.x) {
+        uint32_t b;
+        const PrepArgs& a = member(src, vb, b);
+        const int H = a.brd.H, W = a.brd.W, F = a.fill;
+        const int by = (int)b / a.tx, bx = (int)b - by * a.tx;
+        const int EW = kPrepTX + 2 * F, EH = kPrepTY + 2 * F;
+        const int x0 = bx * kPrepTX - F, y0 = by * kPrepTY - F;
+        __syncthreads();                          // LDS of the previous tile is read
+        for (int i = threadIdx.x; i < EW * EH; i += kThreads) {
+            const int ey = i / EW, ex = i - ey * EW;
+            const int y = y0 + ey, x = x0 + ex;
+            int out = -1;
+            if (y >= 0 && y < H && x >= 0 && x < W) {
+                const int p = y * W + x;
+                const FuseArgs& f = a.fuse;
+                int d[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) d[v] = v < f.nv ? f.maps[(size_t)v * f.HW + p] : 0;
+                int acc = d[0];
+                bool valid = true;
+#pragma unroll
+                for (int v = 1; v < 4; ++v) {
+                    if (v >= f.nv) break;
+                    if (valid && abs(acc - d[v]) < f.phi)
+                        acc = (acc + d[v]) >> 1;
+                    else
+                        valid = false;
+                }
+                out = valid ? acc : -1;
+            }
+            buf[0][i] = (int16_t)out;
+        }
+        __syncthreads();
+        int cur = 0;
+        for (int pass = 1; pass <= F; ++pass) {
+            const int16_t* in = buf[cur];
+            int16_t* o = buf[cur ^ 1];
+            for (int i = threadIdx.x; i < EW * EH; i += kThreads) {
+                const int ey = i / EW, ex = i - ey * EW;
+                if (ey < pass || ey >= EH - pass || ex < pass || ex >= EW - pass) continue;
+                const int d0 = in[i];
+                const int y = y0 + ey, x = x0 + ex;
+                if (d0 >= 0 || y < 0 || y >= H || x < 0 || x >= W) {
+                    o[i] = (int16_t)d0;               // outside the image: stays absent (-1)
+                    continue;
+                }
+                // lower median of the valid neighbours (as fill_pixel)
+                constexpr int kNone = 0x7FFF;
+                int sv[8], n = 0;
+#pragma unroll
+                for (int dy = 0, q = 0; dy < 3; ++dy)
+#pragma unroll
+                    for (int dx = 0; dx < 3; ++dx) {
+                        if (dy == 1 && dx == 1) continue;
+                        const int d = in[i + (dy - 1) * EW + dx - 1];
+                        sv[q++] = d >= 0 ? d : kNone;
+                        n += d >= 0;
+                    }
+                constexpr int kNet[19][2] = {{0, 1}, {2, 3}, {4, 5}, {6, 7}, {0, 2}, {1, 3}, {4, 6},
+                                             {5, 7}, {1, 2}, {5, 6}, {0, 4}, {1, 5}, {2, 6}, {3, 7},
+                                             {2, 4}, {3, 5}, {1, 2}, {3, 4}, {5, 6}};
+#pragma unroll
+                for (int c = 0; c < 19; ++c) {
+                    const int x = sv[kNet[c][0]], y = sv[kNet[c][1]];
+                    sv[kNet[c][0]] = min(x, y);
+                    sv[kNet[c][1]] = max(x, y);
+                }
+                const int want = (n - 1) / 2;
+                int res = -1;
+#pragma unroll
+                for (int k = 0; k < 8; ++k)
+                    if (n > 0 && k == want) res = sv[k];
+                o[i] = (int16_t)res;
+            }
+            __syncthreads();
+            cur ^= 1;
+        }
+        // this thread's pixel of the tile
+        const int lx = threadIdx.x % kPrepTX, ly = threadIdx.x / kPrepTX;
+        const int x = bx * kPrepTX + lx, y = by * kPrepTY + ly;
+        if (x < W && y < H) {
+            const int p = y * W + x;
+            const int d = buf[cur][(ly + F) * EW + lx + F];
+            a.fuse.dinit[p] = (int16_t)d;
+            borders_pixel<T>(a.brd, p, d);
+        }
     }
 }
 
@@ -375,18 +486,19 @@ size_t scan_scratch_bytes(int64_t HW) {
 }
 
 hipError_t stage_borders(Runner& r, const Jobs& jobs) {
+    // light fields with at most kMaxPrepFill fill passes: one tile kernel; others:
+    // fusion, the fill passes and the borders as separate launches
+    std::vector<PrepArgs> prep[2];
+    std::vector<uint32_t> prep_blocks[2];
     std::vector<FuseArgs> fuse;
     std::vector<uint32_t> fuse_blocks;
     std::vector<BordersArgs> brd[2];
     std::vector<uint32_t> brd_blocks[2];
+    Jobs sep;
     int max_passes = 0;
     for (const Job* j : jobs) {
         const int HW = j->H * j->W;
-        int16_t* buf[2] = {j->dinit, j->fill_tmp};
-        // the passes ping-pong between the two buffers and end in dinit
-        fuse.push_back(FuseArgs{j->maps, buf[j->prm.fill_passes % 2], j->nv, HW, j->prm.phi});
-        fuse_blocks.push_back(blocks_for(HW));
-        max_passes = std::max(max_passes, j->prm.fill_passes);
+        const int t = j->dtype == LF_U8 ? 0 : 1;
         const int sh = (j->S - 1) / 2, th = (j->T - 1) / 2;
         const size_t elem = j->dtype == LF_U8 ? 1 : 4;
         BordersArgs b{};
@@ -403,16 +515,44 @@ hipError_t stage_borders(Runner& r, const Jobs& jobs) {
         b.C = j->C;
         b.alpha = j->alpha;
         b.tau = j->prm.edge_tau;
-        brd[j->dtype == LF_U8 ? 0 : 1].push_back(b);
-        brd_blocks[j->dtype == LF_U8 ? 0 : 1].push_back(blocks_for(HW));
+        if (j->prm.fill_passes <= kMaxPrepFill) {
+            PrepArgs pa{};
+            pa.fuse = FuseArgs{j->maps, j->dinit, j->nv, HW, j->prm.phi};
+            pa.brd = b;
+            pa.fill = j->prm.fill_passes;
+            pa.tx = (j->W + kPrepTX - 1) / kPrepTX;
+            prep[t].push_back(pa);
+            prep_blocks[t].push_back((uint32_t)pa.tx * ((j->H + kPrepTY - 1) / kPrepTY));
+            continue;
+        }
+        sep.push_back(j);
+        int16_t* buf[2] = {j->dinit, j->fill_tmp};
+        // the passes ping-pong between the two buffers and end in dinit
+        fuse.push_back(FuseArgs{j->maps, buf[j->prm.fill_passes % 2], j->nv, HW, j->prm.phi});
+        fuse_blocks.push_back(blocks_for(HW));
+        max_passes = std::max(max_passes, j->prm.fill_passes);
+        brd[t].push_back(b);
+        brd_blocks[t].push_back(blocks_for(HW));
     }
-    hipError_t e = launch(r, kStBorders, fuse_kernel<Single<FuseArgs>>,
-                          fuse_kernel<Group<FuseArgs>>, fuse, fuse_blocks, kThreads);
+    hipError_t e = hipSuccess;
+    if (!prep[0].empty() &&
+        (e = launch(r, kStBorders, prep_kernel<Single<PrepArgs>, uint8_t>,
+                    prep_kernel<Group<PrepArgs>, uint8_t>, prep[0], prep_blocks[0],
+                    kThreads)) != hipSuccess)
+        return e;
+    if (!prep[1].empty() &&
+        (e = launch(r, kStBorders, prep_kernel<Single<PrepArgs>, float>,
+                    prep_kernel<Group<PrepArgs>, float>, prep[1], prep_blocks[1],
+                    kThreads)) != hipSuccess)
+        return e;
+    if (sep.empty()) return hipSuccess;
+    e = launch(r, kStBorders, fuse_kernel<Single<FuseArgs>>, fuse_kernel<Group<FuseArgs>>, fuse,
+               fuse_blocks, kThreads);
     if (e != hipSuccess) return e;
     for (int f = 0; f < max_passes; ++f) {
         std::vector<FillArgs> fill;
         std::vector<uint32_t> fill_blocks;
-        for (const Job* j : jobs) {
+        for (const Job* j : sep) {
             if (f >= j->prm.fill_passes) continue;
             int16_t* buf[2] = {j->dinit, j->fill_tmp};
             const int cur = (j->prm.fill_passes + f) % 2;

@@ -161,8 +161,18 @@ def _dev(t, dtype, name):
     return t
 
 
+PARAM_KEYS = frozenset(("win_h", "win_w", "P1_init", "P2_init", "P1_final", "P2_final",
+                        "npaths", "phi", "lam", "fill_passes", "edge_tau", "alpha", "cost_kind",
+                        "median", "sum_bits", "lam_far"))
+
+
 def make_params(p: dict) -> Params:
-    """lf_params from a dict of method parameters (the keys of lfsynth workloads)."""
+    """lf_params from a dict of method parameters (the keys of lfsynth workloads).
+    Unknown keys are an error, so that a misspelt parameter is not silently
+    left at its default."""
+    unknown = set(p) - PARAM_KEYS
+    if unknown:
+        raise KeyError(f"unknown method parameters: {sorted(unknown)}")
     return Params(CensusWindow(p["win_h"], p["win_w"]),
                   SgmParams(p["P1_init"], p["P2_init"], p["npaths"]),
                   SgmParams(p["P1_final"], p["P2_final"], p["npaths"]),

@@ -35,11 +35,11 @@ def case(name):
                                   lfsynth._params(alpha=255.0, lam=1, fill=1, sum_bits=16))
     if name == "one_row":                    # H = 1: every diagonal line has one pixel
         lf = lfsynth.workload("paper_s", seed=11, H=1, W=64, S=3, T=3, N=12)
-        lf.params.update(win_h=3, win_w=3, lam=0, fill=0)
+        lf.params.update(win_h=3, win_w=3, lam=0, fill_passes=0)
         return lf
     if name == "one_col":
         lf = lfsynth.workload("paper_s", seed=12, H=50, W=1, S=3, T=3, N=9)
-        lf.params.update(win_h=3, win_w=3, median=0, fill=3)
+        lf.params.update(win_h=3, win_w=3, median=0, fill_passes=3)
         return lf
     if name == "u16_paths":                  # bits + P2 > 255: 16-bit path-cost storage
         lf = lfsynth.workload("paper_s", seed=14, H=37, W=45, S=5, T=5, N=70)
@@ -74,6 +74,14 @@ def case(name):
         lf = lfsynth.workload("paper_s", seed=21, H=29, W=37, S=5, T=5, N=99)
         lf.params.update(P1_init=10, P2_init=190)
         return lf
+    if name == "fill_4":                     # four fill passes: fusion, fill and borders
+        lf = lfsynth.workload("paper_s", seed=22, H=26, W=33, S=5, T=5, N=20)   # launched apart
+        lf.params.update(fill_passes=4, phi=1)
+        return lf
+    if name == "fill_3_sparse":              # three fill passes over a sparse initial map
+        lf = lfsynth.workload("paper_s", seed=23, H=27, W=35, S=5, T=5, N=20)   # (phi = 1):
+        lf.params.update(fill_passes=3, phi=1)   # holes reach the image edges in every tile
+        return lf
     if name == "adaptive":                   # depth-adaptive borders (Sec. 4.6)
         lf = lfsynth.workload("paper_s", seed=20, H=44, W=50, S=7, T=7, N=80)
         lf.params.update(lam=2, lam_far=6)
@@ -83,6 +91,6 @@ def case(name):
 
 CASES = ["small", "f32_ragged", "u8_n65", "n256", "stage_1x11", "col_7x1", "one_row", "one_col",
          "u16_paths", "census_cost", "paths16", "paths16_u16", "boundless", "rgb_f32",
-         "rgb_u8_census", "adaptive", "u8_inf_add"]
+         "rgb_u8_census", "adaptive", "u8_inf_add", "fill_4", "fill_3_sparse"]
 
 
