@@ -80,10 +80,11 @@ def source_sha(path):
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def load_traffic(kernel, src):
-    """HBM bytes per launch of `kernel` measured by rocprofv3 counters (profiles/), or None
-    if the counters were taken on another version of its source."""
-    path = os.path.join(ROOT, "profiles", f"{kernel}.traffic.txt")
+def load_record(kernel, kind, src):
+    """The key = value record profiles/<kernel>.<kind>.txt written from rocprofv3
+    counters, or None if it is missing or was taken on another version of the
+    kernel's source."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}.{kind}.txt")
     if not os.path.exists(path):
         return None
     rec = {}
@@ -91,10 +92,25 @@ def load_traffic(kernel, src):
         if "=" in line and not line.startswith("#"):
             k, v = line.split("=", 1)
             rec[k.strip()] = v.strip()
-    if rec.get("source_sha") != source_sha(src):
-        return None
+    return rec if rec.get("source_sha") == source_sha(src) else None
+
+
+def load_traffic(kernel, src):
+    """HBM bytes per launch of `kernel` measured by rocprofv3 counters (profiles/), or None
+    if the counters were taken on another version of its source."""
+    rec = load_record(kernel, "traffic", src)
     try:
-        return float(rec["bytes_per_launch"])
+        return float(rec["bytes_per_launch"]) if rec else None
+    except (KeyError, ValueError):
+        return None
+
+
+def load_units(kernel, src):
+    """Busy fractions of the kernel's texture address / data units and VALU over its
+    cycles (rocprofv3 counters, profiles/), or None for another source version."""
+    rec = load_record(kernel, "units", src)
+    try:
+        return {k: float(rec[k]) for k in ("ta_busy", "td_busy", "valu_busy")} if rec else None
     except (KeyError, ValueError):
         return None
 
@@ -469,8 +485,10 @@ def main():
     src = {"sgm_initial": "sgm.hip", "sgm_bounded": "sgm.hip", "cost_bounded": "cost.hip"}
     roofline = dict(roofs[dominant])
     roofline["stage"] = dominant
-    roofline["traffic"] = load_traffic(
-        dominant, os.path.join(ROOT, "paper_1907_13449_amd", "csrc", src[dominant]))
+    src_path = os.path.join(ROOT, "paper_1907_13449_amd", "csrc", src[dominant])
+    roofline["traffic"] = load_traffic(dominant, src_path)
+    # what bounds it in practice: the vector memory path's units (not in the model)
+    roofline["units"] = load_units(dominant, src_path)
 
     if args.calib_copy:
         a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
