@@ -246,7 +246,8 @@ size_t plan_cost(Carve& c, int S, int T, int C, int H, int W, const lf_params* p
         census ? (uint64_t*)c.take((size_t)S * T * C * HW * sizeof(uint64_t)) : nullptr;
     // sized for float32 views (uint8 ones use a quarter of it)
     q.padded =
-        census ? nullptr : c.take((size_t)S * T * C * (H + 2) * (W + 2) * sizeof(float));
+        census ? nullptr
+               : c.take((size_t)S * T * C * (H + lf::kPadH) * (W + lf::kPadW) * sizeof(float));
     if (p) *p = q;
     return c.used;
 }

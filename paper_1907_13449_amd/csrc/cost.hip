@@ -65,14 +65,19 @@ __device__ __forceinline__ Pair<T> ld_pair(const T* p) {
     }
 }
 
-// Views with a replicated one-pixel edge: padded (y', x') holds the view at
-// (clamp(y'-1), clamp(x'-1)).  With it, the two clamped taps of a bilinear row,
+// Views with a replicated edge: padded (y', x') holds the view at
+// (clamp(y' - 1), clamp(x' - 2)), y' < H + 2, x' < W + 4 (one row above and below,
+// two columns left and right).  With it, the two clamped taps of a bilinear row,
 // (clamp(X), clamp(X+1)), are always the two consecutive elements starting at
-// clamp(X, -1, W-1) + 1 -- one 8-byte load, no edge cases, and the same values
-// (so the same float32 sums) as clamping each tap.
+// clamp(X, -1, W-1) + 2 -- one 8-byte load, no edge cases, and the same values
+// (so the same float32 sums) as clamping each tap; and the taps of the pixel to
+// the right, (clamp(X+1), clamp(X+2)), are always the next two of the three
+// starting at clamp(X, -2, W-1) + 2 (X below -2 or above W-1 reads replicas).
+constexpr int kPadL = 2, kPadT = 1;
+
 struct PadArgs {
     const void* src;          // [planes][H][pitch] (a view is C planes)
-    void* dst;                // [planes][H+2][W+2]
+    void* dst;                // [planes][H + 2][W + 4]
     int H, W, pitch;
 };
 
@@ -82,18 +87,19 @@ __global__ __launch_bounds__(kThreads) void pad_views_kernel(Src src) {
     for (uint32_t vb = blockIdx.x; vb < src.total; vb += gridDim.x) {
         uint32_t b;
         const PadArgs& a = member(src, vb, b);
-        const int Hp = a.H + 2, Wp = a.W + 2;
+        const int Hp = a.H + kPadH, Wp = a.W + kPadW;
         const int z = (int)(b / (uint32_t)Hp);
         const int y = (int)b - z * Hp;
         const T* __restrict__ row =
-            (const T*)a.src + ((size_t)z * a.H + clampi(y - 1, 0, a.H - 1)) * a.pitch;
+            (const T*)a.src + ((size_t)z * a.H + clampi(y - kPadT, 0, a.H - 1)) * a.pitch;
         T* __restrict__ out = (T*)a.dst + ((size_t)z * Hp + y) * Wp;
-        for (int x = threadIdx.x; x < Wp; x += kThreads) out[x] = row[clampi(x - 1, 0, a.W - 1)];
+        for (int x = threadIdx.x; x < Wp; x += kThreads)
+            out[x] = row[clampi(x - kPadL, 0, a.W - 1)];
     }
 }
 
 struct L2Args {
-    const void* views;        // padded: [T][S][C][H+2][W+2]
+    const void* views;        // padded: [T][S][C][H + 2][W + 4]
     const float* hyp;
     const int16_t* lo;
     const int64_t* off;       // [H*W + 1]
@@ -105,20 +111,207 @@ struct L2Args {
     uint32_t nblk;            // workgroups of this light field
 };
 
+// Three consecutive elements of a padded float view row.
+struct Tri {
+    float x, y, z;
+};
+__device__ __forceinline__ Tri ld3(const float* p) {
+    Tri t;
+    __builtin_memcpy(&t, p, 12);
+    return t;
+}
+
+// Block-wide exclusive prefix sum of cnt(i) over i in [0, np) into s_pre[0..np]
+// (s_pre[np] = the total); thread t owns the E consecutive entries from t*E.
+template <class Cnt>
+__device__ __forceinline__ void block_prefix(int np, Cnt cnt, int* s_pre, int* s_tmp) {
+    const int E = (np + kThreads - 1) / kThreads;
+    int local = 0;
+    for (int e = 0; e < E; ++e) {
+        const int i = threadIdx.x * E + e;
+        if (i < np) local += cnt(i);
+    }
+    s_tmp[threadIdx.x] = local;
+    __syncthreads();
+    if (threadIdx.x < 64) {                           // wave 0 scans the 256 sums
+        const int l = threadIdx.x;
+        const int v0 = s_tmp[4 * l], v1 = s_tmp[4 * l + 1], v2 = s_tmp[4 * l + 2],
+                  v3 = s_tmp[4 * l + 3];
+        const int own = v0 + v1 + v2 + v3;
+        int inc = own;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int n = __shfl_up(inc, o);
+            if (l >= o) inc += n;
+        }
+        const int ex = inc - own;
+        s_tmp[4 * l] = ex;
+        s_tmp[4 * l + 1] = ex + v0;
+        s_tmp[4 * l + 2] = ex + v0 + v1;
+        s_tmp[4 * l + 3] = ex + v0 + v1 + v2;
+        if (l == 63) s_pre[np] = inc;
+    }
+    __syncthreads();
+    int run = s_tmp[threadIdx.x];
+    for (int e = 0; e < E; ++e) {
+        const int i = threadIdx.x * E + e;
+        if (i < np) {
+            s_pre[i] = run;
+            run += cnt(i);
+        }
+    }
+    __syncthreads();
+}
+
 template <typename T, int CPT, bool Walk, int C>
 __device__ __forceinline__ void l2_slices(const L2Args& a, uint32_t b, int64_t* s_off, int* s_lo,
-                                          int* s_p) {
+                                          int* s_p, int* s_pre, int* s_tmp) {
+    // float grayscale views: the cells of two horizontally adjacent pixels at one
+    // hypothesis share their loads (see below)
+    constexpr bool kPairs = sizeof(T) == 4 && C == 1;
     constexpr int kChunk = kThreads * CPT;
     const int S = a.S, T_ = a.T, H = a.H, W = a.W, N = a.N;
-    const int Wp = W + 2;
+    const int Wp = W + kPadW;
     const int16_t* __restrict__ lo = a.lo;
     const int64_t* __restrict__ off = a.off;
     const int HW = H * W;
     const int64_t total = min(off[HW], a.cap_cells);
     const int sh = (S - 1) / 2, th = (T_ - 1) / 2;
-    const uint32_t vstride = (uint32_t)(H + 2) * Wp;
+    const uint32_t vstride = (uint32_t)(H + kPadH) * Wp;
     const T* __restrict__ views = (const T*)a.views;
     const T* __restrict__ refv = views + ((size_t)th * S + sh) * C * vstride;
+
+    auto store = [&](int64_t c, float acc) {
+        const float q = rintf(a.alpha * acc);
+        a.cost[c] = (uint16_t)(q > a.cap ? a.cap : q);
+        if (a.cost_f32) a.cost_f32[c] = acc;
+    };
+
+    // Eq. (12) for one cell: pixel (u, v), hypothesis d, over the views t outer,
+    // s inner.  One view of row t takes taps at horizontal fraction fx from the
+    // rows rt and rt + Wp.  Two cases skip taps that are weighted by an exact 0,
+    // since fma(0, b - a, a) is a exactly: the reference row of views (t = t_hat,
+    // flat: fy = 0, no bottom taps) and the reference column (s = s_hat, col:
+    // fx = 0, only the left tap of each row).  Each case is its own branch-free
+    // copy of the loop body.
+    auto cell = [&](int u, int v, float d) -> float {
+        float ref[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            ref[c] = ld(refv + (uint32_t)c * vstride + (uint32_t)(v + kPadT) * Wp + u + kPadL);
+        float acc = 0.0f;
+        auto view = [&](const T* __restrict__ vt, uint32_t rt, float fy, int s, bool flat,
+                        bool col) {
+            const float shx = (float)(sh - s) * d;
+            const float x0 = floorf(shx);
+            const float fx = shx - x0;
+            const uint32_t o = rt + (uint32_t)(clampi(u + (int)x0, -1, W - 1) + kPadL);
+            float sq = 0.0f, dist = 0.0f;
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const T* __restrict__ vs = vt + (uint32_t)(s * C + c) * vstride;
+                float tv, val;
+                if (col) {
+                    tv = ld(vs + o);
+                    val = flat ? tv : fmaf(fy, ld(vs + o + Wp) - tv, tv);
+                } else {
+                    const Pair<T> top = ld_pair(vs + o);
+                    tv = fmaf(fx, top.hi - top.lo, top.lo);
+                    val = tv;
+                    if (!flat) {
+                        const Pair<T> bot = ld_pair(vs + o + Wp);
+                        const float bv = fmaf(fx, bot.hi - bot.lo, bot.lo);
+                        val = fmaf(fy, bv - tv, tv);
+                    }
+                }
+                const float dl = ref[c] - val;
+                dist = fabsf(dl);
+                sq = c == 0 ? dl * dl : fmaf(dl, dl, sq);   // colour: l2 norm
+            }
+            acc = acc + (C == 1 ? dist : sqrtf(sq));
+        };
+        // s ascending; the reference view itself adds exactly +0 and is skipped
+        auto view_row = [&](const T* __restrict__ vt, uint32_t rt, float fy, bool flat) {
+            for (int s = 0; s < sh; ++s) view(vt, rt, fy, s, flat, false);
+            if (!flat) view(vt, rt, fy, sh, false, true);
+            for (int s = sh + 1; s < S; ++s) view(vt, rt, fy, s, flat, false);
+        };
+        for (int t = 0; t < T_; ++t) {
+            const float shy = (float)(th - t) * d;
+            const float y0 = floorf(shy);
+            const float fy = shy - y0;
+            // top tap row in padded coordinates; the bottom one follows it
+            const uint32_t rt = (uint32_t)(clampi(v + (int)y0, -1, H - 1) + kPadT) * Wp;
+            const T* __restrict__ vt = views + (size_t)t * S * C * vstride;
+            if (t == th) view_row(vt, rt, fy, true);
+            else view_row(vt, rt, fy, false);
+        }
+        return acc;
+    };
+
+    // Eq. (12) for the pixels (u, v) and (u+1, v) at one hypothesis d, with the
+    // arithmetic of cell() for each.  The shift of a view is the same for both,
+    // so the right pixel's taps are the left pixel's moved by one element: one
+    // 12-byte load per tap row serves both (8 bytes for the reference column of
+    // views, where only the left taps count).
+    auto pair = [&](int u, int v, float d, float& acc_a, float& acc_b) {
+        const float* __restrict__ fv = (const float*)views;
+        const uint32_t rr = (uint32_t)(v + kPadT) * Wp + u + kPadL;
+        const float ref_a = fv[((size_t)th * S + sh) * vstride + rr];
+        const float ref_b = fv[((size_t)th * S + sh) * vstride + rr + 1];
+        acc_a = 0.0f;
+        acc_b = 0.0f;
+        auto view = [&](const float* __restrict__ vt, uint32_t rt, float fy, int s, bool flat,
+                        bool col) {
+            const float shx = (float)(sh - s) * d;
+            const float x0 = floorf(shx);
+            const float fx = shx - x0;
+            const float* __restrict__ pv =
+                vt + (uint32_t)s * vstride + rt + (uint32_t)(clampi(u + (int)x0, -2, W - 1) + kPadL);
+            float va, vb;
+            if (col) {                            // fx = 0: the left taps only
+                float2 top;
+                __builtin_memcpy(&top, pv, 8);
+                va = top.x;
+                vb = top.y;
+                if (!flat) {
+                    float2 bot;
+                    __builtin_memcpy(&bot, pv + Wp, 8);
+                    va = fmaf(fy, bot.x - va, va);
+                    vb = fmaf(fy, bot.y - vb, vb);
+                }
+            } else {
+                const Tri top = ld3(pv);
+                const float ta = fmaf(fx, top.y - top.x, top.x);
+                const float tb = fmaf(fx, top.z - top.y, top.y);
+                va = ta;
+                vb = tb;
+                if (!flat) {
+                    const Tri bot = ld3(pv + Wp);
+                    const float ba = fmaf(fx, bot.y - bot.x, bot.x);
+                    const float bb = fmaf(fx, bot.z - bot.y, bot.y);
+                    va = fmaf(fy, ba - ta, ta);
+                    vb = fmaf(fy, bb - tb, tb);
+                }
+            }
+            acc_a = acc_a + fabsf(ref_a - va);
+            acc_b = acc_b + fabsf(ref_b - vb);
+        };
+        auto view_row = [&](const float* __restrict__ vt, uint32_t rt, float fy, bool flat) {
+            for (int s = 0; s < sh; ++s) view(vt, rt, fy, s, flat, false);
+            if (!flat) view(vt, rt, fy, sh, false, true);
+            for (int s = sh + 1; s < S; ++s) view(vt, rt, fy, s, flat, false);
+        };
+        for (int t = 0; t < T_; ++t) {
+            const float shy = (float)(th - t) * d;
+            const float y0 = floorf(shy);
+            const float fy = shy - y0;
+            const uint32_t rt = (uint32_t)(clampi(v + (int)y0, -1, H - 1) + kPadT) * Wp;
+            const float* __restrict__ vt = fv + (size_t)t * S * vstride;
+            if (t == th) view_row(vt, rt, fy, true);
+            else view_row(vt, rt, fy, false);
+        }
+    };
 
     for (int64_t slice = b; slice * kChunk < total; slice += a.nblk) {   // uniform
         const int64_t c0 = slice * kChunk;
@@ -150,75 +343,76 @@ __device__ __forceinline__ void l2_slices(const L2Args& a, uint32_t b, int64_t* 
             np = x + 1;
         }
 
-        for (int r = 0; r < CPT; ++r) {
-            const int64_t c = c0 + threadIdx.x + (int64_t)r * kThreads;
-            if (c >= c1) break;
-            const int i = find_pixel(s_off, np, c);
-            const int p = p0 + i;
-            const int v = p / W, u = p - v * W;
-            const int k = s_lo[i] + (int)(c - s_off[i]);
-            if ((unsigned)k >= (unsigned)N) continue;      // only for ranges outside [0, N)
-            const float d = a.hyp[k];
-            float ref[C];
-#pragma unroll
-            for (int c = 0; c < C; ++c)
-                ref[c] = ld(refv + (uint32_t)c * vstride + (uint32_t)(v + 1) * Wp + u + 1);
-            float acc = 0.0f;
-            // one view of row t: taps at horizontal fraction fx from the rows rt and
-            // rt + Wp.  Two cases skip taps that are weighted by an exact 0, since
-            // fma(0, b - a, a) is a exactly: the reference row of views (t = t_hat,
-            // flat: fy = 0, no bottom taps) and the reference column (s = s_hat,
-            // col: fx = 0, only the left tap of each row).  Each case is its own
-            // branch-free copy of the loop body.
-            auto view = [&](const T* __restrict__ vt, uint32_t rt, float fy, int s, bool flat,
-                            bool col) {
-                const float shx = (float)(sh - s) * d;
-                const float x0 = floorf(shx);
-                const float fx = shx - x0;
-                const uint32_t o = rt + (uint32_t)(clampi(u + (int)x0, -1, W - 1) + 1);
-                float sq = 0.0f, dist = 0.0f;
-#pragma unroll
-                for (int c = 0; c < C; ++c) {
-                    const T* __restrict__ vs = vt + (uint32_t)(s * C + c) * vstride;
-                    float tv, val;
-                    if (col) {
-                        tv = ld(vs + o);
-                        val = flat ? tv : fmaf(fy, ld(vs + o + Wp) - tv, tv);
-                    } else {
-                        const Pair<T> top = ld_pair(vs + o);
-                        tv = fmaf(fx, top.hi - top.lo, top.lo);
-                        val = tv;
-                        if (!flat) {
-                            const Pair<T> bot = ld_pair(vs + o + Wp);
-                            const float bv = fmaf(fx, bot.hi - bot.lo, bot.lo);
-                            val = fmaf(fy, bv - tv, tv);
-                        }
-                    }
-                    const float dl = ref[c] - val;
-                    dist = fabsf(dl);
-                    sq = c == 0 ? dl * dl : fmaf(dl, dl, sq);   // colour: l2 norm
+        if constexpr (kPairs) {
+            // Groups of the slice's pixels: a pixel at even u with its right
+            // neighbour (same row, also in the slice), or a pixel alone.  A
+            // group's items are the hypotheses k of the hull of its pixels'
+            // slice cells; an item computes the cells (p, k) and (p+1, k) of the
+            // group that exist.
+            auto first = [&](int i) { return max(s_off[i], c0); };       // slice cells of
+            auto last = [&](int i) { return min(s_off[i + 1], c1) - 1; }; // pixel i
+            auto kfirst = [&](int i) { return s_lo[i] + (int)(first(i) - s_off[i]); };
+            auto klast = [&](int i) { return s_lo[i] + (int)(last(i) - s_off[i]); };
+            auto ucol = [&](int i) { return (p0 + i) % W; };
+            auto leads = [&](int i) { return i == 0 || (ucol(i) & 1) == 0; };
+            auto paired = [&](int i) {            // pixel i + 1 joins pixel i's group
+                return (ucol(i) & 1) == 0 && i + 1 < np && ucol(i) + 1 < W;
+            };
+            // hull [kl, kh] of the group led by pixel i (a pixel whose range is
+            // empty -- possible only for bounds given with hi < lo -- adds nothing)
+            auto hull = [&](int i, int& kl, int& kh) {
+                kl = INT_MAX;
+                kh = INT_MIN;
+                if (first(i) <= last(i)) {
+                    kl = kfirst(i);
+                    kh = klast(i);
                 }
-                acc = acc + (C == 1 ? dist : sqrtf(sq));
+                if (paired(i) && first(i + 1) <= last(i + 1)) {
+                    kl = min(kl, kfirst(i + 1));
+                    kh = max(kh, klast(i + 1));
+                }
+                return kl <= kh;
             };
-            // s ascending; the reference view itself adds exactly +0 and is skipped
-            auto view_row = [&](const T* __restrict__ vt, uint32_t rt, float fy, bool flat) {
-                for (int s = 0; s < sh; ++s) view(vt, rt, fy, s, flat, false);
-                if (!flat) view(vt, rt, fy, sh, false, true);
-                for (int s = sh + 1; s < S; ++s) view(vt, rt, fy, s, flat, false);
+            auto count = [&](int i) {
+                int kl, kh;
+                return leads(i) && hull(i, kl, kh) ? kh - kl + 1 : 0;
             };
-            for (int t = 0; t < T_; ++t) {
-                const float shy = (float)(th - t) * d;
-                const float y0 = floorf(shy);
-                const float fy = shy - y0;
-                // top tap row in padded coordinates; the bottom one follows it
-                const uint32_t rt = (uint32_t)(clampi(v + (int)y0, -1, H - 1) + 1) * Wp;
-                const T* __restrict__ vt = views + (size_t)t * S * C * vstride;
-                if (t == th) view_row(vt, rt, fy, true);
-                else view_row(vt, rt, fy, false);
+            block_prefix(np, count, s_pre, s_tmp);
+            const int nitems = s_pre[np];
+            for (int j = threadIdx.x; j < nitems; j += kThreads) {
+                int x = 0, y = np;                // largest i with s_pre[i] <= j
+                while (y - x > 1) {
+                    const int mid = (x + y) >> 1;
+                    if (s_pre[mid] <= j) x = mid; else y = mid;
+                }
+                const int i = x;
+                const bool two = paired(i);
+                const int ka0 = kfirst(i), ka1 = klast(i);
+                const int kb0 = two ? kfirst(i + 1) : INT_MAX, kb1 = two ? klast(i + 1) : -1;
+                int kl, kh;
+                hull(i, kl, kh);
+                const int k = kl + (j - s_pre[i]);
+                const bool has_a = k >= ka0 && k <= ka1 && (unsigned)k < (unsigned)N;
+                const bool has_b = k >= kb0 && k <= kb1 && (unsigned)k < (unsigned)N;
+                if (!has_a && !has_b) continue;   // a gap of the hull, or a range
+                const int p = p0 + i;             // outside [0, N)
+                const int v = p / W, u = p - v * W;
+                float acc_a, acc_b;
+                pair(u, v, a.hyp[k], acc_a, acc_b);
+                if (has_a) store(s_off[i] + (k - s_lo[i]), acc_a);
+                if (has_b) store(s_off[i + 1] + (k - s_lo[i + 1]), acc_b);
             }
-            const float q = rintf(a.alpha * acc);
-            a.cost[c] = (uint16_t)(q > a.cap ? a.cap : q);
-            if (a.cost_f32) a.cost_f32[c] = acc;
+        } else {
+            for (int r = 0; r < CPT; ++r) {
+                const int64_t c = c0 + threadIdx.x + (int64_t)r * kThreads;
+                if (c >= c1) break;
+                const int i = find_pixel(s_off, np, c);
+                const int p = p0 + i;
+                const int v = p / W, u = p - v * W;
+                const int k = s_lo[i] + (int)(c - s_off[i]);
+                if ((unsigned)k >= (unsigned)N) continue;      // only for ranges outside [0, N)
+                store(c, cell(u, v, a.hyp[k]));
+            }
         }
         if constexpr (!Walk) break;               // one slice per workgroup
     }
@@ -226,12 +420,15 @@ __device__ __forceinline__ void l2_slices(const L2Args& a, uint32_t b, int64_t* 
 
 template <class Src, typename T, int CPT, bool Walk, int C>
 __global__ __launch_bounds__(kThreads) void cost_l2_kernel(Src src) {
+    constexpr bool kPairs = sizeof(T) == 4 && C == 1;
     __shared__ int64_t s_off[kThreads * CPT + 1];
     __shared__ int s_lo[kThreads * CPT];
     __shared__ int s_p[2];
+    __shared__ int s_pre[kPairs ? kThreads * CPT + 1 : 1];
+    __shared__ int s_tmp[kPairs ? kThreads : 1];
     uint32_t b;
     const L2Args& a = member(src, blockIdx.x, b);
-    l2_slices<T, CPT, Walk, C>(a, b, s_off, s_lo, s_p);
+    l2_slices<T, CPT, Walk, C>(a, b, s_off, s_lo, s_p, s_pre, s_tmp);
 }
 
 // ---------------------------------------------------------------------------
@@ -338,7 +535,8 @@ hipError_t stage_cost_inputs(Runner& r, const Jobs& jobs) {
         pa.W = j->W;
         pa.pitch = j->pitch;
         pads[j->dtype == LF_U8 ? 0 : 1].push_back(pa);
-        pad_blocks[j->dtype == LF_U8 ? 0 : 1].push_back((uint32_t)(j->H + 2) * j->S * j->T * j->C);
+        pad_blocks[j->dtype == LF_U8 ? 0 : 1].push_back((uint32_t)(j->H + kPadH) * j->S * j->T *
+                                                        j->C);
     }
     hipError_t e = hipSuccess;
     if (!pads[0].empty() &&
