@@ -65,19 +65,24 @@ __device__ __forceinline__ Pair<T> ld_pair(const T* p) {
     }
 }
 
+// Pixels per group of the grayscale float l2 cost (see l2_slices).
+constexpr int kGroup = 3;
+
 // Views with a replicated edge: padded (y', x') holds the view at
-// (clamp(y' - 1), clamp(x' - 2)), y' < H + 2, x' < W + 4 (one row above and below,
-// two columns left and right).  With it, the two clamped taps of a bilinear row,
-// (clamp(X), clamp(X+1)), are always the two consecutive elements starting at
-// clamp(X, -1, W-1) + 2 -- one 8-byte load, no edge cases, and the same values
-// (so the same float32 sums) as clamping each tap; and the taps of the pixel to
-// the right, (clamp(X+1), clamp(X+2)), are always the next two of the three
-// starting at clamp(X, -2, W-1) + 2 (X below -2 or above W-1 reads replicas).
-constexpr int kPadL = 2, kPadT = 1;
+// (clamp(y' - 1), clamp(x' - kGroup)), y' < H + 2, x' < W + 2 kGroup (one row
+// above and below, kGroup columns left and right).  With it, the two clamped
+// taps of a bilinear row, (clamp(X), clamp(X+1)), are always the two consecutive
+// elements starting at clamp(X, -1, W-1) + kGroup -- one 8-byte load, no edge
+// cases, and the same values (so the same float32 sums) as clamping each tap;
+// and the taps of the pixels g = 1 .. kGroup-1 to the right, (clamp(X+g),
+// clamp(X+g+1)), are always elements g, g+1 of the kGroup+1 starting at
+// clamp(X, -kGroup, W-1) + kGroup (X outside that range reads replicas).
+constexpr int kPadL = kGroup, kPadT = 1;
+static_assert(kPadW == 2 * kGroup && kPadH == 2, "view copy margins");
 
 struct PadArgs {
     const void* src;          // [planes][H][pitch] (a view is C planes)
-    void* dst;                // [planes][H + 2][W + 4]
+    void* dst;                // [planes][H + 2][W + 2 kGroup]
     int H, W, pitch;
 };
 
@@ -99,7 +104,7 @@ __global__ __launch_bounds__(kThreads) void pad_views_kernel(Src src) {
 }
 
 struct L2Args {
-    const void* views;        // padded: [T][S][C][H + 2][W + 4]
+    const void* views;        // padded: [T][S][C][H + 2][W + 2 kGroup]
     const float* hyp;
     const int16_t* lo;
     const int64_t* off;       // [H*W + 1]
@@ -111,14 +116,14 @@ struct L2Args {
     uint32_t nblk;            // workgroups of this light field
 };
 
-// Three consecutive elements of a padded float view row.
-struct Tri {
-    float x, y, z;
+// kGroup + 1 consecutive elements of a padded float view row, one load.
+struct Row {
+    float e[kGroup + 1];
 };
-__device__ __forceinline__ Tri ld3(const float* p) {
-    Tri t;
-    __builtin_memcpy(&t, p, 12);
-    return t;
+__device__ __forceinline__ Row ld_row(const float* p) {
+    Row r;
+    __builtin_memcpy(&r, p, sizeof(Row));
+    return r;
 }
 
 // Block-wide exclusive prefix sum of cnt(i) over i in [0, np) into s_pre[0..np]
@@ -249,53 +254,56 @@ __device__ __forceinline__ void l2_slices(const L2Args& a, uint32_t b, int64_t* 
         return acc;
     };
 
-    // Eq. (12) for the pixels (u, v) and (u+1, v) at one hypothesis d, with the
-    // arithmetic of cell() for each.  The shift of a view is the same for both,
-    // so the right pixel's taps are the left pixel's moved by one element: one
-    // 12-byte load per tap row serves both (8 bytes for the reference column of
-    // views, where only the left taps count).
-    auto pair = [&](int u, int v, float d, float& acc_a, float& acc_b) {
+    // Eq. (12) for the kGroup pixels (u + g, v) at one hypothesis d, with the
+    // arithmetic of cell() for each.  The shift of a view is the same for all of
+    // them, so pixel g's taps are pixel 0's moved by g elements: one load of
+    // kGroup + 1 elements per tap row serves the group (kGroup elements for the
+    // reference column of views, where only each pixel's left tap counts).
+    auto group = [&](int u, int v, float d, float (&acc)[kGroup]) {
         const float* __restrict__ fv = (const float*)views;
-        const uint32_t rr = (uint32_t)(v + kPadT) * Wp + u + kPadL;
-        const float ref_a = fv[((size_t)th * S + sh) * vstride + rr];
-        const float ref_b = fv[((size_t)th * S + sh) * vstride + rr + 1];
-        acc_a = 0.0f;
-        acc_b = 0.0f;
+        const float* __restrict__ rp =
+            fv + ((size_t)th * S + sh) * vstride + (uint32_t)(v + kPadT) * Wp + u + kPadL;
+        float ref[kGroup];
+#pragma unroll
+        for (int g = 0; g < kGroup; ++g) {
+            ref[g] = rp[g];
+            acc[g] = 0.0f;
+        }
         auto view = [&](const float* __restrict__ vt, uint32_t rt, float fy, int s, bool flat,
                         bool col) {
             const float shx = (float)(sh - s) * d;
             const float x0 = floorf(shx);
             const float fx = shx - x0;
-            const float* __restrict__ pv =
-                vt + (uint32_t)s * vstride + rt + (uint32_t)(clampi(u + (int)x0, -2, W - 1) + kPadL);
-            float va, vb;
+            const float* __restrict__ pv = vt + (uint32_t)s * vstride + rt +
+                                           (uint32_t)(clampi(u + (int)x0, -kPadL, W - 1) + kPadL);
+            float val[kGroup];
             if (col) {                            // fx = 0: the left taps only
-                float2 top;
-                __builtin_memcpy(&top, pv, 8);
-                va = top.x;
-                vb = top.y;
+                float top[kGroup];
+                __builtin_memcpy(&top, pv, sizeof(top));
+#pragma unroll
+                for (int g = 0; g < kGroup; ++g) val[g] = top[g];
                 if (!flat) {
-                    float2 bot;
-                    __builtin_memcpy(&bot, pv + Wp, 8);
-                    va = fmaf(fy, bot.x - va, va);
-                    vb = fmaf(fy, bot.y - vb, vb);
+                    float bot[kGroup];
+                    __builtin_memcpy(&bot, pv + Wp, sizeof(bot));
+#pragma unroll
+                    for (int g = 0; g < kGroup; ++g) val[g] = fmaf(fy, bot[g] - val[g], val[g]);
                 }
             } else {
-                const Tri top = ld3(pv);
-                const float ta = fmaf(fx, top.y - top.x, top.x);
-                const float tb = fmaf(fx, top.z - top.y, top.y);
-                va = ta;
-                vb = tb;
+                const Row top = ld_row(pv);
+#pragma unroll
+                for (int g = 0; g < kGroup; ++g)
+                    val[g] = fmaf(fx, top.e[g + 1] - top.e[g], top.e[g]);
                 if (!flat) {
-                    const Tri bot = ld3(pv + Wp);
-                    const float ba = fmaf(fx, bot.y - bot.x, bot.x);
-                    const float bb = fmaf(fx, bot.z - bot.y, bot.y);
-                    va = fmaf(fy, ba - ta, ta);
-                    vb = fmaf(fy, bb - tb, tb);
+                    const Row bot = ld_row(pv + Wp);
+#pragma unroll
+                    for (int g = 0; g < kGroup; ++g) {
+                        const float bv = fmaf(fx, bot.e[g + 1] - bot.e[g], bot.e[g]);
+                        val[g] = fmaf(fy, bv - val[g], val[g]);
+                    }
                 }
             }
-            acc_a = acc_a + fabsf(ref_a - va);
-            acc_b = acc_b + fabsf(ref_b - vb);
+#pragma unroll
+            for (int g = 0; g < kGroup; ++g) acc[g] = acc[g] + fabsf(ref[g] - val[g]);
         };
         auto view_row = [&](const float* __restrict__ vt, uint32_t rt, float fy, bool flat) {
             for (int s = 0; s < sh; ++s) view(vt, rt, fy, s, flat, false);
@@ -344,38 +352,36 @@ __device__ __forceinline__ void l2_slices(const L2Args& a, uint32_t b, int64_t* 
         }
 
         if constexpr (kPairs) {
-            // Groups of the slice's pixels: a pixel at even u with its right
-            // neighbour (same row, also in the slice), or a pixel alone.  A
-            // group's items are the hypotheses k of the hull of its pixels'
-            // slice cells; an item computes the cells (p, k) and (p+1, k) of the
-            // group that exist.
+            // Groups of the slice's pixels: a pixel at u = 0 mod kGroup (or the
+            // slice's first pixel) with the following pixels of its row up to the
+            // next such u that are in the slice.  A group's items are the
+            // hypotheses k of the hull of its pixels' slice cells; an item
+            // computes the cells (p + g, k) of the group that exist.
             auto first = [&](int i) { return max(s_off[i], c0); };       // slice cells of
             auto last = [&](int i) { return min(s_off[i + 1], c1) - 1; }; // pixel i
             auto kfirst = [&](int i) { return s_lo[i] + (int)(first(i) - s_off[i]); };
             auto klast = [&](int i) { return s_lo[i] + (int)(last(i) - s_off[i]); };
             auto ucol = [&](int i) { return (p0 + i) % W; };
-            auto leads = [&](int i) { return i == 0 || (ucol(i) & 1) == 0; };
-            auto paired = [&](int i) {            // pixel i + 1 joins pixel i's group
-                return (ucol(i) & 1) == 0 && i + 1 < np && ucol(i) + 1 < W;
+            auto leads = [&](int i) { return i == 0 || ucol(i) % kGroup == 0; };
+            auto members = [&](int i) {           // pixels of the group led by pixel i
+                const int u = ucol(i);
+                return min(min(kGroup - u % kGroup, np - i), W - u);
             };
             // hull [kl, kh] of the group led by pixel i (a pixel whose range is
             // empty -- possible only for bounds given with hi < lo -- adds nothing)
-            auto hull = [&](int i, int& kl, int& kh) {
+            auto hull = [&](int i, int n, int& kl, int& kh) {
                 kl = INT_MAX;
                 kh = INT_MIN;
-                if (first(i) <= last(i)) {
-                    kl = kfirst(i);
-                    kh = klast(i);
-                }
-                if (paired(i) && first(i + 1) <= last(i + 1)) {
-                    kl = min(kl, kfirst(i + 1));
-                    kh = max(kh, klast(i + 1));
-                }
+                for (int g = 0; g < n; ++g)
+                    if (first(i + g) <= last(i + g)) {
+                        kl = min(kl, kfirst(i + g));
+                        kh = max(kh, klast(i + g));
+                    }
                 return kl <= kh;
             };
             auto count = [&](int i) {
                 int kl, kh;
-                return leads(i) && hull(i, kl, kh) ? kh - kl + 1 : 0;
+                return leads(i) && hull(i, members(i), kl, kh) ? kh - kl + 1 : 0;
             };
             block_prefix(np, count, s_pre, s_tmp);
             const int nitems = s_pre[np];
@@ -386,21 +392,25 @@ __device__ __forceinline__ void l2_slices(const L2Args& a, uint32_t b, int64_t* 
                     if (s_pre[mid] <= j) x = mid; else y = mid;
                 }
                 const int i = x;
-                const bool two = paired(i);
-                const int ka0 = kfirst(i), ka1 = klast(i);
-                const int kb0 = two ? kfirst(i + 1) : INT_MAX, kb1 = two ? klast(i + 1) : -1;
+                const int n = members(i);
                 int kl, kh;
-                hull(i, kl, kh);
+                hull(i, n, kl, kh);
                 const int k = kl + (j - s_pre[i]);
-                const bool has_a = k >= ka0 && k <= ka1 && (unsigned)k < (unsigned)N;
-                const bool has_b = k >= kb0 && k <= kb1 && (unsigned)k < (unsigned)N;
-                if (!has_a && !has_b) continue;   // a gap of the hull, or a range
+                bool has[kGroup], any = false;
+#pragma unroll
+                for (int g = 0; g < kGroup; ++g) {
+                    has[g] = g < n && k >= kfirst(i + g) && k <= klast(i + g) &&
+                             (unsigned)k < (unsigned)N;
+                    any |= has[g];
+                }
+                if (!any) continue;               // a gap of the hull, or a range
                 const int p = p0 + i;             // outside [0, N)
                 const int v = p / W, u = p - v * W;
-                float acc_a, acc_b;
-                pair(u, v, a.hyp[k], acc_a, acc_b);
-                if (has_a) store(s_off[i] + (k - s_lo[i]), acc_a);
-                if (has_b) store(s_off[i + 1] + (k - s_lo[i + 1]), acc_b);
+                float acc[kGroup];
+                group(u, v, a.hyp[k], acc);
+#pragma unroll
+                for (int g = 0; g < kGroup; ++g)
+                    if (has[g]) store(s_off[i + g] + (k - s_lo[i + g]), acc[g]);
             }
         } else {
             for (int r = 0; r < CPT; ++r) {

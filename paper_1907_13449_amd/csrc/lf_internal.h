@@ -25,7 +25,7 @@ namespace lf {
 
 constexpr uint32_t kInf = 0x3FFFFFFFu;   // +inf of the SGM path recurrences
 constexpr int kMaxCensusRadius = 7;      // windows up to 15 x 15
-constexpr int kPadH = 2, kPadW = 4;      // rows / columns added to the cost stage's view copy
+constexpr int kPadH = 2, kPadW = 6;      // rows / columns added to the cost stage's view copy
 constexpr int kMaxBatchImages = 16;
 
 __device__ __forceinline__ int clampi(int x, int lo, int hi) { return min(max(x, lo), hi); }
