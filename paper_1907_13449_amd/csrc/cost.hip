@@ -86,20 +86,45 @@ struct PadArgs {
     int H, W, pitch;
 };
 
-// One workgroup per padded row: block b is row b % (H+2) of plane b / (H+2).
+// A workgroup copies kPadRows padded rows of one plane: block b is rows
+// kPadRows * (b % g) .. of plane b / g (g row groups per plane).  Each thread
+// loads its elements of all the rows (3 x kPadRows per 768 columns) before it
+// stores them, so that many loads are in flight.
+constexpr int kPadRows = 4;
+
 template <class Src, typename T>
 __global__ __launch_bounds__(kThreads) void pad_views_kernel(Src src) {
     for (uint32_t vb = blockIdx.x; vb < src.total; vb += gridDim.x) {
         uint32_t b;
         const PadArgs& a = member(src, vb, b);
         const int Hp = a.H + kPadH, Wp = a.W + kPadW;
-        const int z = (int)(b / (uint32_t)Hp);
-        const int y = (int)b - z * Hp;
-        const T* __restrict__ row =
-            (const T*)a.src + ((size_t)z * a.H + clampi(y - kPadT, 0, a.H - 1)) * a.pitch;
-        T* __restrict__ out = (T*)a.dst + ((size_t)z * Hp + y) * Wp;
-        for (int x = threadIdx.x; x < Wp; x += kThreads)
-            out[x] = row[clampi(x - kPadL, 0, a.W - 1)];
+        const int g = (Hp + kPadRows - 1) / kPadRows;
+        const int z = (int)(b / (uint32_t)g);
+        const int y0 = ((int)b - z * g) * kPadRows;
+        for (int xb = 0; xb < Wp; xb += 3 * kThreads) {
+            T v[kPadRows][3];
+#pragma unroll
+            for (int r = 0; r < kPadRows; ++r) {
+                const T* __restrict__ row =
+                    (const T*)a.src +
+                    ((size_t)z * a.H + clampi(y0 + r - kPadT, 0, a.H - 1)) * a.pitch;
+#pragma unroll
+                for (int e = 0; e < 3; ++e) {
+                    const int x = xb + e * kThreads + (int)threadIdx.x;
+                    v[r][e] = row[clampi(x - kPadL, 0, a.W - 1)];
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < kPadRows; ++r) {
+                if (y0 + r >= Hp) break;
+                T* __restrict__ out = (T*)a.dst + ((size_t)z * Hp + y0 + r) * Wp;
+#pragma unroll
+                for (int e = 0; e < 3; ++e) {
+                    const int x = xb + e * kThreads + (int)threadIdx.x;
+                    if (x < Wp) out[x] = v[r][e];
+                }
+            }
+        }
     }
 }
 
@@ -545,8 +570,8 @@ hipError_t stage_cost_inputs(Runner& r, const Jobs& jobs) {
         pa.W = j->W;
         pa.pitch = j->pitch;
         pads[j->dtype == LF_U8 ? 0 : 1].push_back(pa);
-        pad_blocks[j->dtype == LF_U8 ? 0 : 1].push_back((uint32_t)(j->H + kPadH) * j->S * j->T *
-                                                        j->C);
+        pad_blocks[j->dtype == LF_U8 ? 0 : 1].push_back(
+            (uint32_t)((j->H + kPadH + kPadRows - 1) / kPadRows) * j->S * j->T * j->C);
     }
     hipError_t e = hipSuccess;
     if (!pads[0].empty() &&
