@@ -130,10 +130,10 @@ int32_t lf_cross_views(int32_t S, int32_t T, int32_t* st);
 
 /* Stage timing for measurement.  lf_profile_enable(1) makes every later call
  * record a HIP event pair on its stream around each group of launches (stages:
- * 0 census, 1 initial SGM, 2 fusion/fill/borders, 3 offsets, 4 cost inputs (the
- * edge-replicated view copy, or the Census of every view for the Eq. (15) cost),
- * 5 bounded cost, 6 bounded SGM, 7 WTA/sub-pixel/median); returns the previous
- * setting.
+ * 0 census, 1 initial Census cost volume, 2 initial path costs, 3 their sum and
+ * WTA, 4 fusion/fill/borders, 5 offsets, 6 cost inputs (the edge-replicated view
+ * copy, or the Census of every view for the Eq. (15) cost), 7 bounded cost,
+ * 8 bounded SGM, 9 WTA/sub-pixel/median); returns the previous setting.
  * lf_profile_read waits for the recorded events, writes per-stage milliseconds
  * and launch counts (host arrays of n entries, either may be NULL), forgets the
  * records and returns the number of stages.  Event objects are created on first

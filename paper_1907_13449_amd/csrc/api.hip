@@ -64,9 +64,9 @@ lf_status device_status(hipError_t e, const char* where) {
 // Opt-in stage timing: a HIP event pair recorded on the call's stream around
 // each group of launches.  Off by default; when off nothing is recorded.
 namespace prof {
-const char* const kNames[lf::kNumStages] = {"census",      "sgm_initial",  "fuse_fill_borders",
-                                            "offsets",     "cost_inputs",  "cost_bounded",
-                                            "sgm_bounded", "wta_subpixel_median"};
+const char* const kNames[lf::kNumStages] = {
+    "census",      "initial_cost", "initial_paths", "initial_sum_wta", "fuse_fill_borders",
+    "offsets",     "cost_inputs",  "cost_bounded",  "sgm_bounded",     "wta_subpixel_median"};
 struct Rec {
     int stage, launches;
     hipEvent_t a, b;
@@ -385,9 +385,9 @@ lf_status run_initial(lf::Runner& r, const lf::Jobs& jobs) {
         prof::Scope _ps(lf::kStCensus, r);
         LF_HIP(lf::stage_census(r, jobs, false), "census");
     }
-    {
-        prof::Scope _ps(lf::kStSgmInit, r);
-        LF_HIP(lf::stage_sgm_initial(r, jobs), "initial SGM");
+    for (int part = 0; part < 3; ++part) {
+        prof::Scope _ps(lf::kStInitCost + part, r);
+        LF_HIP(lf::stage_sgm_initial(r, jobs, part), "initial SGM");
     }
     prof::Scope _ps(lf::kStBorders, r);
     LF_HIP(lf::stage_borders(r, jobs), "fusion/fill/borders");

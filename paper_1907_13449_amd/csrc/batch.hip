@@ -240,7 +240,8 @@ lf_status lf_plan_autotune(lf_plan* p, hipStream_t stream, int32_t reps, lf_tuni
         double ms[lf::kNumStages];
         if ((s = measure(t, ms)) != LF_OK) break;
         if (ms[lf::kStCost] < best_cost) best_cost = ms[lf::kStCost], best.cost_cpt = cpt[i];
-        if (ms[lf::kStSgmInit] < best_dense) best_dense = ms[lf::kStSgmInit], best.dense_depth = dd[i];
+        if (ms[lf::kStInitPaths] < best_dense)
+            best_dense = ms[lf::kStInitPaths], best.dense_depth = dd[i];
         if (ms[lf::kStSgmFinal] < best_bounded)
             best_bounded = ms[lf::kStSgmFinal], best.bounded_depth = bd[i];
     }

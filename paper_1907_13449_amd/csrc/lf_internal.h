@@ -72,8 +72,8 @@ struct Tuning {
 };
 
 // Stages of the method, in order (also the profiling buckets).
-enum Stage { kStCensus, kStSgmInit, kStBorders, kStOffsets, kStCostInputs, kStCost, kStSgmFinal,
-             kStWta, kNumStages };
+enum Stage { kStCensus, kStInitCost, kStInitPaths, kStInitSum, kStBorders, kStOffsets,
+             kStCostInputs, kStCost, kStSgmFinal, kStWta, kNumStages };
 
 // Receives the launches of a batch plan.  table() copies host records into the
 // plan's device table and returns their device address.
@@ -182,7 +182,8 @@ hipError_t stage_census(Runner& r, const Jobs& jobs, bool all_views);
 hipError_t census_image(Runner& r, const void* img, int dtype, int H, int W, int pitch,
                         int win_h, int win_w, uint64_t* out);
 // Census cost + SGM + WTA over the cross views -> maps.
-hipError_t stage_sgm_initial(Runner& r, const Jobs& jobs);
+// part 0: the Census cost volume, 1: the path costs, 2: their sum and the WTA
+hipError_t stage_sgm_initial(Runner& r, const Jobs& jobs, int part);
 // Fusion, fill passes ending in dinit, edges and borders -> dinit, lo, hi.
 hipError_t stage_borders(Runner& r, const Jobs& jobs);
 // The full hypothesis range for every pixel -> lo, hi (boundary-less search).

@@ -613,15 +613,15 @@ hipError_t dense_variant(Runner& r, const std::vector<DenseArgs>& args,
                          const std::vector<uint32_t>& blocks) {
     switch (r.tune.dense_depth) {
         case 4:
-            return launch(r, kStSgmInit, sgm_dense_paths_kernel<Single<DenseArgs>, K, LT, 4, kPad>,
+            return launch(r, kStInitPaths, sgm_dense_paths_kernel<Single<DenseArgs>, K, LT, 4, kPad>,
                           sgm_dense_paths_kernel<Group<DenseArgs>, K, LT, 4, kPad>, args, blocks,
                           64 * kWavesPerBlock);
         case 16:
-            return launch(r, kStSgmInit, sgm_dense_paths_kernel<Single<DenseArgs>, K, LT, 16, kPad>,
+            return launch(r, kStInitPaths, sgm_dense_paths_kernel<Single<DenseArgs>, K, LT, 16, kPad>,
                           sgm_dense_paths_kernel<Group<DenseArgs>, K, LT, 16, kPad>, args, blocks,
                           64 * kWavesPerBlock);
         default:
-            return launch(r, kStSgmInit, sgm_dense_paths_kernel<Single<DenseArgs>, K, LT, 8, kPad>,
+            return launch(r, kStInitPaths, sgm_dense_paths_kernel<Single<DenseArgs>, K, LT, 8, kPad>,
                           sgm_dense_paths_kernel<Group<DenseArgs>, K, LT, 8, kPad>, args, blocks,
                           64 * kWavesPerBlock);
     }
@@ -699,7 +699,7 @@ size_t sgm_bounded_scratch_bytes(int H, int W, int N, int npaths) {
     return meta + (size_t)npaths * H * W * N * sizeof(uint16_t);
 }
 
-hipError_t stage_sgm_initial(Runner& r, const Jobs& jobs) {
+hipError_t stage_sgm_initial(Runner& r, const Jobs& jobs, int part) {
     std::vector<CcvArgs> ccv;
     std::vector<uint32_t> ccv_blocks;
     // variants: K in 1..4 x (8-bit, 16-bit, 8-bit with padded rows)
@@ -772,43 +772,48 @@ hipError_t stage_sgm_initial(Runner& r, const Jobs& jobs) {
             sum_blocks[lt][np16].push_back(div_up((uint64_t)j->nv * HW, 4));
         }
     }
-    hipError_t e = launch(r, kStSgmInit, census_cost_volume_kernel<Single<CcvArgs>>,
-                          census_cost_volume_kernel<Group<CcvArgs>>, ccv, ccv_blocks, 256);
-    if (e != hipSuccess) return e;
-    for (int K = 0; K < 4; ++K)
-        for (int v = 0; v < 3; ++v) {
-            if (dense[K][v].empty()) continue;
-            if ((e = dense_k(r, K + 1, v, dense[K][v], dense_blocks[K][v])) != hipSuccess) return e;
-        }
+    hipError_t e = hipSuccess;
+    if (part == 0)
+        return launch(r, kStInitCost, census_cost_volume_kernel<Single<CcvArgs>>,
+                      census_cost_volume_kernel<Group<CcvArgs>>, ccv, ccv_blocks, 256);
+    if (part == 1) {
+        for (int K = 0; K < 4; ++K)
+            for (int v = 0; v < 3; ++v) {
+                if (dense[K][v].empty()) continue;
+                if ((e = dense_k(r, K + 1, v, dense[K][v], dense_blocks[K][v])) != hipSuccess)
+                    return e;
+            }
+        return hipSuccess;
+    }
     constexpr uint32_t kSumGrid = 8192;       // persistent: each workgroup walks pixels
     using SA = SumWtaArgs;
     if (!rows[0].empty() &&
-        (e = launch(r, kStSgmInit, dense_sum_wta_rows_kernel<Single<SA>, 8>,
+        (e = launch(r, kStInitSum, dense_sum_wta_rows_kernel<Single<SA>, 8>,
                     dense_sum_wta_rows_kernel<Group<SA>, 8>, rows[0], row_blocks[0], 256,
                     kSumGrid)) != hipSuccess)
         return e;
     if (!rows[1].empty() &&
-        (e = launch(r, kStSgmInit, dense_sum_wta_rows_kernel<Single<SA>, 16>,
+        (e = launch(r, kStInitSum, dense_sum_wta_rows_kernel<Single<SA>, 16>,
                     dense_sum_wta_rows_kernel<Group<SA>, 16>, rows[1], row_blocks[1], 256,
                     kSumGrid)) != hipSuccess)
         return e;
     if (!sums[0][0].empty() &&
-        (e = launch(r, kStSgmInit, dense_sum_wta_kernel<Single<SA>, uint8_t, 8>,
+        (e = launch(r, kStInitSum, dense_sum_wta_kernel<Single<SA>, uint8_t, 8>,
                     dense_sum_wta_kernel<Group<SA>, uint8_t, 8>, sums[0][0], sum_blocks[0][0],
                     256, kSumGrid)) != hipSuccess)
         return e;
     if (!sums[1][0].empty() &&
-        (e = launch(r, kStSgmInit, dense_sum_wta_kernel<Single<SA>, uint16_t, 8>,
+        (e = launch(r, kStInitSum, dense_sum_wta_kernel<Single<SA>, uint16_t, 8>,
                     dense_sum_wta_kernel<Group<SA>, uint16_t, 8>, sums[1][0], sum_blocks[1][0],
                     256, kSumGrid)) != hipSuccess)
         return e;
     if (!sums[0][1].empty() &&
-        (e = launch(r, kStSgmInit, dense_sum_wta_kernel<Single<SA>, uint8_t, 16>,
+        (e = launch(r, kStInitSum, dense_sum_wta_kernel<Single<SA>, uint8_t, 16>,
                     dense_sum_wta_kernel<Group<SA>, uint8_t, 16>, sums[0][1], sum_blocks[0][1],
                     256, kSumGrid)) != hipSuccess)
         return e;
     if (!sums[1][1].empty() &&
-        (e = launch(r, kStSgmInit, dense_sum_wta_kernel<Single<SA>, uint16_t, 16>,
+        (e = launch(r, kStInitSum, dense_sum_wta_kernel<Single<SA>, uint16_t, 16>,
                     dense_sum_wta_kernel<Group<SA>, uint16_t, 16>, sums[1][1], sum_blocks[1][1],
                     256, kSumGrid)) != hipSuccess)
         return e;
