@@ -290,15 +290,15 @@ __global__ __launch_bounds__(kThreads) void full_range_kernel(Src src) {
 }
 
 // --- exclusive prefix sum of the range widths -> CSR offsets ----------------
-// Three launches: per-tile totals, a scan of the totals (one workgroup per light
-// field), and the per-tile scan plus its tile base.
+// Two launches: per-tile totals, then per tile the sum of the totals before it
+// (its base) and the scan of its own widths.
 constexpr int kScanPerThread = 8;
 constexpr int kScanTile = kThreads * kScanPerThread;
 
 struct ScanArgs {
     const int16_t* lo;
     const int16_t* hi;
-    int64_t* bsum;            // [nb]: tile totals, then tile bases
+    int64_t* bsum;            // [nb]: tile totals
     int64_t* offsets;         // [HW + 1]
     int64_t HW;
     int nb;
@@ -340,31 +340,17 @@ __global__ __launch_bounds__(kThreads) void scan_reduce_kernel(Src src) {
 }
 
 template <class Src>
-__global__ __launch_bounds__(kThreads) void scan_blocks_kernel(Src src) {
-    // one workgroup per light field: exclusive scan of the tile totals, in chunks of 256
-    __shared__ int64_t sh[kThreads];
-    for (uint32_t vb = blockIdx.x; vb < src.total; vb += gridDim.x) {
-        uint32_t b;
-        const ScanArgs& a = member(src, vb, b);
-        int64_t carry = 0;
-        for (int c = 0; c < a.nb; c += kThreads) {
-            const int i = c + threadIdx.x;
-            const int64_t x = i < a.nb ? a.bsum[i] : 0;
-            int64_t total;
-            const int64_t ex = block_exclusive_scan(x, sh, total);
-            if (i < a.nb) a.bsum[i] = carry + ex;
-            carry += total;
-        }
-        if (threadIdx.x == 0) a.offsets[a.HW] = carry;
-    }
-}
-
-template <class Src>
 __global__ __launch_bounds__(kThreads) void scan_apply_kernel(Src src) {
     __shared__ int64_t sh[kThreads];
     for (uint32_t vb = blockIdx.x; vb < src.total; vb += gridDim.x) {
         uint32_t b;
         const ScanArgs& a = member(src, vb, b);
+        // the tile's base: the sum of the totals of the tiles before it (a tile
+        // count of HW / 2048, so each thread adds a few)
+        int64_t pre = 0;
+        for (int i = threadIdx.x; i < (int)b; i += kThreads) pre += a.bsum[i];
+        int64_t tile_base;
+        block_exclusive_scan(pre, sh, tile_base);
         // each thread owns kScanPerThread consecutive pixels of the tile
         const int64_t base = (int64_t)b * kScanTile + (int64_t)threadIdx.x * kScanPerThread;
         int w[kScanPerThread];
@@ -375,12 +361,13 @@ __global__ __launch_bounds__(kThreads) void scan_apply_kernel(Src src) {
             s += w[i];
         }
         int64_t total;
-        int64_t run = a.bsum[b] + block_exclusive_scan(s, sh, total);
+        int64_t run = tile_base + block_exclusive_scan(s, sh, total);
         for (int i = 0; i < kScanPerThread; ++i) {
             const int64_t p = base + i;
             if (p < a.HW) a.offsets[p] = run;
             run += w[i];
         }
+        if ((int)b == a.nb - 1 && threadIdx.x == 0) a.offsets[a.HW] = tile_base + total;
     }
 }
 
@@ -587,7 +574,7 @@ hipError_t stage_full_range(Runner& r, const Jobs& jobs) {
 
 hipError_t stage_offsets(Runner& r, const Jobs& jobs) {
     std::vector<ScanArgs> args;
-    std::vector<uint32_t> tiles, ones;
+    std::vector<uint32_t> tiles;
     for (const Job* j : jobs) {
         const int64_t HW = (int64_t)j->H * j->W;
         ScanArgs a{};
@@ -599,13 +586,9 @@ hipError_t stage_offsets(Runner& r, const Jobs& jobs) {
         a.nb = (int)((HW + kScanTile - 1) / kScanTile);
         args.push_back(a);
         tiles.push_back((uint32_t)a.nb);
-        ones.push_back(1);
     }
     hipError_t e = launch(r, kStOffsets, scan_reduce_kernel<Single<ScanArgs>>,
                           scan_reduce_kernel<Group<ScanArgs>>, args, tiles, kThreads);
-    if (e != hipSuccess) return e;
-    e = launch(r, kStOffsets, scan_blocks_kernel<Single<ScanArgs>>,
-               scan_blocks_kernel<Group<ScanArgs>>, args, ones, kThreads);
     if (e != hipSuccess) return e;
     return launch(r, kStOffsets, scan_apply_kernel<Single<ScanArgs>>,
                   scan_apply_kernel<Group<ScanArgs>>, args, tiles, kThreads);
