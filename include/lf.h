@@ -26,6 +26,8 @@
  *    disparities d_0 < ... < d_{N-1} (checked on the host copy by
  *    lf_validate_hypotheses; a device array is not read back).  2 <= N <= 256.
  *    Disparity indices are int16 in [0, N-1]; -1 marks an invalid pixel.
+ *  - Image size: H, W <= LF_MAX_SIDE and H*W <= 2^30 pixels (LF_EUNSUPPORTED
+ *    beyond; the kernels address a path step's rows with 32-bit offsets).
  *  - Bounded volumes ("CSR" layout): pixel p = v*W + u owns the index range
  *    [d_lo[p], d_hi[p]] and the cells offsets[p] .. offsets[p+1]-1, cell
  *    offsets[p] + (k - d_lo[p]) holding hypothesis k.  offsets has H*W+1 int64
@@ -44,6 +46,7 @@ extern "C" {
 
 #define LF_ABI_VERSION 3
 #define LF_MAX_HYPOTHESES 256
+#define LF_MAX_SIDE 65536
 
 typedef enum {
     LF_OK = 0,

@@ -136,7 +136,8 @@ lf_status check_shape(int S, int T, int H, int W, int N) {
         return fail(LF_EINVAL, "angular grid %dx%d: S and T must be odd and >= 1", S, T);
     if (S * T < 2) return fail(LF_EINVAL, "a light field needs at least 2 views");
     if (H < 1 || W < 1) return fail(LF_EINVAL, "image size %dx%d", H, W);
-    if ((int64_t)H * W > (1 << 30)) return fail(LF_EUNSUPPORTED, "image of %d x %d pixels", H, W);
+    if ((int64_t)H * W > (1 << 30) || H > LF_MAX_SIDE || W > LF_MAX_SIDE)
+        return fail(LF_EUNSUPPORTED, "image of %d x %d pixels", H, W);
     if (N < 2) return fail(LF_EINVAL, "N = %d hypotheses (need >= 2)", N);
     if (N > LF_MAX_HYPOTHESES)
         return fail(LF_EUNSUPPORTED, "N = %d hypotheses (max %d)", N, LF_MAX_HYPOTHESES);
@@ -614,7 +615,8 @@ lf_status lf_sgm_aggregate(const uint16_t* cost, const int64_t* offsets, const i
     if (!cost || !offsets || !d_lo || !d_hi || !csum || !ws)
         return fail(LF_EINVAL, "NULL argument");
     if (H < 1 || W < 1) return fail(LF_EINVAL, "image %dx%d", H, W);
-    if ((int64_t)H * W > (1 << 30)) return fail(LF_EUNSUPPORTED, "image of %d x %d pixels", H, W);
+    if ((int64_t)H * W > (1 << 30) || H > LF_MAX_SIDE || W > LF_MAX_SIDE)
+        return fail(LF_EUNSUPPORTED, "image of %d x %d pixels", H, W);
     if (N < 2 || N > LF_MAX_HYPOTHESES)
         return fail(N < 2 ? LF_EINVAL : LF_EUNSUPPORTED, "N = %d", N);
     LF_CHECK(check_sgm(sgm, "aggregate"));

@@ -26,6 +26,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <type_traits>
 
 namespace lf {
 namespace {
@@ -134,15 +135,20 @@ __device__ __forceinline__ uint32_t in_vgpr(uint32_t x) {
 template <int K>
 __device__ __forceinline__ void sgm_step(const uint32_t (&Lp)[K], uint32_t m, uint32_t P1,
                                          uint32_t P2, const uint32_t (&C)[K], uint32_t (&L)[K]) {
-    const uint32_t left = dpp<0x138>(UINT_MAX, Lp[K - 1]);   // wave_shr:1 -> from lane l-1
-    const uint32_t right = dpp<0x130>(UINT_MAX, Lp[0]);      // wave_shl:1 -> from lane l+1
-    const uint32_t mP2 = m + P2, negm = 0u - m;
+    // X = Lp + P1 first: each DPP neighbour move then fuses into the min that
+    // consumes it, and (for K = 2) none of the sources needs a copy
+    uint32_t X[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) X[j] = Lp[j] + P1;
+    const uint32_t left = dpp<0x138>(UINT_MAX, X[K - 1]);    // wave_shr:1 -> from lane l-1
+    const uint32_t right = dpp<0x130>(UINT_MAX, X[0]);       // wave_shl:1 -> from lane l+1
+    const uint32_t mP2 = m + P2;
 #pragma unroll
     for (int j = 0; j < K; ++j) {
-        const uint32_t lm = j == 0 ? left : Lp[j - 1];
-        const uint32_t lp = j == K - 1 ? right : Lp[j + 1];
-        const uint32_t t = min(min(Lp[j], mP2), min(lm, lp) + P1);
-        L[j] = C[j] + t + negm;              // C + t - m as one three-input add
+        const uint32_t lm = j == 0 ? left : X[j - 1];
+        const uint32_t lp = j == K - 1 ? right : X[j + 1];
+        const uint32_t t = min(min(Lp[j], mP2), min(lm, lp));
+        L[j] = t + (C[j] - m);               // the cost byte less m: one SDWA subtract
     }
 }
 
@@ -238,7 +244,7 @@ __global__ __launch_bounds__(256) void census_cost_volume_kernel(Src src) {
 }
 
 // SGM over the Census cost volume, every direction of every view in one launch.
-// Output: Lbuf[r][z][p][NP], storage type LT.
+// Output: Lbuf[r][z][p][NP], storage type LT, NP a multiple of 4 elements.
 struct DenseArgs {
     const uint8_t* cvol;      // [nv][H*W][NPc]
     void* Lbuf;
@@ -248,25 +254,91 @@ struct DenseArgs {
     uint32_t wblocks;         // blocks per view
 };
 
+// The K path costs of a lane, written as LT into the wave's staging row.
+template <int K, typename LT>
+__device__ __forceinline__ void stage_put(uint8_t* dst, const uint32_t (&L)[K]) {
+    if constexpr (sizeof(LT) == 1) {
+        if constexpr (K == 1) {
+            *dst = (uint8_t)L[0];
+        } else if constexpr (K == 2) {
+            *(uint16_t*)dst = (uint16_t)((L[0] & 0xFFu) | (L[1] << 8));
+        } else if constexpr (K == 4) {
+            *(uint32_t*)dst = (L[0] & 0xFFu) | ((L[1] & 0xFFu) << 8) | ((L[2] & 0xFFu) << 16) |
+                              (L[3] << 24);
+        } else {
+#pragma unroll
+            for (int j = 0; j < K; ++j) dst[j] = (uint8_t)L[j];
+        }
+    } else {
+        if constexpr (K == 1) {
+            *(uint16_t*)dst = (uint16_t)L[0];
+        } else if constexpr (K == 2) {
+            *(uint32_t*)dst = (L[0] & 0xFFFFu) | (L[1] << 16);
+        } else if constexpr (K == 4) {
+            *(uint2*)dst = make_uint2((L[0] & 0xFFFFu) | (L[1] << 16),
+                                      (L[2] & 0xFFFFu) | (L[3] << 16));
+        } else {
+#pragma unroll
+            for (int j = 0; j < K; ++j) ((uint16_t*)dst)[j] = (uint16_t)L[j];
+        }
+    }
+}
+
 // kPad (8-bit path costs, K <= 2, and B + 2 P2 <= 255 + P1 for the largest Census
 // cost B): hypotheses k >= N read the 255 that pads each cost row instead of
 // adding kInf.  Their path costs then stay >= 255 while every real one stays
 // <= B + P2 <= 255, so they never lower the minimum m, and as the neighbour of
 // k = N-1 their 255 + P1 >= m + P2 (m <= B + P2) never wins the min of Eq. (8):
 // the real path costs are those of the exact recurrence.
+//
+// Stores.  A path-cost row (NP elements) per step would be one narrow store per
+// step, and those stores took about a third of the kernel's vector-memory
+// issue.  Instead each step's row goes to the wave's staging area in LDS, and
+// after every D steps the wave copies the D rows out with 16-byte stores, the
+// lanes over (row, 16-byte chunk) pairs, and one store for the rows' short
+// tails: D = 8 rows of 100 bytes are two store instructions.  Row elements
+// k >= N hold don't-care values.
 template <int K, typename LT, int D, bool kPad>
-__device__ __forceinline__ void dense_wave(const DenseArgs& a, uint32_t b) {
+__device__ __forceinline__ void dense_wave(const DenseArgs& a, uint32_t b, uint8_t* wst) {
+    constexpr int kRow = 64 * K * (int)sizeof(LT);          // staged bytes per step
+    constexpr int kRounds = (D * kRow / 16 + 63) / 64;      // 16-byte copies per lane
     const int lane = threadIdx.x & 63;
     const int z = (int)(b / a.wblocks);
     const uint32_t wb = b - (uint32_t)z * a.wblocks;
     const int g = __builtin_amdgcn_readfirstlane(wb * kWavesPerBlock + (threadIdx.x >> 6));
     if (g >= a.lines.base[a.lines.npaths]) return;        // wave-uniform exit
-    const int H = a.H, W = a.W, N = a.N, NP = a.NP, NPc = a.NPc;
+    const int H = a.H, W = a.W, N = a.N, NPc = a.NPc;
     const uint32_t P1 = a.P1, P2 = a.P2;
     const LineInfo li = locate(a.lines, H, W, g);
     const uint32_t HW = (uint32_t)H * W;
     const uint8_t* __restrict__ cz = a.cvol + (size_t)z * HW * NPc;
-    LT* __restrict__ out = (LT*)a.Lbuf + ((size_t)li.r * a.nv + z) * HW * NP;
+    const int rb = a.NP * (int)sizeof(LT);                  // bytes per path-cost row
+    uint8_t* __restrict__ out = (uint8_t*)a.Lbuf + ((size_t)li.r * a.nv + z) * HW * rb;
+
+    // Copy plan of a flush, fixed per line.  A row is c16 whole 16-byte chunks
+    // and a tail of 0, 4, 8 or 12 bytes (rows are 4-byte aligned).  Copy j of
+    // this lane moves chunk c of staged row s to byte goff[j] past the flush's
+    // base address, that of the lowest-addressed row (rows follow the line, so
+    // for a direction running backwards it is the block's last row); lane s < D
+    // also moves the tail of row s.  Chunks past the D rows repeat the last one
+    // (the same bytes to the same place).
+    const int c16 = rb >> 4, tail = rb & 15, nchunk = D * c16;
+    const int dstep = li.dv * W + li.du;                    // pixels per step
+    const int sbytes = dstep * rb;
+    const int minoff = min(0, (D - 1) * sbytes);
+    uint32_t loff[kRounds], goff[kRounds];
+    int srow[kRounds];
+#pragma unroll
+    for (int j = 0; j < kRounds; ++j) {
+        const int idx = min(lane + 64 * j, max(nchunk - 1, 0));
+        const int s = c16 ? idx / c16 : 0, c = idx - s * c16;
+        srow[j] = s;
+        loff[j] = (uint32_t)(s * kRow + c * 16);
+        goff[j] = (uint32_t)(s * sbytes - minoff + c * 16);
+    }
+    const int tsrow = min(lane, D - 1);
+    const uint32_t tloff = (uint32_t)(tsrow * kRow + c16 * 16);
+    const uint32_t tgoff = (uint32_t)(tsrow * sbytes - minoff + c16 * 16);
 
     // the lane's K bytes of a pixel row; lanes past N read the row's last bytes
     // (with kPad: its 255 padding, since NPc >= N + 2) and, without kPad, add kInf
@@ -275,35 +347,56 @@ __device__ __forceinline__ void dense_wave(const DenseArgs& a, uint32_t b) {
 #pragma unroll
     for (int j = 0; j < K; ++j) cinit[j] = kPad || lane * K + j < N ? 0u : kInf;
     const int last = li.len - 1;
-    // one load per step for the K bytes (the texture units, shared by the CU's
-    // four SIMDs, would otherwise bound the kernel)
-    auto load = [&](int step) -> uint32_t {
-        step = min(step, last);
-        const uint32_t p = (uint32_t)((li.v0 + step * li.dv) * W + li.u0 + step * li.du);
-        const uint32_t o = p * (uint32_t)NPc + lofs;     // 32-bit offset off a scalar base
-        if constexpr (K == 1) return cz[o];
-        else if constexpr (K == 2) return *(const uint16_t*)(cz + o);
-        else if constexpr (K == 4) return *(const uint32_t*)(cz + o);
-        else return (uint32_t)cz[o] | ((uint32_t)cz[o + 1] << 8) | ((uint32_t)cz[o + 2] << 16);
+    const int64_t srow_bytes = (int64_t)dstep * NPc;       // cost-row bytes per step
+    // One load per step for the K bytes.  The loads of a block of D steps go
+    // through a buffer descriptor based at the lowest-addressed row among them;
+    // a step's row offset from it (>= 0, < 2^31) is the scalar offset, the lane's
+    // byte within the row the vector offset: no per-step vector arithmetic.
+    auto block_rsrc = [&](int nb, int& lo) {
+        lo = dstep >= 0 ? min(nb, last) : min(nb + D - 1, last);
+        const uint32_t p = (uint32_t)((li.v0 + lo * li.dv) * W + li.u0 + lo * li.du);
+        return __builtin_amdgcn_make_buffer_rsrc((void*)(cz + (size_t)p * NPc), (short)0,
+                                                 0x7FFFFFFF, 0x00020000);
+    };
+    auto load = [&](__amdgpu_buffer_rsrc_t rs, int lo, int step) -> uint32_t {
+        const int so = (int)((int64_t)(min(step, last) - lo) * srow_bytes);
+        if constexpr (K == 1) {
+            return __builtin_amdgcn_raw_buffer_load_b8(rs, lofs, so, 0);
+        } else if constexpr (K == 2) {
+            return __builtin_amdgcn_raw_buffer_load_b16(rs, lofs, so, 0);
+        } else if constexpr (K == 4) {
+            return __builtin_amdgcn_raw_buffer_load_b32(rs, lofs, so, 0);
+        } else {
+            return (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(rs, lofs, so, 0) |
+                   ((uint32_t)__builtin_amdgcn_raw_buffer_load_b8(rs, lofs + 1, so, 0) << 8) |
+                   ((uint32_t)__builtin_amdgcn_raw_buffer_load_b8(rs, lofs + 2, so, 0) << 16);
+        }
     };
     uint32_t cb[D];
+    {
+        int lo;
+        const __amdgpu_buffer_rsrc_t rs = block_rsrc(0, lo);
 #pragma unroll
-    for (int i = 0; i < D; ++i) cb[i] = load(i);
+        for (int i = 0; i < D; ++i) cb[i] = load(rs, lo, i);
+    }
 
+    uint8_t* const mine = wst + lane * K * (int)sizeof(LT);
     uint32_t Lp[K], m = 0;
 #pragma unroll
     for (int j = 0; j < K; ++j) Lp[j] = kInf;
     for (int base = 0; base < li.len; base += D) {
+        int lo;
+        const __amdgpu_buffer_rsrc_t rs = block_rsrc(base + D, lo);
 #pragma unroll
         for (int i = 0; i < D; ++i) {
             const int step = base + i;           // steps past the line end are computed
-            uint32_t C[K];                       // and not stored
+            uint32_t C[K];                       // and not copied out
 #pragma unroll
             for (int j = 0; j < K; ++j) {
                 const uint32_t byte = (cb[i] >> (8 * j)) & 0xFFu;
                 C[j] = kPad ? byte : byte + cinit[j];
             }
-            cb[i] = load(step + D);              // refill the slot just consumed
+            cb[i] = load(rs, lo, step + D);      // refill the slot just consumed
             uint32_t L[K];
             if (step == 0) {
 #pragma unroll
@@ -312,35 +405,54 @@ __device__ __forceinline__ void dense_wave(const DenseArgs& a, uint32_t b) {
                 sgm_step<K>(Lp, m, P1, P2, C, L);
             }
             m = wave_min(lane_min(L));
-
-            const uint32_t p = (uint32_t)((li.v0 + step * li.dv) * W + li.u0 + step * li.du);
-            const uint32_t e0 = p * (uint32_t)NP + (uint32_t)(lane * K);   // element offset
-            if (step < li.len) {
-                if constexpr (K == 2) {
-                    if (lane * 2 < N) {          // a pair: one 16- or 32-bit store
-                        if constexpr (sizeof(LT) == 1)
-                            *(uint16_t*)(out + e0) = (uint16_t)((L[0] & 0xFF) | (L[1] << 8));
-                        else
-                            *(uint32_t*)(out + e0) = (L[0] & 0xFFFF) | (L[1] << 16);
-                    }
-                } else {
-#pragma unroll
-                    for (int j = 0; j < K; ++j)
-                        if (lane * K + j < N) out[e0 + j] = (LT)L[j];
-                }
-            }
+            stage_put<K, LT>(mine + i * kRow, L);
 #pragma unroll
             for (int j = 0; j < K; ++j) Lp[j] = L[j];
         }
+        // flush: the staged rows were written by other lanes of this wave, whose
+        // LDS accesses complete in order
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int rows = min(D, li.len - base);
+        const uint32_t pb = (uint32_t)((li.v0 + base * li.dv) * W + li.u0 + base * li.du);
+        uint8_t* const ob = out + (int64_t)pb * rb + minoff;
+        // LDS offsets are 16-byte aligned; rows in memory 4-byte aligned
+        auto copy = [&](uint32_t lo, uint32_t go, auto n) {
+            constexpr int kBytes = decltype(n)::value;
+            using V = typename std::conditional<kBytes == 16, uint4,
+                      typename std::conditional<kBytes == 12, uint3,
+                      typename std::conditional<kBytes == 8, uint2, uint32_t>::type>::type>::type;
+            V v;
+            __builtin_memcpy(&v, __builtin_assume_aligned(wst + lo, 16), kBytes);
+            __builtin_memcpy(__builtin_assume_aligned(ob + go, 4), &v, kBytes);
+        };
+#pragma unroll
+        for (int j = 0; j < kRounds; ++j) {
+            if (64 * j >= nchunk) break;         // wave-uniform
+            if (rows == D || srow[j] < rows) copy(loff[j], goff[j], std::integral_constant<int, 16>());
+        }
+        if (tail && tsrow < rows) {
+            if (tail == 4) copy(tloff, tgoff, std::integral_constant<int, 4>());
+            else if (tail == 8) copy(tloff, tgoff, std::integral_constant<int, 8>());
+            else copy(tloff, tgoff, std::integral_constant<int, 12>());
+        }
+        // the next steps overwrite the staging rows only after these reads
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
 }
 
 template <class Src, int K, typename LT, int D, bool kPad>
 __global__ __launch_bounds__(64 * kWavesPerBlock) void sgm_dense_paths_kernel(Src src) {
+    constexpr int kWaveBytes = D * 64 * K * (int)sizeof(LT);
+    __shared__ __align__(16) uint8_t stage[kWavesPerBlock * kWaveBytes];
+    uint8_t* const wst = stage + (threadIdx.x >> 6) * kWaveBytes;
     for (uint32_t vb = blockIdx.x; vb < src.total; vb += gridDim.x) {
         uint32_t b;
         const DenseArgs& a = member(src, vb, b);
-        dense_wave<K, LT, D, kPad>(a, b);
+        dense_wave<K, LT, D, kPad>(a, b, wst);
     }
 }
 

@@ -73,6 +73,7 @@ def _params(lf, **kw):
 
 @pytest.mark.parametrize("bad", [
     dict(S=4, T=5), dict(S=1, T=1), dict(N=1), dict(N=300), dict(H=0), dict(C=2), dict(C=4),
+    dict(H=2, W=65537), dict(H=65537, W=2),
 ])
 def test_initial_disparity_rejects_bad_shapes(lf, bad):
     shape = dict(S=5, T=5, H=16, W=16, N=8, C=1)
