@@ -270,8 +270,9 @@ typedef struct {
  * default.  cost_cells_per_thread: 2, 4 (default) or 8 -- cells per thread of
  * one slice of the bounded cost kernel; cost_stride: 1 (default), 2 or 4 --
  * slices each cost workgroup walks (persistent workgroups); dense_prefetch: 4, 8
- * (default) or 16 -- path steps of cost loads in flight per wave in the initial
- * SGM; bounded_prefetch: 4, 8 or 16 (default) -- pixel metadata steps in flight
+ * or 16 (default) -- path steps of cost loads in flight per wave in the initial
+ * SGM, also the steps whose path costs it stages before copying them out;
+ * bounded_prefetch: 4, 8 or 16 (default) -- pixel metadata steps in flight
  * per wave in the bounded SGM (their costs run half as many steps ahead). */
 typedef struct {
     int32_t cost_cells_per_thread;
