@@ -45,6 +45,10 @@ def case(name):
         lf = lfsynth.workload("paper_s", seed=14, H=37, W=45, S=5, T=5, N=70)
         lf.params.update(P1_init=60, P2_init=250)
         return lf
+    if name == "u16_tail":                   # 16-bit path costs in rows of 88 bytes: the
+        lf = lfsynth.workload("paper_s", seed=24, H=31, W=43, S=5, T=5, N=44)   # staged
+        lf.params.update(P1_init=60, P2_init=250)  # copy-out ends each row with 8 bytes
+        return lf
     if name == "census_cost":                # Eq. (15) as the final cost
         lf = lfsynth.workload("paper_s", seed=13, H=40, W=52, S=5, T=5, N=24)
         lf.params.update(cost_kind=1, win_h=5, win_w=5, sum_bits=16)
@@ -91,6 +95,6 @@ def case(name):
 
 CASES = ["small", "f32_ragged", "u8_n65", "n256", "stage_1x11", "col_7x1", "one_row", "one_col",
          "u16_paths", "census_cost", "paths16", "paths16_u16", "boundless", "rgb_f32",
-         "rgb_u8_census", "adaptive", "u8_inf_add", "fill_4", "fill_3_sparse"]
+         "rgb_u8_census", "adaptive", "u8_inf_add", "fill_4", "fill_3_sparse", "u16_tail"]
 
 
