@@ -202,28 +202,39 @@ __device__ __forceinline__ void ccv_block(const CcvArgs& a, uint32_t b, uint32_t
 #pragma unroll
     for (int c = 0; c < 3; ++c) r[c] = c < C ? a.cref[(size_t)c * HW + p] : 0;
     const uint64_t* __restrict__ cv = a.cview + (size_t)z * C * HW;
-    uint8_t* t8 = (uint8_t*)tile;
     // The rounded shift is monotone in k, so consecutive hypotheses mostly share
     // it (at |s_hat - s| * (d_k+1 - d_k) < 1 a shift spans several k): wave w
-    // walks the quarter [wN/4, (w+1)N/4) of the hypotheses in order and gathers
-    // and counts a Census string only when the shift changes.
-    const int kb = N * wave / 4, ke = N * (wave + 1) / 4;
+    // walks its quarter of the row's 4-hypothesis words in order, gathers and
+    // counts a Census string only when the shift changes, and writes each word
+    // of four costs (255 past N) with one LDS store.
+    const int NW = NP / 4;
+    const int wb = NW * wave / 4, we = NW * (wave + 1) / 4;
     int prev = INT_MIN;
     uint32_t hd = 0;
-    for (int k = kb; k < ke; ++k) {                  // k is wave-uniform
-        const int sh = __builtin_amdgcn_readfirstlane(s_sh[k]);
-        if (sh != prev) {
-            prev = sh;
-            const uint32_t q = along_u ? (uint32_t)(v * W + clampi(u + sh, 0, W - 1))
-                                       : (uint32_t)(clampi(v + sh, 0, H - 1) * W + u);
-            hd = 0;
+    for (int w4 = wb; w4 < we; ++w4) {               // w4 is wave-uniform
+        const int4 sh4 = *(const int4*)(s_sh + 4 * w4);
+        const int shq[4] = {sh4.x, sh4.y, sh4.z, sh4.w};
+        uint32_t word = 0;
 #pragma unroll
-            for (int c = 0; c < 3; ++c)
-                if (c < C) hd += (uint32_t)__popcll(r[c] ^ cv[(size_t)c * HW + q]);
+        for (int q = 0; q < 4; ++q) {
+            uint32_t val = 255;
+            if (4 * w4 + q < N) {
+                const int sh = __builtin_amdgcn_readfirstlane(shq[q]);
+                if (sh != prev) {
+                    prev = sh;
+                    const uint32_t qq = along_u ? (uint32_t)(v * W + clampi(u + sh, 0, W - 1))
+                                                : (uint32_t)(clampi(v + sh, 0, H - 1) * W + u);
+                    hd = 0;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c)
+                        if (c < C) hd += (uint32_t)__popcll(r[c] ^ cv[(size_t)c * HW + qq]);
+                }
+                val = hd;
+            }
+            word |= val << (8 * q);
         }
-        t8[lane * NP + k] = (uint8_t)hd;
+        tile[lane * NW + w4] = word;
     }
-    for (int k = N + wave; k < NP; k += 4) t8[lane * NP + k] = (uint8_t)255;
     __syncthreads();
     // the tile is npix * NP contiguous bytes of C (NP is a multiple of 4)
     uint32_t* dst = (uint32_t*)(a.cvol + ((size_t)z * HW + p0) * NP);
@@ -234,7 +245,7 @@ __device__ __forceinline__ void ccv_block(const CcvArgs& a, uint32_t b, uint32_t
 template <class Src>
 __global__ __launch_bounds__(256) void census_cost_volume_kernel(Src src) {
     __shared__ uint32_t tile[kTilePix * LF_MAX_HYPOTHESES / 4];
-    __shared__ int s_sh[LF_MAX_HYPOTHESES];
+    __shared__ __align__(16) int s_sh[LF_MAX_HYPOTHESES];
     for (uint32_t vb = blockIdx.x; vb < src.total; vb += gridDim.x) {
         uint32_t b;
         const CcvArgs& a = member(src, vb, b);
