@@ -459,7 +459,8 @@ def main():
     torch.cuda.synchronize()
     log(f"[bench] warmup {args.warmup} done; timing {args.steps} steps")
 
-    lf.profile_enable(True)
+    # the timed steps run without the stage-event hook; the same number of steps
+    # is then run again with it, for the per-stage times
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
     t_start = time.perf_counter()
@@ -469,12 +470,16 @@ def main():
         ev[i + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
-    lf.profile_enable(False)
-    stages = lf.profile_read()
     lat = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps)])
     gpu_ms = float(ev[0].elapsed_time(ev[-1]))
     ms_per_step = gpu_ms / args.steps
     log(f"[bench] {args.steps} steps: {ms_per_step:.3f} ms/step (wall {wall * 1e3 / args.steps:.3f})")
+    lf.profile_enable(True)
+    for i in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    lf.profile_enable(False)
+    stages = lf.profile_read()
 
     stage_ms = {k: v[0] / args.steps for k, v in stages.items()}
     stage_launches = {k: v[1] // args.steps for k, v in stages.items()}
