@@ -908,17 +908,19 @@ hipError_t stage_sgm_initial(Runner& r, const Jobs& jobs, int part) {
             }
         return hipSuccess;
     }
-    constexpr uint32_t kSumGrid = 8192;       // persistent: each workgroup walks pixels
+    // the row-wise sums: one workgroup per 16 pixels (measured faster than
+    // persistent workgroups); the others: persistent, each workgroup walks pixels
+    constexpr uint32_t kSumGrid = 8192;
     using SA = SumWtaArgs;
     if (!rows[0].empty() &&
         (e = launch(r, kStInitSum, dense_sum_wta_rows_kernel<Single<SA>, 8>,
-                    dense_sum_wta_rows_kernel<Group<SA>, 8>, rows[0], row_blocks[0], 256,
-                    kSumGrid)) != hipSuccess)
+                    dense_sum_wta_rows_kernel<Group<SA>, 8>, rows[0], row_blocks[0], 256)) !=
+            hipSuccess)
         return e;
     if (!rows[1].empty() &&
         (e = launch(r, kStInitSum, dense_sum_wta_rows_kernel<Single<SA>, 16>,
-                    dense_sum_wta_rows_kernel<Group<SA>, 16>, rows[1], row_blocks[1], 256,
-                    kSumGrid)) != hipSuccess)
+                    dense_sum_wta_rows_kernel<Group<SA>, 16>, rows[1], row_blocks[1], 256)) !=
+            hipSuccess)
         return e;
     if (!sums[0][0].empty() &&
         (e = launch(r, kStInitSum, dense_sum_wta_kernel<Single<SA>, uint8_t, 8>,
