@@ -236,15 +236,21 @@ __device__ __forceinline__ void ccv_block(const CcvArgs& a, uint32_t b, uint32_t
         tile[lane * NW + w4] = word;
     }
     __syncthreads();
-    // the tile is npix * NP contiguous bytes of C (NP is a multiple of 4)
+    // the tile is npix * NP contiguous bytes of C (NP is a multiple of 4): 16-byte
+    // stores (4-byte aligned), then the last words one by one
     uint32_t* dst = (uint32_t*)(a.cvol + ((size_t)z * HW + p0) * NP);
-    const int words = npix * NP / 4;
-    for (int i = threadIdx.x; i < words; i += 256) dst[i] = tile[i];
+    const int words = npix * NP / 4, quads = words / 4;
+    for (int i = threadIdx.x; i < quads; i += 256) {
+        uint4 q;
+        __builtin_memcpy(&q, __builtin_assume_aligned(tile + 4 * i, 16), 16);
+        __builtin_memcpy(dst + 4 * i, &q, 16);
+    }
+    for (int i = 4 * quads + threadIdx.x; i < words; i += 256) dst[i] = tile[i];
 }
 
 template <class Src>
 __global__ __launch_bounds__(256) void census_cost_volume_kernel(Src src) {
-    __shared__ uint32_t tile[kTilePix * LF_MAX_HYPOTHESES / 4];
+    __shared__ __align__(16) uint32_t tile[kTilePix * LF_MAX_HYPOTHESES / 4];
     __shared__ __align__(16) int s_sh[LF_MAX_HYPOTHESES];
     for (uint32_t vb = blockIdx.x; vb < src.total; vb += gridDim.x) {
         uint32_t b;
