@@ -313,7 +313,7 @@ __device__ __forceinline__ void stage_put(uint8_t* dst, const uint32_t (&L)[K]) 
 // issue.  Instead each step's row goes to the wave's staging area in LDS, and
 // after every D steps the wave copies the D rows out with 16-byte stores, the
 // lanes over (row, 16-byte chunk) pairs, and one store for the rows' short
-// tails: D = 8 rows of 100 bytes are two store instructions.  Row elements
+// tails: 16 rows of 100 bytes are three store instructions.  Row elements
 // k >= N hold don't-care values.
 template <int K, typename LT, int D, bool kPad>
 __device__ __forceinline__ void dense_wave(const DenseArgs& a, uint32_t b, uint8_t* wst) {
