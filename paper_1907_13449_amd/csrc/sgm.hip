@@ -19,6 +19,8 @@
 //     shift (wave_shr:1 / wave_shl:1);
 //   - m = min_k L_r(p-r, k) is a DPP reduction (quad perms, half/row mirror, row
 //     broadcasts) and a readlane, so it is wave-uniform in an SGPR.
+// The initial stage stages each step's path-cost row in LDS and copies D rows
+// at a time out with 16-byte stores.
 // Path costs use the normalised recurrence (subtract m), which keeps them in
 // [0, C + P2]: 8 bits suffice for the Census stage when bits + P2 <= 255.
 // Hypotheses outside a pixel's range hold +inf (kInf) so they never win a min.
