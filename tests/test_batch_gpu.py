@@ -92,7 +92,7 @@ def test_batch_equals_alone(lf, items):
 @pytest.mark.parametrize("tuning", [
     dict(cost_cells_per_thread=2, dense_prefetch=4, bounded_prefetch=4),
     dict(cost_cells_per_thread=8, cost_stride=4, dense_prefetch=16, bounded_prefetch=8),
-    dict(cost_stride=2),
+    dict(cost_stride=2, dense_prefetch=8),
 ])
 def test_batch_every_tuning(lf, items, tuning):
     order = [3, 0, 1, 1, 9, 2]                       # repeats and a shuffled order
