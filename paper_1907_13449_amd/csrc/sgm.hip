@@ -273,6 +273,13 @@ struct DenseArgs {
     uint32_t wblocks;         // blocks per view
 };
 
+// Staged bytes per step of the initial path kernel: the lanes' 64 K path costs,
+// rounded up to whole 128-byte lines, as are the rows in memory (a path-cost
+// row of NP elements is never longer: see dense_lnp).
+constexpr int dense_stage_row(int K, int elem_bytes) {
+    return (64 * K * elem_bytes + 127) / 128 * 128;
+}
+
 // The K path costs of a lane, written as LT into the wave's staging row.
 template <int K, typename LT>
 __device__ __forceinline__ void stage_put(uint8_t* dst, const uint32_t (&L)[K]) {
@@ -319,7 +326,7 @@ __device__ __forceinline__ void stage_put(uint8_t* dst, const uint32_t (&L)[K]) 
 // k >= N hold don't-care values.
 template <int K, typename LT, int D, bool kPad>
 __device__ __forceinline__ void dense_wave(const DenseArgs& a, uint32_t b, uint8_t* wst) {
-    constexpr int kRow = 64 * K * (int)sizeof(LT);          // staged bytes per step
+    constexpr int kRow = dense_stage_row(K, sizeof(LT));    // staged bytes per step
     constexpr int kRounds = (D * kRow / 16 + 63) / 64;      // 16-byte copies per lane
     const int lane = threadIdx.x & 63;
     const int z = (int)(b / a.wblocks);
@@ -444,7 +451,17 @@ __device__ __forceinline__ void dense_wave(const DenseArgs& a, uint32_t b, uint8
                       typename std::conditional<kBytes == 8, uint2, uint32_t>::type>::type>::type;
             V v;
             __builtin_memcpy(&v, __builtin_assume_aligned(wst + lo, 16), kBytes);
-            __builtin_memcpy(__builtin_assume_aligned(ob + go, 4), &v, kBytes);
+            if constexpr (kBytes == 16) {
+                // rows are whole cache lines, read once by the sum: streaming
+                // (non-temporal) stores, measured 0.33 vs 0.41 ms for the kernel
+                uint32_t* d = (uint32_t*)__builtin_assume_aligned(ob + go, 16);
+                __builtin_nontemporal_store(v.x, d);
+                __builtin_nontemporal_store(v.y, d + 1);
+                __builtin_nontemporal_store(v.z, d + 2);
+                __builtin_nontemporal_store(v.w, d + 3);
+            } else {
+                __builtin_memcpy(__builtin_assume_aligned(ob + go, 4), &v, kBytes);
+            }
         };
 #pragma unroll
         for (int j = 0; j < kRounds; ++j) {
@@ -465,7 +482,7 @@ __device__ __forceinline__ void dense_wave(const DenseArgs& a, uint32_t b, uint8
 
 template <class Src, int K, typename LT, int D, bool kPad>
 __global__ __launch_bounds__(64 * kWavesPerBlock) void sgm_dense_paths_kernel(Src src) {
-    constexpr int kWaveBytes = D * 64 * K * (int)sizeof(LT);
+    constexpr int kWaveBytes = D * dense_stage_row(K, sizeof(LT));
     __shared__ __align__(16) uint8_t stage[kWavesPerBlock * kWaveBytes];
     uint8_t* const wst = stage + (threadIdx.x >> 6) * kWaveBytes;
     for (uint32_t vb = blockIdx.x; vb < src.total; vb += gridDim.x) {
@@ -816,6 +833,13 @@ uint32_t div_up(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
 
 int dense_np(int N) { return (N + 3) / 4 * 4; }
 
+// Row stride (elements) of the initial path costs: whole 128-byte cache lines,
+// so that the path kernel's non-temporal copy-out writes full lines.
+int dense_lnp(int N, int elem_bytes) {
+    const int rb = (N * elem_bytes + 127) / 128 * 128;
+    return rb / elem_bytes;
+}
+
 // Row stride of the initial Census cost volume: room for two bytes of 255 after
 // the N costs (hypotheses past N read them), within the 256-byte LDS tile rows.
 int dense_cvol_np(int N) { return min(dense_np(N + 2), LF_MAX_HYPOTHESES); }
@@ -824,7 +848,7 @@ size_t sgm_dense_scratch_bytes(int nv, int H, int W, int N, int npaths, int bits
     const size_t lt = bits + P2 <= 255 ? 1 : 2;
     const size_t cv = round256((size_t)nv * H * W * dense_cvol_np(N));
     // + 256: the row-wise sum reads up to 128 bytes past the last pixel's row
-    return cv + (size_t)npaths * nv * H * W * dense_np(N) * lt + 256;
+    return cv + (size_t)npaths * nv * H * W * dense_lnp(N, (int)lt) * lt + 256;
 }
 
 size_t sgm_bounded_scratch_bytes(int H, int W, int N, int npaths) {
@@ -843,11 +867,12 @@ hipError_t stage_sgm_initial(Runner& r, const Jobs& jobs, int part) {
     std::vector<SumWtaArgs> rows[2];               // 8-bit rows <= 128 B: [8/16 paths]
     std::vector<uint32_t> row_blocks[2];
     for (const Job* j : jobs) {
-        const int H = j->H, W = j->W, N = j->N, NP = dense_np(N), NPc = dense_cvol_np(N);
+        const int H = j->H, W = j->W, N = j->N, NPc = dense_cvol_np(N);
         const size_t HW = (size_t)H * W;
         const lf_sgm_params& sp = j->prm.sgm_init;
         const int bits = j->C * (j->prm.census.win_h * j->prm.census.win_w - 1);
         const int lt = bits + sp.P2 <= 255 ? 0 : 1;
+        const int NP = dense_lnp(N, 1 << lt);
         uint8_t* cvol = (uint8_t*)j->paths;
         void* Lbuf = (char*)j->paths + round256((size_t)j->nv * HW * NPc);
         const int sh = (j->S - 1) / 2, th = (j->T - 1) / 2;

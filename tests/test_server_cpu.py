@@ -42,8 +42,10 @@ def test_batch_workspace_is_the_sum_plus_tables(lf):
     one_b = lf.batch_workspace_bytes([b])
     both = lf.batch_workspace_bytes([a, b])
     da = lf.lib.lf_depth_workspace_size(5, 5, 1, 32, 40, 16, C.byref(a.params))
-    assert one_a > da
-    assert both >= lf.batch_workspace_bytes([a]) + da - 1
+    db = lf.lib.lf_depth_workspace_size(5, 5, 1, 50, 21, 40, C.byref(b.params))
+    assert one_a > da and one_b > db
+    # the batch holds both members' workspaces and one set of tables
+    assert both >= one_a + db - 1 and both >= one_b + da - 1
     assert both < one_a + one_b
     bad = _req(lf, S=4)
     assert lf.batch_workspace_bytes([a, bad]) == 0
