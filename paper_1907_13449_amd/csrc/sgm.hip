@@ -443,6 +443,7 @@ __device__ __forceinline__ void dense_wave(const DenseArgs& a, uint32_t b, uint8
         const int rows = min(D, li.len - base);
         const uint32_t pb = (uint32_t)((li.v0 + base * li.dv) * W + li.u0 + base * li.du);
         uint8_t* const ob = out + (int64_t)pb * rb + minoff;
+        const bool stream = (rb & 127) == 0;     // whole-line rows
         // LDS offsets are 16-byte aligned; rows in memory 4-byte aligned
         auto copy = [&](uint32_t lo, uint32_t go, auto n) {
             constexpr int kBytes = decltype(n)::value;
@@ -452,16 +453,18 @@ __device__ __forceinline__ void dense_wave(const DenseArgs& a, uint32_t b, uint8
             V v;
             __builtin_memcpy(&v, __builtin_assume_aligned(wst + lo, 16), kBytes);
             if constexpr (kBytes == 16) {
-                // rows are whole cache lines, read once by the sum: streaming
-                // (non-temporal) stores, measured 0.33 vs 0.41 ms for the kernel
-                uint32_t* d = (uint32_t*)__builtin_assume_aligned(ob + go, 16);
-                __builtin_nontemporal_store(v.x, d);
-                __builtin_nontemporal_store(v.y, d + 1);
-                __builtin_nontemporal_store(v.z, d + 2);
-                __builtin_nontemporal_store(v.w, d + 3);
-            } else {
-                __builtin_memcpy(__builtin_assume_aligned(ob + go, 4), &v, kBytes);
+                if (stream) {
+                    // rows are whole cache lines, read once by the sum: streaming
+                    // (non-temporal) stores, measured 0.33 vs 0.41 ms for the kernel
+                    uint32_t* d = (uint32_t*)__builtin_assume_aligned(ob + go, 16);
+                    __builtin_nontemporal_store(v.x, d);
+                    __builtin_nontemporal_store(v.y, d + 1);
+                    __builtin_nontemporal_store(v.z, d + 2);
+                    __builtin_nontemporal_store(v.w, d + 3);
+                    return;
+                }
             }
+            __builtin_memcpy(__builtin_assume_aligned(ob + go, 4), &v, kBytes);
         };
 #pragma unroll
         for (int j = 0; j < kRounds; ++j) {
@@ -833,11 +836,12 @@ uint32_t div_up(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
 
 int dense_np(int N) { return (N + 3) / 4 * 4; }
 
-// Row stride (elements) of the initial path costs: whole 128-byte cache lines,
-// so that the path kernel's non-temporal copy-out writes full lines.
+// Row stride (elements) of the initial path costs: rows longer than 64 bytes
+// take whole 128-byte cache lines, so that the path kernel's non-temporal
+// copy-out writes full lines; shorter ones stay packed (4-byte multiples).
 int dense_lnp(int N, int elem_bytes) {
-    const int rb = (N * elem_bytes + 127) / 128 * 128;
-    return rb / elem_bytes;
+    const int rb = dense_np(N) * elem_bytes;
+    return rb <= 64 ? dense_np(N) : (rb + 127) / 128 * 128 / elem_bytes;
 }
 
 // Row stride of the initial Census cost volume: room for two bytes of 255 after
