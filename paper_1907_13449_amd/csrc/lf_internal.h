@@ -65,7 +65,7 @@ __device__ __forceinline__ const A& member(const Group<A>& g, uint32_t vb, uint3
 
 // Tunable schedule parameters.  None of them changes a result.
 struct Tuning {
-    int cost_cpt = 4;        // cells per thread of the bounded cost kernel (2, 4, 8)
+    int cost_cpt = 2;        // cells per thread of the bounded cost kernel (2, 4, 8)
     int cost_stride = 1;     // slices walked per cost workgroup (1, 2, 4)
     int dense_depth = 16;    // steps prefetched by the initial-stage SGM (4, 8, 16)
     int bounded_depth = 16;  // steps prefetched by the bounded SGM (4, 8, 16)

@@ -92,7 +92,7 @@ def test_batch_equals_alone(lf, items):
 @pytest.mark.parametrize("tuning", [
     dict(cost_cells_per_thread=2, dense_prefetch=4, bounded_prefetch=4),
     dict(cost_cells_per_thread=8, cost_stride=4, dense_prefetch=16, bounded_prefetch=8),
-    dict(cost_stride=2, dense_prefetch=8),
+    dict(cost_cells_per_thread=4, cost_stride=2, dense_prefetch=8),
 ])
 def test_batch_every_tuning(lf, items, tuning):
     order = [3, 0, 1, 1, 9, 2]                       # repeats and a shuffled order
@@ -107,7 +107,7 @@ def test_batch_every_tuning(lf, items, tuning):
 def test_single_path_tuning_independent(lf, items):
     # the single-light-field path at default tuning equals a batch of one at another
     outs = _outputs(items, [1])
-    plan = _plan(lf, items, [1], outs, dict(cost_cells_per_thread=2, cost_stride=4))
+    plan = _plan(lf, items, [1], outs, dict(cost_cells_per_thread=4, cost_stride=4))
     plan.run()
     torch.cuda.synchronize()
     _check(items, [1], outs)
