@@ -267,7 +267,8 @@ typedef struct {
 } lf_request;
 
 /* Schedule parameters of the kernels; none changes a result.  0 selects the
- * default.  cost_cells_per_thread: 2 (default), 4 or 8 -- cells per thread of
+ * default.  cost_cells_per_thread: 2 (default; lf_depth takes 4 for the
+ * boundary-less search, lambda < 0), 4 or 8 -- cells per thread of
  * one slice of the bounded cost kernel; cost_stride: 1 (default), 2 or 4 --
  * slices each cost workgroup walks (persistent workgroups); dense_prefetch: 4, 8
  * or 16 (default) -- path steps of cost loads in flight per wave in the initial

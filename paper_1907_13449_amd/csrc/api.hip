@@ -698,6 +698,9 @@ lf_status lf_depth(const lf_view_set* views, const float* hyp, int32_t N, const 
     lf::Job j = depth_job(views, hyp, N, prm, disparity, d_index, ws);
     lf::Runner r;
     r.stream = stream;
+    // the boundary-less search has every pixel at the full range, where longer
+    // cost slices pay (measured 1.70 vs 1.88 ms per 9x9x512^2 light field)
+    if (prm->lambda < 0) r.tune.cost_cpt = 4;
     return run_depth(r, {&j});
 }
 
