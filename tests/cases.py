@@ -45,9 +45,9 @@ def case(name):
         lf = lfsynth.workload("paper_s", seed=14, H=37, W=45, S=5, T=5, N=70)
         lf.params.update(P1_init=60, P2_init=250)
         return lf
-    if name == "u16_tail":                   # 16-bit path costs in rows of 88 bytes: the
-        lf = lfsynth.workload("paper_s", seed=24, H=31, W=43, S=5, T=5, N=44)   # staged
-        lf.params.update(P1_init=60, P2_init=250)  # copy-out ends each row with 8 bytes
+    if name == "u16_tail":                   # 16-bit path costs in packed rows of 56 bytes:
+        lf = lfsynth.workload("paper_s", seed=24, H=31, W=43, S=5, T=5, N=28)   # the
+        lf.params.update(P1_init=60, P2_init=250)  # staged copy-out ends each with 8 bytes
         return lf
     if name == "census_cost":                # Eq. (15) as the final cost
         lf = lfsynth.workload("paper_s", seed=13, H=40, W=52, S=5, T=5, N=24)
