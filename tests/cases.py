@@ -57,6 +57,10 @@ def case(name):
         lf = lfsynth.workload("paper_s", seed=26, H=19, W=27, S=3, T=3, N=200)
         lf.params.update(P1_init=60, P2_init=250, sum_bits=32)
         return lf
+    if name == "k3_u16":                     # K = 3 with 16-bit path costs (384-byte rows)
+        lf = lfsynth.workload("paper_s", seed=27, H=21, W=25, S=3, T=3, N=150)
+        lf.params.update(P1_init=60, P2_init=250, sum_bits=32)
+        return lf
     if name == "census_cost":                # Eq. (15) as the final cost
         lf = lfsynth.workload("paper_s", seed=13, H=40, W=52, S=5, T=5, N=24)
         lf.params.update(cost_kind=1, win_h=5, win_w=5, sum_bits=16)
@@ -104,6 +108,6 @@ def case(name):
 CASES = ["small", "f32_ragged", "u8_n65", "n256", "stage_1x11", "col_7x1", "one_row", "one_col",
          "u16_paths", "census_cost", "paths16", "paths16_u16", "boundless", "rgb_f32",
          "rgb_u8_census", "adaptive", "u8_inf_add", "fill_4", "fill_3_sparse", "u16_tail", "k3_u8",
-         "k4_u16"]
+         "k4_u16", "k3_u16"]
 
 

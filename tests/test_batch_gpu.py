@@ -24,7 +24,7 @@ torch = pytest.importorskip("torch")
 MIX = ["small", "f32_ragged", "u8_n65", "n256", "stage_1x11", "col_7x1", "one_row", "one_col",
        "u16_paths", "census_cost", "paths16", "paths16_u16", "boundless", "rgb_f32",
        "rgb_u8_census", "adaptive", "u8_inf_add", "fill_4", "fill_3_sparse", "u16_tail", "k3_u8",
-       "k4_u16"]
+       "k4_u16", "k3_u16"]
 
 
 @pytest.fixture(scope="module")
