@@ -35,6 +35,7 @@ __all__ = [
 # ----------------------------------------------------------------------------
 _GRADS = np.array([[1, 1], [-1, 1], [1, -1], [-1, -1],
                    [1, 0], [-1, 0], [0, 1], [0, -1]], dtype=np.float64)
+_GX, _GY = np.ascontiguousarray(_GRADS[:, 0]), np.ascontiguousarray(_GRADS[:, 1])
 
 
 def _fade(t):
@@ -53,15 +54,18 @@ def perlin2(x, y, perm):
     v = _fade(yf)
 
     def grad(h, dx, dy):
-        g = _GRADS[h & 7]
-        return g[..., 0] * dx + g[..., 1] * dy
+        i = h & 7
+        return _GX[i] * dx + _GY[i] * dy
 
-    aa = perm[perm[X] + Y]
-    ab = perm[perm[X] + Y + 1]
-    ba = perm[perm[X + 1] + Y]
-    bb = perm[perm[X + 1] + Y + 1]
-    x1 = grad(aa, xf, yf) + u * (grad(ba, xf - 1, yf) - grad(aa, xf, yf))
-    x2 = grad(ab, xf, yf - 1) + u * (grad(bb, xf - 1, yf - 1) - grad(ab, xf, yf - 1))
+    pX, pX1 = perm[X], perm[X + 1]
+    aa = perm[pX + Y]
+    ab = perm[pX + Y + 1]
+    ba = perm[pX1 + Y]
+    bb = perm[pX1 + Y + 1]
+    g_aa = grad(aa, xf, yf)
+    g_ab = grad(ab, xf, yf - 1)
+    x1 = g_aa + u * (grad(ba, xf - 1, yf) - g_aa)
+    x2 = g_ab + u * (grad(bb, xf - 1, yf - 1) - g_ab)
     return x1 + v * (x2 - x1)
 
 
@@ -180,50 +184,59 @@ def render(scene: Scene, S: int, T: int, dtype=np.float32, noise_sigma=0.0, rng=
     yy, xx = np.meshgrid(np.arange(H, dtype=np.float64), np.arange(W, dtype=np.float64),
                          indexing="ij")
     views = np.empty((T, S, H, W), dtype=dtype)
-    gt = None
-    for t in range(T):
-        for s in range(S):
-            cs, ct = sh - s, th - t
-            best_d = np.full((H, W), -np.inf)
-            best_j = np.full((H, W), -1, dtype=np.int64)
-            best_u = np.zeros((H, W))
-            best_v = np.zeros((H, W))
-            for j, pl in enumerate(scene.planes):
-                # x = u + cs d(u,v), y = v + ct d(u,v) with d linear in (u, v)
-                k0 = pl.a - pl.b * pl.uc - pl.c * pl.vc
-                m00, m01 = 1.0 + cs * pl.b, cs * pl.c
-                m10, m11 = ct * pl.b, 1.0 + ct * pl.c
-                det = m00 * m11 - m01 * m10
-                rx = xx - cs * k0
-                ry = yy - ct * k0
-                u = (m11 * rx - m01 * ry) / det
-                v = (m00 * ry - m10 * rx) / det
-                d = pl.a + pl.b * (u - pl.uc) + pl.c * (v - pl.vc)
-                if np.isinf(pl.ax):
-                    inside = np.ones((H, W), dtype=bool)
-                elif pl.square:
-                    inside = (np.abs(u - pl.uc) < pl.ax) & (np.abs(v - pl.vc) < pl.ay)
-                else:
-                    inside = ((u - pl.uc) / pl.ax) ** 2 + ((v - pl.vc) / pl.ay) ** 2 <= 1.0
-                take = inside & (d > best_d)
-                best_d = np.where(take, d, best_d)
-                best_j = np.where(take, j, best_j)
-                best_u = np.where(take, u, best_u)
-                best_v = np.where(take, v, best_v)
-            img = np.zeros((H, W))
-            for j, pl in enumerate(scene.planes):
-                sel = best_j == j
-                if not sel.any():
-                    continue
-                img[sel] = _bilinear(pl.texture, best_u[sel] + pl.margin, best_v[sel] + pl.margin)
-            if noise_sigma > 0:
-                img = img + rng.normal(0.0, noise_sigma, size=img.shape)
-            if np.dtype(dtype) == np.uint8:
-                views[t, s] = np.clip(np.rint(img), 0, 255).astype(np.uint8)
+    # the noise of every view is drawn first, in view order, so that the views can
+    # be rendered in any order with the same values
+    noise = {}
+    if noise_sigma > 0:
+        for t in range(T):
+            for s in range(S):
+                noise[t, s] = rng.normal(0.0, noise_sigma, size=(H, W))
+
+    def one_view(ts):
+        t, s = ts
+        cs, ct = sh - s, th - t
+        best_d = np.full((H, W), -np.inf)
+        best_j = np.full((H, W), -1, dtype=np.int64)
+        best_u = np.zeros((H, W))
+        best_v = np.zeros((H, W))
+        for j, pl in enumerate(scene.planes):
+            # x = u + cs d(u,v), y = v + ct d(u,v) with d linear in (u, v)
+            k0 = pl.a - pl.b * pl.uc - pl.c * pl.vc
+            m00, m01 = 1.0 + cs * pl.b, cs * pl.c
+            m10, m11 = ct * pl.b, 1.0 + ct * pl.c
+            det = m00 * m11 - m01 * m10
+            rx = xx - cs * k0
+            ry = yy - ct * k0
+            u = (m11 * rx - m01 * ry) / det
+            v = (m00 * ry - m10 * rx) / det
+            d = pl.a + pl.b * (u - pl.uc) + pl.c * (v - pl.vc)
+            if np.isinf(pl.ax):
+                inside = np.ones((H, W), dtype=bool)
+            elif pl.square:
+                inside = (np.abs(u - pl.uc) < pl.ax) & (np.abs(v - pl.vc) < pl.ay)
             else:
-                views[t, s] = np.clip(img, 0.0, 1.0).astype(np.float32)
-            if s == (S - 1) // 2 and t == (T - 1) // 2:
-                gt = best_d.astype(np.float32)
+                inside = ((u - pl.uc) / pl.ax) ** 2 + ((v - pl.vc) / pl.ay) ** 2 <= 1.0
+            take = inside & (d > best_d)
+            best_d = np.where(take, d, best_d)
+            best_j = np.where(take, j, best_j)
+            best_u = np.where(take, u, best_u)
+            best_v = np.where(take, v, best_v)
+        img = np.zeros((H, W))
+        for j, pl in enumerate(scene.planes):
+            sel = best_j == j
+            if not sel.any():
+                continue
+            img[sel] = _bilinear(pl.texture, best_u[sel] + pl.margin, best_v[sel] + pl.margin)
+        if noise_sigma > 0:
+            img = img + noise[t, s]
+        if np.dtype(dtype) == np.uint8:
+            views[t, s] = np.clip(np.rint(img), 0, 255).astype(np.uint8)
+        else:
+            views[t, s] = np.clip(img, 0.0, 1.0).astype(np.float32)
+        return best_d.astype(np.float32)
+
+    depth = _parallel_map(one_view, [(t, s) for t in range(T) for s in range(S)])
+    gt = depth[((T - 1) // 2) * S + (S - 1) // 2]
     return views, gt
 
 
@@ -246,17 +259,42 @@ def two_plane_scene(seed, H=96, W=96, d_back=-1.25, d_front=0.75, S=5, T=5):
     return Scene(H, W, [back, front])
 
 
-def _perlin_texture(rng, H, W, margin):
+def _draw_perlin_texture(rng, H, W, margin):
+    """The random draws of one Perlin+noise texture, in their fixed order; the
+    texture itself is computed later by _perlin_from_draws (so that several can be
+    computed at once without changing any value)."""
     perm = rng.permutation(256)
     perm = np.concatenate([perm, perm]).astype(np.int64)
     sigma = rng.uniform(16.0, 64.0)
     hh, ww = H + 2 * margin + 2, W + 2 * margin + 2
+    ox, oy = rng.uniform(0, 256, size=2)
+    noise = rng.uniform(0.0, 1.0, size=(hh, ww))
+    return (perm, sigma, ox, oy, noise)
+
+
+def _perlin_from_draws(draws):
+    perm, sigma, ox, oy, noise = draws
+    hh, ww = noise.shape
     yy, xx = np.meshgrid(np.arange(hh, dtype=np.float64), np.arange(ww, dtype=np.float64),
                          indexing="ij")
-    ox, oy = rng.uniform(0, 256, size=2)
     f = fbm(xx / sigma + ox, yy / sigma + oy, perm, octaves=4)
-    noise = rng.uniform(0.0, 1.0, size=(hh, ww))
     return np.clip(0.5 + 0.35 * f + 0.15 * (noise - 0.5), 0.0, 1.0)
+
+
+def _parallel_map(fn, items):
+    """map() over a thread pool (numpy releases the GIL in the array work); the
+    results do not depend on the schedule."""
+    import concurrent.futures as cf
+    import os
+    items = list(items)
+    if len(items) <= 1:
+        return [fn(x) for x in items]
+    with cf.ThreadPoolExecutor(max_workers=min(len(items), os.cpu_count() or 1, 16)) as ex:
+        return list(ex.map(fn, items))
+
+
+def _perlin_texture(rng, H, W, margin):
+    return _perlin_from_draws(_draw_perlin_texture(rng, H, W, margin))
 
 
 def slanted_scene(seed, H, W, d_min, d_max, n_planes=12, S=9, T=9, channels=1):
@@ -264,10 +302,10 @@ def slanted_scene(seed, H, W, d_min, d_max, n_planes=12, S=9, T=9, channels=1):
     (channels = 3: an independent texture per colour channel)."""
     rng = np.random.default_rng(seed)
 
+    # each texture's random draws are taken here in order; the textures are computed
+    # together at the end
     def texture():
-        if channels == 1:
-            return _perlin_texture(rng, H, W, margin)
-        return np.stack([_perlin_texture(rng, H, W, margin) for _ in range(channels)])
+        return [_draw_perlin_texture(rng, H, W, margin) for _ in range(channels)]
 
     span = d_max - d_min
     margin = int(np.ceil(max(S, T) / 2.0 * max(abs(d_min), abs(d_max)))) + 3
@@ -291,6 +329,11 @@ def slanted_scene(seed, H, W, d_min, d_max, n_planes=12, S=9, T=9, channels=1):
             b, c = b * f, c * f
         planes.append(Plane(a=a, b=b, c=c, uc=uc, vc=vc, ax=ax, ay=ay,
                             texture=texture(), margin=margin))
+    flat = [d for pl in planes for d in pl.texture]
+    tex = _parallel_map(_perlin_from_draws, flat)
+    for j, pl in enumerate(planes):
+        t = tex[j * channels:(j + 1) * channels]
+        pl.texture = t[0] if channels == 1 else np.stack(t)
     return Scene(H, W, planes)
 
 
