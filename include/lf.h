@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define LF_ABI_VERSION 3
+#define LF_ABI_VERSION 4
 #define LF_MAX_HYPOTHESES 256
 #define LF_MAX_SIDE 65536
 
@@ -167,10 +167,18 @@ size_t lf_initial_workspace_size(int32_t S, int32_t T, int32_t C, int32_t H, int
  *     8-neighbours), Sobel edge exclusion, borders of Eq. (11) saturated to
  *     [0, N-1]; invalid and edge pixels get the full range.
  * d_maps: [|V|][H][W] int16 or NULL; d_init, d_lo, d_hi: [H][W] int16.
+ * census_cost, csum_init: optional outputs for checking (NULL skips them; asking
+ * for them adds copy kernels, it changes no other output):
+ *   census_cost [|V|][H][W][N] uint8: C_i(p,k) of Eq. (7) (channels summed);
+ *   csum_init   [|V|][H][W][N] uint16: the aggregated cost of Eq. (9) from which
+ *               D_i is taken, path costs in the normalised form of Eq. (8)
+ *               (m = min_j L_r(p-r,j) subtracted at every step; the first pixel of
+ *               a path takes L_r = C).
  * ws: at least lf_initial_workspace_size() bytes, 256-byte aligned. */
 lf_status lf_initial_disparity(const lf_view_set* views, const float* hyp, int32_t N,
                                const lf_params* prm, int16_t* d_maps, int16_t* d_init,
-                               int16_t* d_lo, int16_t* d_hi, void* ws, size_t ws_bytes,
+                               int16_t* d_lo, int16_t* d_hi, uint8_t* census_cost,
+                               uint16_t* csum_init, void* ws, size_t ws_bytes,
                                hipStream_t stream);
 
 /* Bytes of workspace lf_cost_volume_bounded needs (prefix-sum scratch, and the
@@ -210,6 +218,11 @@ size_t lf_sgm_workspace_size(int32_t H, int32_t W, int32_t N, int32_t npaths);
  * first pixel of a path takes L_r = C.  csum[cell] = sum over directions.
  * cost: uint16 [cells], every value <= lf_cost_cap(sgm.P2, sgm.npaths, sum_bits)
  * (the caller's contract; lf_cost_volume_bounded guarantees it).
+ * Bounds contract (device data, not checked on the host): 0 <= d_lo[p] <= d_hi[p]
+ * < N for every pixel and offsets = the exclusive prefix sum of d_hi - d_lo + 1,
+ * as lf_initial_disparity and lf_cost_volume_bounded produce them; the cell count
+ * offsets[H*W] is then <= H*W*N.  The kernels clamp the count to H*W*N; other
+ * breaches give unspecified results.
  * csum: uint16 (sum_bits 16) or uint32 (32) [cells], CSR layout of `cost`.
  * ws: at least lf_sgm_workspace_size() bytes. */
 lf_status lf_sgm_aggregate(const uint16_t* cost, const int64_t* offsets, const int16_t* d_lo,
@@ -228,7 +241,9 @@ size_t lf_wta_workspace_size(int32_t H, int32_t W);
  *  reversed), disparity = o >= 0 ? fma(o, d[k*+1]-d[k*], d[k*])
  *                                : fma(o, d[k*]-d[k*-1], d[k*]); else d[k*];
  *  median = 3: the 3x3 median (clamp-to-edge) of that map.
- * d_index: [H][W] int16; disparity: [H][W] float32. */
+ * d_index: [H][W] int16; disparity: [H][W] float32.
+ * Bounds contract as for lf_sgm_aggregate; bounds outside [0, N-1] are clamped
+ * into it (no hypothesis outside the array is read; results are unspecified). */
 lf_status lf_wta_subpixel(const void* csum, int32_t sum_bits, const int64_t* offsets,
                           const int16_t* d_lo, const int16_t* d_hi, int32_t H, int32_t W,
                           const float* hyp, int32_t N, int32_t median, int16_t* d_index,
@@ -358,9 +373,15 @@ typedef struct {
 lf_status lf_server_create(const lf_server_config* cfg, lf_server** out);
 
 /* Queues a request (copied; its buffers must stay valid until it completes).
+ * Ordering: the request's device work starts only after everything enqueued on
+ * `stream` before this call (the producer of its views and hypotheses, earlier
+ * users of its outputs) has completed: an event is recorded on `stream` here and
+ * the batch's stream waits for it.  NULL is the null stream.
+ * If the event cannot be recorded the request completes with LF_EDEVICE.
  * Returns LF_EINVAL for an invalid request, LF_ENOSPACE if its workspace can
  * never fit in the arena, LF_EBUSY if the queue is full; *ticket identifies it. */
-lf_status lf_server_submit(lf_server* srv, const lf_request* req, int64_t* ticket);
+lf_status lf_server_submit(lf_server* srv, const lf_request* req, hipStream_t stream,
+                           int64_t* ticket);
 
 /* Waits up to timeout_s seconds (< 0: forever) for a ticket; on completion
  * returns the request's status (LF_OK when its outputs are ready) and fills

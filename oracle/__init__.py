@@ -240,8 +240,10 @@ def cost_cap(P2_final, npaths, sum_bits):
     return lib().lfo_cost_cap(int(P2_final), int(npaths), int(sum_bits))
 
 
-def depth(views, hyp, params, want_intermediates=False):
-    """The whole method (Sec. 3.3-3.6) on one light field; returns a dict."""
+def depth(views, hyp, params, want_intermediates=False, want_initial_volumes=False):
+    """The whole method (Sec. 3.3-3.6) on one light field; returns a dict.  With
+    want_initial_volumes also init_cost ([|V|][H][W][N] int32, Eq. 7) and init_csum
+    ([|V|][H][W][N] int64, Eq. 9) of the initial stage."""
     views, T, S, Cn, H, W = _views(views)
     hyp = _f32(hyp)
     N = hyp.shape[0]
@@ -261,6 +263,10 @@ def depth(views, hyp, params, want_intermediates=False):
                    lo=np.zeros((H, W), np.int16), hi=np.zeros((H, W), np.int16),
                    cost=np.zeros((H, W, N), np.int32), csum=np.zeros((H, W, N), np.int64))
         args = [out[k] for k in ("maps", "dinit", "lo", "hi", "cost", "csum")]
+    if want_initial_volumes:
+        out.update(init_cost=np.zeros((nv, H, W, N), np.int32),
+                   init_csum=np.zeros((nv, H, W, N), np.int64))
+    args = args + [out.get("init_cost"), out.get("init_csum")]
     rc = lib().lfo_depth(_p(views), S, T, H, W, _p(hyp), N, C.byref(prm), _p(disp), _p(idx),
                          *[_p(a) for a in args])
     if rc != 0:

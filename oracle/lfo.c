@@ -431,7 +431,8 @@ int32_t lfo_cost_cap(int P2_final, int npaths, int sum_bits)
 int lfo_depth(const float* views, int S, int T, int H, int W, const float* hyp, int N,
               const lfo_params* prm, float* disparity, int16_t* d_index,
               int16_t* maps_out, int16_t* dinit_out, int16_t* lo_out, int16_t* hi_out,
-              int32_t* cost_out, int64_t* csum_out)
+              int32_t* cost_out, int64_t* csum_out, int32_t* init_cost_out,
+              int64_t* init_csum_out)
 {
     if (S < 1 || T < 1 || (S % 2) == 0 || (T % 2) == 0 || S * T < 2 || H < 1 || W < 1 || N < 2)
         return -1;
@@ -464,6 +465,8 @@ int lfo_depth(const float* views, int S, int T, int H, int W, const float* hyp, 
         }
         lfo_sgm(cost, NULL, NULL, H, W, N, prm->P1_init, prm->P2_init, prm->npaths, csum);
         lfo_wta(csum, NULL, NULL, H, W, N, maps + (size_t)i * plane);
+        if (init_cost_out) memcpy(init_cost_out + (size_t)i * vol, cost, vol * sizeof(int32_t));
+        if (init_csum_out) memcpy(init_csum_out + (size_t)i * vol, csum, vol * sizeof(int64_t));
     }
     free(cpart);
 

@@ -156,12 +156,14 @@ typedef struct {
 } lfo_params;
 
 /* The whole method, Sec. 3.3-3.6.  Optional outputs may be NULL:
- * maps [|V|][H][W], dinit/lo/hi [H][W], cost/csum dense [H][W][N].
+ * maps [|V|][H][W], dinit/lo/hi [H][W], cost/csum dense [H][W][N] (final stage),
+ * init_cost [|V|][H][W][N] (Eq. 7, channels summed) and init_csum [|V|][H][W][N]
+ * (Eq. 9 over the initial stage's paths) of every cross view.
  * Returns 0, or -1 on invalid arguments. */
 int lfo_depth(const float* views, int S, int T, int H, int W, const float* hyp, int N,
               const lfo_params* prm, float* disparity, int16_t* d_index,
               int16_t* maps, int16_t* dinit, int16_t* lo, int16_t* hi,
-              int32_t* cost, int64_t* csum);
+              int32_t* cost, int64_t* csum, int32_t* init_cost, int64_t* init_csum);
 
 #ifdef __cplusplus
 }

@@ -523,7 +523,8 @@ size_t lf_initial_workspace_size(int32_t S, int32_t T, int32_t C, int32_t H, int
 
 lf_status lf_initial_disparity(const lf_view_set* views, const float* hyp, int32_t N,
                                const lf_params* prm, int16_t* d_maps, int16_t* d_init,
-                               int16_t* d_lo, int16_t* d_hi, void* ws, size_t ws_bytes,
+                               int16_t* d_lo, int16_t* d_hi, uint8_t* census_cost,
+                               uint16_t* csum_init, void* ws, size_t ws_bytes,
                                hipStream_t stream) {
     LF_CHECK(check_views(views));
     LF_CHECK(check_shape(views->S, views->T, views->H, views->W, N));
@@ -544,6 +545,8 @@ lf_status lf_initial_disparity(const lf_view_set* views, const float* hyp, int32
     j.census = pl.census;
     j.paths = pl.paths;
     j.maps = d_maps ? d_maps : pl.maps;
+    j.ccv_out = census_cost;
+    j.csum_init_out = csum_init;
     j.fill_tmp = pl.tmp;
     j.dinit = d_init;
     j.lo = d_lo;

@@ -146,6 +146,8 @@ struct Job {
     uint64_t* census;         // [1 + nv][C][H*W]: reference, then the cross views
     void* paths;              // initial SGM scratch (sgm_dense_scratch_bytes)
     int16_t* maps;            // [nv][H*W] D_i
+    uint8_t* ccv_out;         // [nv][H*W][N] Census costs of Eq. (7), or null (checking)
+    uint16_t* csum_init_out;  // [nv][H*W][N] aggregated initial costs, or null (checking)
     int16_t* fill_tmp;        // [H*W]
     int16_t* dinit;           // [H*W]
     int16_t* lo;              // [H*W]

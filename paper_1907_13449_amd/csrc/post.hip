@@ -380,12 +380,14 @@ struct WtaArgs {
     const float* hyp;
     int16_t* d_index;
     float* disp;
-    int HW;
+    int HW, N;
 };
 
 template <typename SumT>
 __device__ __forceinline__ void wta_pixel(const WtaArgs& a, int p) {
-    const int l = a.lo[p], h = a.hi[p];
+    // bounds outside the documented 0 <= lo <= hi < N are clamped into it, so no
+    // hypothesis outside [0, N) is read (the result is then unspecified)
+    const int l = clampi(a.lo[p], 0, a.N - 1), h = clampi(a.hi[p], l, a.N - 1);
     const SumT* c = (const SumT*)a.csum + a.off[p] - l;     // c[k] for k in [l, h]
     const float* hyp = a.hyp;
     // in increasing k, strict <, so the lowest index wins ties; eight loads in
@@ -611,6 +613,7 @@ hipError_t stage_wta(Runner& r, const Jobs& jobs) {
         a.d_index = j->d_index;
         a.disp = median ? j->pre_median : j->disparity;
         a.HW = HW;
+        a.N = j->N;
         const int sb = j->prm.sum_bits == 16 ? 0 : 1;
         wta[sb].push_back(a);
         wta_blocks[sb].push_back(blocks_for(HW));

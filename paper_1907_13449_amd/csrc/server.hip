@@ -39,6 +39,8 @@ struct Pending {
     int64_t ticket;
     lf_request q;
     size_t bytes;             // its lf_depth workspace, aligned
+    hipEvent_t ready;         // recorded on the submitter's stream
+    bool ready_failed;        // it could not be recorded: the request fails with LF_EDEVICE
     lf_request_info info;
 };
 
@@ -117,7 +119,12 @@ struct lf_server {
         }
     }
 
+    // Events of finished requests, kept for reuse (guarded by mu).
+    std::vector<hipEvent_t> event_pool;
+
     void finish(Pending& r, int32_t status) {
+        if (r.ready) event_pool.push_back(r.ready);
+        r.ready = nullptr;
         r.info.status = status;
         r.info.t_done = now();
         done[r.ticket] = r.info;
@@ -194,6 +201,15 @@ struct lf_server {
         std::vector<lf_request> qs;
         for (const Pending& r : b.reqs) qs.push_back(r.q);
         hipStream_t st = streams[b.slot];
+        // each member's inputs were produced on its submitter's stream
+        for (const Pending& r : b.reqs) {
+            if (r.ready_failed || !r.ready)
+                return lf::record_error(LF_EDEVICE, "%s",
+                                        "a request's ordering event could not be recorded");
+            if (hipError_t e = hipStreamWaitEvent(st, r.ready, 0); e != hipSuccess)
+                return lf::record_error(LF_EDEVICE, "server stream wait: %s",
+                                        hipGetErrorString(e));
+        }
         lf_status s = lf_plan_create(qs.data(), (int)qs.size(), (char*)cfg.arena + b.off, b.len,
                                      &cfg.tuning, st, &b.plan);
         if (s != LF_OK) return s;
@@ -300,7 +316,8 @@ lf_status lf_server_create(const lf_server_config* cfg, lf_server** out) {
     return LF_OK;
 }
 
-lf_status lf_server_submit(lf_server* srv, const lf_request* req, int64_t* ticket) {
+lf_status lf_server_submit(lf_server* srv, const lf_request* req, hipStream_t stream,
+                           int64_t* ticket) {
     if (!srv || !ticket) return lf::record_error(LF_EINVAL, "%s", "NULL argument");
     lf_status st = lf::validate_request(req, 0, nullptr);
     if (st != LF_OK) return st;
@@ -312,6 +329,15 @@ lf_status lf_server_submit(lf_server* srv, const lf_request* req, int64_t* ticke
     if ((int)srv->pending.size() >= srv->cfg.max_queue)
         return lf::record_error(LF_EBUSY, "%s", "request queue is full");
     Pending p{};
+    // the ordering event; if it cannot be made or recorded the request is still
+    // queued and completes with LF_EDEVICE, like any other device failure
+    if (!srv->event_pool.empty()) {
+        p.ready = srv->event_pool.back();
+        srv->event_pool.pop_back();
+    } else if (hipEventCreateWithFlags(&p.ready, hipEventDisableTiming) != hipSuccess) {
+        p.ready = nullptr;
+    }
+    p.ready_failed = !p.ready || hipEventRecord(p.ready, stream) != hipSuccess;
     p.ticket = srv->next_ticket++;
     p.q = *req;
     p.bytes = align_up(lf::request_workspace_bytes(req));
@@ -362,6 +388,7 @@ void lf_server_destroy(lf_server* srv) {
     }
     srv->cv_sched.notify_all();
     srv->th.join();
+    for (hipEvent_t e : srv->event_pool) (void)hipEventDestroy(e);
     if (srv->device_ready)
         for (int i = 0; i < srv->cfg.max_inflight; ++i) {
             if (srv->events[i]) (void)hipEventDestroy(srv->events[i]);

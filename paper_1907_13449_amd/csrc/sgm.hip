@@ -605,6 +605,38 @@ __global__ __launch_bounds__(256) void dense_sum_wta_kernel(Src src) {
     }
 }
 
+// Optional outputs of the initial stage for checking: the Census cost of Eq. (7)
+// and the aggregated cost of Eq. (9) of every cross view, [nv][H*W][N], copied
+// and summed out of the stage's own buffers (element e = (z*HW + p)*N + k).
+struct ExportArgs {
+    const void* src;          // cvol [nv][HW][NPc] (8-bit), or Lbuf [npaths][nv][HW][NP]
+    void* dst;                // [nv][HW][N]: 8-bit costs, or 16-bit sums
+    int64_t rows;             // nv * HW
+    int N, NP, npaths, lt;    // lt: bytes per path-cost element (sums)
+};
+
+template <class Src, bool kSum>
+__global__ __launch_bounds__(256) void initial_export_kernel(Src src) {
+    for (uint32_t vb = blockIdx.x; vb < src.total; vb += gridDim.x) {
+        uint32_t b;
+        const ExportArgs& a = member(src, vb, b);
+        const int64_t e = (int64_t)b * 256 + threadIdx.x;
+        if (e >= a.rows * a.N) continue;
+        const int64_t q = e / a.N;
+        const int64_t at = q * a.NP + (e - q * a.N);
+        if constexpr (!kSum) {
+            ((uint8_t*)a.dst)[e] = ((const uint8_t*)a.src)[at];
+        } else {
+            const int64_t dir = a.rows * a.NP;
+            uint32_t s = 0;
+            for (int r = 0; r < a.npaths; ++r)
+                s += a.lt == 1 ? ((const uint8_t*)a.src)[r * dir + at]
+                               : ((const uint16_t*)a.src)[r * dir + at];
+            ((uint16_t*)a.dst)[e] = (uint16_t)s;
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Final stage: CSR volume over per-pixel ranges [lo, hi].  Output Lbuf[r][cell].
 // meta[p] = {off[p] - lo[p] (int64), lo | hi << 16}: one 16-byte load per step.
@@ -744,7 +776,9 @@ __global__ __launch_bounds__(256) void bounded_sum_kernel(Src src) {
     for (uint32_t vb = blockIdx.x; vb < src.total; vb += gridDim.x) {
         uint32_t b;
         const BsumArgs& a = member(src, vb, b);
-        const int64_t n = *a.total;
+        // the device-side count, never past the buffers (offsets that are not the
+        // prefix sum of in-range widths would otherwise run past them)
+        const int64_t n = min(*a.total, (int64_t)a.dir_stride);
         const uint16_t* __restrict__ L = a.Lbuf;
         SumT* __restrict__ csum = (SumT*)a.csum;
         for (int64_t c = (int64_t)b * 256 + threadIdx.x; c < n; c += (int64_t)a.nblk * 256) {
@@ -870,6 +904,8 @@ hipError_t stage_sgm_initial(Runner& r, const Jobs& jobs, int part) {
     std::vector<uint32_t> sum_blocks[2][2];
     std::vector<SumWtaArgs> rows[2];               // 8-bit rows <= 128 B: [8/16 paths]
     std::vector<uint32_t> row_blocks[2];
+    std::vector<ExportArgs> ex_cost, ex_sum;       // outputs for checking
+    std::vector<uint32_t> ex_cost_blocks, ex_sum_blocks;
     for (const Job* j : jobs) {
         const int H = j->H, W = j->W, N = j->N, NPc = dense_cvol_np(N);
         const size_t HW = (size_t)H * W;
@@ -925,6 +961,17 @@ hipError_t stage_sgm_initial(Runner& r, const Jobs& jobs, int part) {
         s.N = N;
         s.NP = NP;
         s.dmap = j->maps;
+        const uint32_t ex_blocks = div_up((uint64_t)j->nv * HW * N, 256);
+        if (j->ccv_out) {
+            ex_cost.push_back(ExportArgs{cvol, j->ccv_out, (int64_t)(j->nv * HW), N, NPc,
+                                         sp.npaths, 1});
+            ex_cost_blocks.push_back(ex_blocks);
+        }
+        if (j->csum_init_out) {
+            ex_sum.push_back(ExportArgs{Lbuf, j->csum_init_out, (int64_t)(j->nv * HW), N, NP,
+                                        sp.npaths, 1 << lt});
+            ex_sum_blocks.push_back(ex_blocks);
+        }
         const int np16 = sp.npaths == 16 ? 1 : 0;
         if (lt == 0 && NP <= 128) {
             rows[np16].push_back(s);
@@ -935,9 +982,20 @@ hipError_t stage_sgm_initial(Runner& r, const Jobs& jobs, int part) {
         }
     }
     hipError_t e = hipSuccess;
-    if (part == 0)
-        return launch(r, kStInitCost, census_cost_volume_kernel<Single<CcvArgs>>,
-                      census_cost_volume_kernel<Group<CcvArgs>>, ccv, ccv_blocks, 256);
+    using EA = ExportArgs;
+    if (part == 0) {
+        e = launch(r, kStInitCost, census_cost_volume_kernel<Single<CcvArgs>>,
+                   census_cost_volume_kernel<Group<CcvArgs>>, ccv, ccv_blocks, 256);
+        if (e == hipSuccess && !ex_cost.empty())
+            e = launch(r, kStInitCost, initial_export_kernel<Single<EA>, false>,
+                       initial_export_kernel<Group<EA>, false>, ex_cost, ex_cost_blocks, 256);
+        return e;
+    }
+    if (part == 2 && !ex_sum.empty() &&
+        (e = launch(r, kStInitSum, initial_export_kernel<Single<EA>, true>,
+                    initial_export_kernel<Group<EA>, true>, ex_sum, ex_sum_blocks, 256)) !=
+            hipSuccess)
+        return e;
     if (part == 1) {
         for (int K = 0; K < 4; ++K)
             for (int v = 0; v < 3; ++v) {

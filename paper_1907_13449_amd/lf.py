@@ -101,7 +101,7 @@ def _load():
     P, i32, i64, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
     lib.lf_census.argtypes = [P, i32, i32, i32, i32, CensusWindow, P, P]
     lib.lf_initial_workspace_size.argtypes = [i32, i32, i32, i32, i32, i32, P]
-    lib.lf_initial_disparity.argtypes = [P, P, i32, P, P, P, P, P, P, sz, P]
+    lib.lf_initial_disparity.argtypes = [P, P, i32, P, P, P, P, P, P, P, P, sz, P]
     lib.lf_cost_workspace_size.argtypes = [i32, i32, i32, i32, i32, i32, P]
     lib.lf_cost_volume_bounded.argtypes = [P, P, i32, P, P, P, P, P, i64, P, P, sz, P]
     lib.lf_sgm_workspace_size.argtypes = [i32, i32, i32, i32]
@@ -128,7 +128,7 @@ def _load():
     lib.lf_plan_destroy.argtypes = [P]
     lib.lf_plan_destroy.restype = None
     lib.lf_server_create.argtypes = [P, P]
-    lib.lf_server_submit.argtypes = [P, P, P]
+    lib.lf_server_submit.argtypes = [P, P, P, P]
     lib.lf_server_wait.argtypes = [P, i64, C.c_double, P]
     lib.lf_server_stats.argtypes = [P, P, P, P, P]
     lib.lf_server_stats.restype = None
@@ -235,7 +235,10 @@ def lf_census(img: torch.Tensor, win_h: int, win_w: int, out=None, stream=None):
 
 
 def lf_initial_disparity(views: torch.Tensor, hyp: torch.Tensor, params: dict, want_maps=True,
-                         ws=None, stream=None):
+                         want_volumes=False, ws=None, stream=None):
+    """D_i per cross view, d_init, d_lo, d_hi; with want_volumes also the Census cost
+    volume of Eq. (7) ([|V|][H][W][N] uint8) and the aggregated cost of Eq. (9)
+    ([|V|][H][W][N], int16 tensor holding uint16 values)."""
     vs = view_set(views)
     prm = make_params(params)
     _dev(hyp, torch.float32, "hyp")
@@ -247,13 +250,18 @@ def lf_initial_disparity(views: torch.Tensor, hyp: torch.Tensor, params: dict, w
     d_init = torch.empty((H, W), dtype=torch.int16, device=dev)
     d_lo = torch.empty((H, W), dtype=torch.int16, device=dev)
     d_hi = torch.empty((H, W), dtype=torch.int16, device=dev)
+    ccv = csum = None
+    if want_volumes:
+        ccv = torch.empty((nv, H, W, N), dtype=torch.uint8, device=dev)
+        csum = torch.empty((nv, H, W, N), dtype=torch.int16, device=dev)
     need = lib.lf_initial_workspace_size(vs.S, vs.T, vs.channels, H, W, N, C.byref(prm))
     if ws is None:
         ws = workspace(need, dev)
     _check(lib.lf_initial_disparity(C.byref(vs), _ptr(hyp), N, C.byref(prm), _ptr(maps),
-                                    _ptr(d_init), _ptr(d_lo), _ptr(d_hi), _ptr(ws), ws.numel(),
-                                    _stream(stream)))
-    return dict(maps=maps, d_init=d_init, d_lo=d_lo, d_hi=d_hi)
+                                    _ptr(d_init), _ptr(d_lo), _ptr(d_hi), _ptr(ccv), _ptr(csum),
+                                    _ptr(ws), ws.numel(), _stream(stream)))
+    return dict(maps=maps, d_init=d_init, d_lo=d_lo, d_hi=d_hi, census_cost=ccv,
+                csum_init=csum)
 
 
 def lf_cost_volume_bounded(views: torch.Tensor, hyp: torch.Tensor, params: dict,
@@ -444,10 +452,12 @@ class Server:
         _check(lib.lf_server_create(C.byref(cfg), C.byref(self._h)))
         self._keep = {}
 
-    def submit(self, views, hyp, params, disparity, d_index=None) -> int:
+    def submit(self, views, hyp, params, disparity, d_index=None, stream=None) -> int:
+        """Queues a request; its work is ordered after what the current (or the
+        given) torch stream has enqueued so far."""
         req = make_request(views, hyp, params, disparity, d_index)
         tk = C.c_int64()
-        _check(lib.lf_server_submit(self._h, C.byref(req), C.byref(tk)))
+        _check(lib.lf_server_submit(self._h, C.byref(req), _stream(stream), C.byref(tk)))
         self._keep[tk.value] = (views, hyp, disparity, d_index)
         return tk.value
 

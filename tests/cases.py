@@ -102,12 +102,23 @@ def case(name):
         lf = lfsynth.workload("paper_s", seed=20, H=44, W=50, S=7, T=7, N=80)
         lf.params.update(lam=2, lam_far=6)
         return lf
+    if name == "half_shifts":                # (s_hat - s) d_k = x.5 exactly for odd k: the
+        # nearest-pixel shift of Eq. (7) is decided by rounding half to even
+        sc = lfsynth.two_plane_scene(28, 40, 48, d_back=-1.25, d_front=1.25, S=5, T=5)
+        v, gt = lfsynth.render(sc, 5, 5, dtype=np.uint8)
+        return lfsynth.LightField(v, lfsynth.hypotheses(-2.0, 2.0, 17), gt, lfsynth._params())
+    if name == "plenoptic_s":                # 15x15 views (224 in the l2 sum), d in [-1.5, 1.5],
+        # N = 64, noise 0.01: the plenoptic shape of the large workload at reduced size
+        return lfsynth.workload("paper_s", seed=4001, H=56, W=80, S=15, T=15, N=64,
+                                d_min=-1.5, d_max=1.5, noise=0.01)
+    if name == "stage_s":                    # 1x11 u8 moving-stage light field, d in [0, 24],
+        return lfsynth.workload("stage", H=270, W=480)   # N = 96, |V| = 2, shifts to 120 px
     raise KeyError(name)
 
 
 CASES = ["small", "f32_ragged", "u8_n65", "n256", "stage_1x11", "col_7x1", "one_row", "one_col",
          "u16_paths", "census_cost", "paths16", "paths16_u16", "boundless", "rgb_f32",
          "rgb_u8_census", "adaptive", "u8_inf_add", "fill_4", "fill_3_sparse", "u16_tail", "k3_u8",
-         "k4_u16", "k3_u16"]
+         "k4_u16", "k3_u16", "half_shifts", "plenoptic_s", "stage_s"]
 
 

@@ -380,6 +380,63 @@ def test_cost_cap():
     assert lfo.cost_cap(120, 8, 16) + 2 * 120 <= 65535
 
 
+def _path_cost_extremes(cost, P1, P2, npaths):
+    """Largest path cost L_r over every direction and the largest sum C_s."""
+    dirs = [(1, 0), (-1, 0), (0, 1), (0, -1), (1, 1), (-1, -1), (1, -1), (-1, 1),
+            (1, 2), (-1, -2), (2, 1), (-2, -1), (2, -1), (-2, 1), (1, -2), (-1, 2)][:npaths]
+    lmax = max(int(lfo.sgm_path(cost, du, dv, P1, P2).max()) for du, dv in dirs)
+    return lmax, int(lfo.sgm(cost, P1, P2, npaths).max())
+
+
+@pytest.mark.parametrize("P2,npaths,sum_bits", [(35, 8, 32), (120, 8, 16), (250, 16, 16),
+                                                (16383, 8, 32)])
+def test_cost_cap_keeps_path_costs_and_sums_in_16_bits(P2, npaths, sum_bits):
+    # What the cap is for (reading R9): with every cost <= cap, the normalised path
+    # costs of Eq. (8) stay <= cap + P2 and leave room for the term m + P2 below a
+    # 16-bit +inf of 65535; with 16-bit sums, Eq. (9) stays <= 65535.  Checked on
+    # the oracle's own int64 path costs, on costs that sit at the cap with pits of
+    # zero cost (the jumps that push a path cost up by P2).
+    cap = lfo.cost_cap(P2, npaths, sum_bits)
+    rng = np.random.default_rng(P2 + npaths)
+    cost = np.full((9, 11, 6), cap, np.int32)
+    pits = rng.random(cost.shape) < 0.3
+    cost[pits] = rng.integers(0, cap + 1, size=int(pits.sum()))
+    lmax, smax = _path_cost_extremes(cost, P1=min(7, P2), P2=P2, npaths=npaths)
+    assert lmax <= cap + P2
+    assert lmax + P2 <= 65535                      # m + P2 never passes the sentinel
+    if sum_bits == 16:
+        assert smax <= 65535
+    # the bound L_r <= C + P2 is reached: a pixel at the cap after a zero-cost pit
+    # (the cap could not be raised by P2 without breaking it)
+    line = np.full((1, 2, 3), cap, np.int32)
+    line[0, 0, 0] = 0
+    L = lfo.sgm_path(line, 1, 0, P1=min(7, P2), P2=P2)
+    assert L[0, 1, 2] == cap + P2
+
+
+def test_initial_cost_rounds_half_pixel_shifts_to_even():
+    # Eq. (7) samples the cross view at the nearest pixel of the Eq. (1) position;
+    # a product (s_hat - s) d_k that is exactly x.5 goes to the even neighbour
+    # (reading R2: rint, round half to even).  cview[x] holds x set bits and cref
+    # none, so each cost is the column (or row) that was sampled.
+    n = 16
+    cref = np.zeros((1, n), np.uint64)
+    cview = np.array([[(1 << x) - 1 for x in range(n)]], np.uint64)
+    hyp = np.array([-2.5, -1.5, -0.5, 0.5, 1.5, 2.5], np.float32)
+    u = 7
+    cost = lfo.cost_census_view(cref, cview, 1, 0, hyp)
+    assert cost[0, u].tolist() == [u + round(float(d)) for d in hyp]   # Python: half to even
+    assert cost[0, u].tolist() == [5, 5, 7, 7, 9, 9]                   # half away: 4,5,6,8,9,10
+    # the same along the vertical axis with t_hat - t = 3; the product is rounded to
+    # float32 before rint: 3 * float32(1/6) is 0.50000001 in double precision (-> 1)
+    # but exactly 0.5 in float32 (-> 0)
+    cref_v = np.zeros((n, 1), np.uint64)
+    cview_v = cview.reshape(n, 1)
+    hyp_v = np.array([-0.5, 0.5, 1.0 / 6.0], np.float32)
+    cost_v = lfo.cost_census_view(cref_v, cview_v, 0, 3, hyp_v)
+    assert cost_v[u, 0].tolist() == [u - 2, u + 2, u]
+
+
 def test_census_all_constant_and_integer_plane():
     views = _shifted_lf(3, 3, 20, 22, 1, seed=5)
     hyp = lfsynth.hypotheses(-2, 2, 9)

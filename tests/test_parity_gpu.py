@@ -1,8 +1,10 @@
 """GPU parity: every C-ABI stage against the CPU oracle on identical seeded inputs.
 
 Bars (from the arithmetic of each stage):
-  - Census strings, initial maps D_i, fusion/fill/borders, CSR offsets, quantised
-    costs, aggregated costs C_s and WTA indices: bit-exact (integer work; the
+  - Census strings, the initial stage's Census cost volume (Eq. 7) and aggregated
+    cost (Eq. 9) of every cross view, initial maps D_i, fusion/fill/borders, CSR
+    offsets, quantised costs, aggregated costs C_s and WTA indices: bit-exact
+    (integer work; the
     float32 l2 sum that decides the quantised cost is evaluated in the same order
     and precision on both sides).
   - float32 l2 cost S: bit-exact against the oracle's float32 sum, and within
@@ -92,7 +94,7 @@ def results(lf, lfo):
         say("case", name, lfd.views.shape, lfd.views.dtype, "N", lfd.N)
         views, hyp = _to_dev(lfd)
         p = lfd.params
-        ini = lf.lf_initial_disparity(views, hyp, p)
+        ini = lf.lf_initial_disparity(views, hyp, p, want_volumes=True)
         cv = lf.lf_cost_volume_bounded(views, hyp, p, ini["d_lo"], ini["d_hi"], want_f32=True)
         csum = lf.lf_sgm_aggregate(cv["cost"], cv["offsets"], ini["d_lo"], ini["d_hi"], lfd.N,
                                    p["P1_final"], p["P2_final"], p["npaths"], p["sum_bits"])
@@ -107,7 +109,13 @@ def results(lf, lfo):
                  csum=(_u16(csum) if p["sum_bits"] == 16 else csum.cpu().numpy().view(np.uint32)),
                  d_index=wta["d_index"].cpu().numpy(), disp=wta["disparity"].cpu().numpy(),
                  depth=full.cpu().numpy())
-        o = lfo.depth(lfd.views, lfd.hyp, p, want_intermediates=True)
+        o = lfo.depth(lfd.views, lfd.hyp, p, want_intermediates=True, want_initial_volumes=True)
+        # the initial volumes are compared here and only the verdicts kept (they are
+        # |V| H W N each, the largest cases' dominate the memory otherwise)
+        g["init_cost_equal"] = np.array_equal(ini["census_cost"].cpu().numpy().astype(np.int32),
+                                              o.pop("init_cost"))
+        g["init_csum_equal"] = np.array_equal(
+            ini["csum_init"].cpu().numpy().view(np.uint16).astype(np.int64), o.pop("init_csum"))
         out[name] = (lfd, g, o)
     return out
 
@@ -119,6 +127,15 @@ def test_initial_stage_bit_exact(results, name):
     assert np.array_equal(g["d_init"], o["dinit"])
     assert np.array_equal(g["lo"], o["lo"])
     assert np.array_equal(g["hi"], o["hi"])
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_initial_volumes_bit_exact(results, name):
+    # every hypothesis, not only the winners: the Census cost of Eq. (7) and the
+    # aggregated cost of Eq. (9) of each cross view against the oracle's
+    lfd, g, o = results[name]
+    assert g["init_cost_equal"]
+    assert g["init_csum_equal"]
 
 
 @pytest.mark.parametrize("name", CASES)

@@ -80,11 +80,11 @@ def test_submit_checks_and_admission_limit(lf):
     assert st == lf.LF_OK
     try:
         tk = C.c_int64()
-        assert lf.lib.lf_server_submit(h, C.byref(_req(lf, N=300)), C.byref(tk)) == lf.LF_EUNSUPPORTED
-        assert lf.lib.lf_server_submit(h, C.byref(_req(lf, data=0)), C.byref(tk)) == lf.LF_EINVAL
+        assert lf.lib.lf_server_submit(h, C.byref(_req(lf, N=300)), None, C.byref(tk)) == lf.LF_EUNSUPPORTED
+        assert lf.lib.lf_server_submit(h, C.byref(_req(lf, data=0)), None, C.byref(tk)) == lf.LF_EINVAL
         # a light field whose workspace can never fit in the arena is refused at once
         big = _req(lf, S=9, T=9, H=512, W=512, N=100)
-        assert lf.lib.lf_server_submit(h, C.byref(big), C.byref(tk)) == lf.LF_ENOSPACE
+        assert lf.lib.lf_server_submit(h, C.byref(big), None, C.byref(tk)) == lf.LF_ENOSPACE
         assert "arena" in lf.lib.lf_last_error().decode()
         info = lf.RequestInfo()
         assert lf.lib.lf_server_wait(h, 12345, 0.0, C.byref(info)) == lf.LF_EINVAL
@@ -102,7 +102,7 @@ def test_device_failure_completes_requests_with_an_error(lf):
         tickets = []
         for i in range(6):
             tk = C.c_int64()
-            assert lf.lib.lf_server_submit(h, C.byref(_req(lf, N=8 + i)), C.byref(tk)) == lf.LF_OK
+            assert lf.lib.lf_server_submit(h, C.byref(_req(lf, N=8 + i)), None, C.byref(tk)) == lf.LF_OK
             tickets.append(tk.value)
         for t in tickets:
             info = lf.RequestInfo()
@@ -124,7 +124,7 @@ def test_destroy_cancels_queued_requests(lf):
     assert st == lf.LF_OK
     for _ in range(200):
         tk = C.c_int64()
-        assert lf.lib.lf_server_submit(h, C.byref(_req(lf)), C.byref(tk)) == lf.LF_OK
+        assert lf.lib.lf_server_submit(h, C.byref(_req(lf)), None, C.byref(tk)) == lf.LF_OK
     lf.lib.lf_server_destroy(h)                    # returns: nothing is left waiting
 
 
@@ -136,7 +136,7 @@ def test_queue_limit(lf):
         codes = set()
         for _ in range(400):
             tk = C.c_int64()
-            codes.add(lf.lib.lf_server_submit(h, C.byref(_req(lf)), C.byref(tk)))
+            codes.add(lf.lib.lf_server_submit(h, C.byref(_req(lf)), None, C.byref(tk)))
         assert codes <= {lf.LF_OK, lf.LF_EBUSY}
         assert lf.LF_OK in codes
     finally:
