@@ -263,6 +263,22 @@ lf_status lf_depth(const lf_view_set* views, const float* hyp, int32_t N,
                    size_t ws_bytes, hipStream_t stream);
 
 
+/* lf_depth for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same method
+ * and the same results as lf_depth, with the workspace taken from a static device
+ * array of LF_NOALLOC_SCRATCH_BYTES (64 MiB) that the library holds on every GPU it
+ * runs on until the process ends.  The caller still passes the inputs and outputs.
+ * A light field whose lf_depth_workspace_size exceeds that returns LF_ENOSPACE
+ * (nothing enqueued).  The array's address is resolved on the first call on each
+ * device, with that device current; `stream` must belong to the current device.
+ * All calls on one GPU share its array: calls that overlap in time on one GPU
+ * (different streams, or different host threads) race and give undefined results;
+ * calls ordered on one stream are safe.  No device memory is allocated or freed. */
+#define LF_NOALLOC_SCRATCH_BYTES (64u << 20)
+lf_status lf_depth_noalloc(const lf_view_set* views, const float* hyp, int32_t N,
+                           const lf_params* prm, float* disparity, int16_t* d_index,
+                           hipStream_t stream);
+
 /* ------------------------------------------------------------- batches
  * Many light fields of uneven resolution, view count and hypothesis range run
  * together: every stage of the method is ONE grouped launch over all of them

@@ -709,6 +709,58 @@ lf_status lf_depth(const lf_view_set* views, const float* hyp, int32_t N, const 
 
 }  // extern "C"
 
+// --- lf_depth without a caller workspace --------------------------------------------
+// The workspace lives in this file-scope device array.  Its name in host code is a
+// host-side stand-in, not a device address: the address of each device's copy is
+// taken once per device with hipGetSymbolAddress (with that device current) and
+// only that address is handed to kernels.  No part of the workspace has to start
+// at zero: every byte lf_depth reads is written earlier in the same call, except
+// the slack past the last initial path-cost row, which is read and discarded.
+namespace {
+
+__device__ __align__(256) uint8_t scratch[LF_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices] = {};
+
+// The current device's copy of `scratch`, resolved on its first use.
+lf_status scratch_address(void** out) {
+    int dev = -1;
+    if (hipError_t e = hipGetDevice(&dev); e != hipSuccess) return device_status(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(LF_EUNSUPPORTED, "device %d", dev);
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* ptr = nullptr;
+        if (hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)); e != hipSuccess)
+            return device_status(e, "hipGetSymbolAddress(scratch)");
+        if (!ptr || (uintptr_t)ptr % kAlign) return fail(LF_EDEVICE, "scratch address %p", ptr);
+        g_scratch[dev] = ptr;
+    }
+    *out = g_scratch[dev];
+    return LF_OK;
+}
+
+}  // namespace
+
+extern "C" lf_status lf_depth_noalloc(const lf_view_set* views, const float* hyp, int32_t N,
+                                      const lf_params* prm, float* disparity, int16_t* d_index,
+                                      hipStream_t stream) {
+    LF_CHECK(check_views(views));
+    LF_CHECK(check_shape(views->S, views->T, views->H, views->W, N));
+    LF_CHECK(check_params(prm));
+    const size_t need = plan_depth(nullptr, views->S, views->T, channels_of(views), views->H,
+                                   views->W, N, prm, nullptr);
+    if (need > (size_t)LF_NOALLOC_SCRATCH_BYTES)
+        return fail(LF_ENOSPACE,
+                    "light field needs %zu bytes of workspace; lf_depth_noalloc holds %zu "
+                    "(use lf_depth with a caller workspace)",
+                    need, (size_t)LF_NOALLOC_SCRATCH_BYTES);
+    void* ws = nullptr;
+    LF_CHECK(scratch_address(&ws));
+    return lf_depth(views, hyp, N, prm, disparity, d_index, ws, LF_NOALLOC_SCRATCH_BYTES, stream);
+}
+
 // --- used by the batch plan and the request loop ----------------------------------
 namespace lf {
 

@@ -27,7 +27,7 @@ EXPORTS = (
     "lf_cost_workspace_size", "lf_cost_volume_bounded", "lf_sgm_workspace_size",
     "lf_sgm_aggregate",
     "lf_wta_workspace_size", "lf_wta_subpixel", "lf_depth_workspace_size", "lf_depth",
-    "lf_profile_enable", "lf_profile_read", "lf_profile_stage_name",
+    "lf_depth_noalloc", "lf_profile_enable", "lf_profile_read", "lf_profile_stage_name",
     "lf_batch_workspace_size", "lf_plan_create", "lf_plan_autotune", "lf_plan_capture",
     "lf_plan_run", "lf_plan_launches", "lf_plan_tuning", "lf_plan_destroy",
     "lf_server_create", "lf_server_submit", "lf_server_wait", "lf_server_stats",
@@ -110,6 +110,7 @@ def _load():
     lib.lf_wta_subpixel.argtypes = [P, i32, P, P, P, i32, i32, P, i32, i32, P, P, P, sz, P]
     lib.lf_depth_workspace_size.argtypes = [i32, i32, i32, i32, i32, i32, P]
     lib.lf_depth.argtypes = [P, P, i32, P, P, P, P, sz, P]
+    lib.lf_depth_noalloc.argtypes = [P, P, i32, P, P, P, P]
     lib.lf_validate_hypotheses.argtypes = [P, i32]
     lib.lf_cost_cap.argtypes = [i32, i32, i32]
     lib.lf_cross_views.argtypes = [i32, i32, P]
@@ -354,6 +355,22 @@ def lf_depth(views: torch.Tensor, hyp: torch.Tensor, params: dict, ws=None, out=
                                                    C.byref(prm)), dev)
     _check(lib.lf_depth(C.byref(vs), _ptr(hyp), N, C.byref(prm), _ptr(out), _ptr(d_index),
                         _ptr(ws), ws.numel(), _stream(stream)))
+    return out
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20      # LF_NOALLOC_SCRATCH_BYTES
+
+
+def lf_depth_noalloc(views: torch.Tensor, hyp: torch.Tensor, params: dict, out=None,
+                     d_index=None, stream=None):
+    """lf_depth with the library's static device workspace (no caller workspace)."""
+    vs = view_set(views)
+    prm = make_params(params)
+    _dev(hyp, torch.float32, "hyp")
+    if out is None:
+        out = torch.empty((vs.H, vs.W), dtype=torch.float32, device=views.device)
+    _check(lib.lf_depth_noalloc(C.byref(vs), _ptr(hyp), hyp.shape[0], C.byref(prm), _ptr(out),
+                                _ptr(d_index), _stream(stream)))
     return out
 
 
