@@ -305,12 +305,16 @@ typedef struct {
  * or 16 (default) -- path steps of cost loads in flight per wave in the initial
  * SGM, also the steps whose path costs it stages before copying them out;
  * bounded_prefetch: 4, 8 or 16 (default) -- pixel metadata steps in flight
- * per wave in the bounded SGM (their costs run half as many steps ahead). */
+ * per wave in the bounded SGM with 64 lanes per line (their costs run half as
+ * many steps ahead); bounded_lanes: 16, 32 or 64 (default) -- lanes per path line
+ * of the bounded SGM (the wavefront-to-path schedule: 64/bounded_lanes lines per
+ * wave, a line's range covered in chunks of that many hypotheses). */
 typedef struct {
     int32_t cost_cells_per_thread;
     int32_t cost_stride;
     int32_t dense_prefetch;
     int32_t bounded_prefetch;
+    int32_t bounded_lanes;
 } lf_tuning;
 
 typedef struct lf_plan lf_plan;

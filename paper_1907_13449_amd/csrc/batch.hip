@@ -36,11 +36,12 @@ lf::Tuning to_tuning(const lf_tuning* t) {
     if (t->cost_stride) u.cost_stride = t->cost_stride;
     if (t->dense_prefetch) u.dense_depth = t->dense_prefetch;
     if (t->bounded_prefetch) u.bounded_depth = t->bounded_prefetch;
+    if (t->bounded_lanes) u.bounded_lanes = t->bounded_lanes;
     return u;
 }
 
 lf_tuning from_tuning(const lf::Tuning& u) {
-    return lf_tuning{u.cost_cpt, u.cost_stride, u.dense_depth, u.bounded_depth};
+    return lf_tuning{u.cost_cpt, u.cost_stride, u.dense_depth, u.bounded_depth, u.bounded_lanes};
 }
 
 bool valid_tuning(const lf::Tuning& u) {
@@ -48,7 +49,8 @@ bool valid_tuning(const lf::Tuning& u) {
         return std::find(ok.begin(), ok.end(), v) != ok.end();
     };
     return in(u.cost_cpt, {2, 4, 8}) && in(u.cost_stride, {1, 2, 4}) &&
-           in(u.dense_depth, {4, 8, 16}) && in(u.bounded_depth, {4, 8, 16});
+           in(u.dense_depth, {4, 8, 16}) && in(u.bounded_depth, {4, 8, 16}) &&
+           in(u.bounded_lanes, {16, 32, 64});
 }
 
 }  // namespace
@@ -226,7 +228,7 @@ lf_status lf_plan_autotune(lf_plan* p, hipStream_t stream, int32_t reps, lf_tuni
     };
     // Phase 1: candidate i takes the i-th value of every list; the stages are
     // timed separately, so each stage's parameter is chosen on its own.
-    const int cpt[3] = {2, 4, 8}, dd[3] = {4, 8, 16}, bd[3] = {8, 16, 16};
+    const int cpt[3] = {2, 4, 8}, dd[3] = {4, 8, 16}, bl[3] = {16, 32, 64};
     double best_cost = 1e30, best_dense = 1e30, best_bounded = 1e30;
     lf::Tuning best = p->tune;
     best.cost_stride = 1;
@@ -236,14 +238,15 @@ lf_status lf_plan_autotune(lf_plan* p, hipStream_t stream, int32_t reps, lf_tuni
         t.cost_cpt = cpt[i];
         t.cost_stride = 1;
         t.dense_depth = dd[i];
-        t.bounded_depth = bd[i];
+        t.bounded_lanes = bl[i];
+        t.bounded_depth = 16;
         double ms[lf::kNumStages];
         if ((s = measure(t, ms)) != LF_OK) break;
         if (ms[lf::kStCost] < best_cost) best_cost = ms[lf::kStCost], best.cost_cpt = cpt[i];
         if (ms[lf::kStInitPaths] < best_dense)
             best_dense = ms[lf::kStInitPaths], best.dense_depth = dd[i];
         if (ms[lf::kStSgmFinal] < best_bounded)
-            best_bounded = ms[lf::kStSgmFinal], best.bounded_depth = bd[i];
+            best_bounded = ms[lf::kStSgmFinal], best.bounded_lanes = bl[i];
     }
     // Phase 2: workgroups walking several cost slices, at the chosen slice size.
     for (int stride : {2, 4}) {

@@ -121,6 +121,10 @@ __device__ __forceinline__ LineInfo locate(const Lines& L, int H, int W, int g) 
 
 constexpr int kWavesPerBlock = 4;
 
+size_t round256(size_t x) { return (x + 255) / 256 * 256; }
+
+uint32_t div_up(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
+
 // Copies a wave-uniform value into a VGPR that the compiler treats as divergent.
 // Loads addressed through it stay vector-memory loads, which complete in order,
 // so a wave can keep several steps of them in flight and wait for the oldest
@@ -651,7 +655,7 @@ struct MetaArgs {
     const int16_t* lo;
     const int16_t* hi;
     PixMeta* meta;
-    int HW;
+    int HW, N;
 };
 
 template <class Src>
@@ -661,9 +665,12 @@ __global__ __launch_bounds__(256) void pix_meta_kernel(Src src) {
         const MetaArgs& a = member(src, vb, b);
         const int p = (int)b * 256 + threadIdx.x;
         if (p >= a.HW) continue;
+        // bounds outside the documented 0 <= lo <= hi < N are clamped into it; that
+        // only narrows a range, so its cells stay within the pixel's own
+        const int lo = clampi(a.lo[p], 0, a.N - 1), hi = clampi(a.hi[p], lo, a.N - 1);
         PixMeta m;
-        m.base = a.off[p] - a.lo[p];
-        m.lohi = (int32_t)((uint16_t)a.lo[p] | ((uint32_t)(uint16_t)a.hi[p] << 16));
+        m.base = a.off[p] - lo;
+        m.lohi = (int32_t)((uint32_t)lo | ((uint32_t)hi << 16));
         m.pad = 0;
         a.meta[p] = m;
     }
@@ -675,7 +682,7 @@ struct BoundedArgs {
     uint16_t* Lbuf;           // [npaths][dir_stride]
     size_t dir_stride;
     Lines lines;
-    int H, W;
+    int H, W, N;
     uint32_t P1, P2;
 };
 
@@ -758,6 +765,143 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void sgm_bounded_paths_kernel(
         uint32_t b;
         const BoundedArgs& a = member(src, vb, b);
         bounded_wave<K, D>(a, b);
+    }
+}
+
+// The bounded SGM with G lanes per path line (G = 16 or 32: 64/G lines per wave).
+// Most pixels keep a window of 2*lambda+1 hypotheses, so one wave per line
+// leaves most lanes idle; here a line's G lanes cover its pixel's range in
+// chunks of G hypotheses (one chunk for a narrow window, ceil(N/G) for a
+// full-range pixel), lane j of chunk c holding k = lo + G*c + j.
+//
+// A pixel's range need not overlap its predecessor's, so the previous path costs
+// are kept by hypothesis index, not by lane: each line has two LDS rows of N + 2
+// entries (k = -1 .. N), written on alternate steps.  An entry holds the path
+// cost in its low 16 bits and the step that wrote it in the high 16 bits; at
+// step s the predecessor's entries are those tagged s - 1, and subtracting
+// (s-1) << 16 leaves their value while every other entry (older steps, never
+// written) becomes >= 65536, which loses to m + P2 <= 65535 and does not wrap
+// when P1 is added (path costs <= cap + P2 <= 65535 - P2).  So the terms of
+// Eq. (8) outside R(p - r) are omitted without clearing anything.  m, the
+// minimum over R(p - r), is the row minimum of the previous step's costs.
+constexpr int kB16Waves = 4;                      // waves per workgroup
+
+// Entries of one LDS row: N + 2, padded so that the rows of the lines of a wave
+// (two per line) start on different banks.
+__host__ __device__ constexpr int b16_row(int N) { return (N + 2 + 15) / 16 * 16 + 8; }
+
+// Minimum over each group of G lanes (G = 16: a DPP row; 32: two rows), in
+// every lane of the group.
+template <int G>
+__device__ __forceinline__ uint32_t group_min(uint32_t v) {
+    v = min(v, dpp<0xB1>(UINT_MAX, v));           // quad_perm [1,0,3,2]
+    v = min(v, dpp<0x4E>(UINT_MAX, v));           // quad_perm [2,3,0,1]
+    v = min(v, dpp<0x141>(UINT_MAX, v));          // row_half_mirror
+    v = min(v, dpp<0x140>(UINT_MAX, v));          // row_mirror: the row's minimum
+    if constexpr (G == 32)                        // swap the rows of each 32-lane half
+        v = min(v, (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x401F));
+    return v;
+}
+
+template <int G, int KC, int DM, int DC>
+__device__ __forceinline__ void bounded_group_wave(const BoundedArgs& a, uint32_t b,
+                                                   uint32_t* lds) {
+    constexpr int kLines = 64 / G;                // lines per wave
+    const int lane = threadIdx.x & 63, sub = lane & (G - 1), grp = lane / G;
+    const int wave = threadIdx.x >> 6;
+    const int H = a.H, W = a.W, N = a.N;
+    const uint32_t P1 = a.P1, P2 = a.P2;
+    const int g = ((int)b * kB16Waves + wave) * kLines + grp;   // this group's line
+    const int nlines = a.lines.base[a.lines.npaths];
+    LineInfo li{0, 0, 0, 0, 0, 0};
+    if (g < nlines) li = locate(a.lines, H, W, g);
+    // steps: the longest line of the wave (wave-uniform)
+    int steps = 0;
+#pragma unroll
+    for (int i = 0; i < kLines; ++i) steps = max(steps, __builtin_amdgcn_readlane(li.len, i * G));
+    if (steps == 0) return;
+    const int RP = b16_row(N);
+    uint32_t* const row0 = lds + (size_t)(wave * kLines + grp) * 2 * RP;
+    for (int i = sub; i < 2 * RP; i += G) row0[i] = 0xFFFF0000u;     // no step wrote it
+    const PixMeta* __restrict__ meta = a.meta;
+    const uint16_t* __restrict__ cost = a.cost;
+    uint16_t* __restrict__ out = a.Lbuf + (size_t)li.r * a.dir_stride;
+    const int last = max(li.len - 1, 0);
+    auto pix = [&](int step) {                    // steps past the line repeat its end
+        const int st = min(step, last);
+        return (uint32_t)((li.v0 + st * li.dv) * W + li.u0 + st * li.du);
+    };
+    PixMeta mb[DM];
+    uint32_t cb[DC][KC];
+    auto load_costs = [&](const PixMeta& pm, uint32_t (&c)[KC]) {
+        const int lo = pm.lohi & 0xFFFF, hi = pm.lohi >> 16;
+#pragma unroll
+        for (int j = 0; j < KC; ++j) {
+            const int k = lo + G * j + sub;
+            c[j] = k <= hi ? (uint32_t)cost[pm.base + k] : 0u;
+        }
+    };
+#pragma unroll
+    for (int i = 0; i < DM; ++i) mb[i] = meta[in_vgpr(pix(i))];
+#pragma unroll
+    for (int i = 0; i < DC; ++i) load_costs(mb[i], cb[i]);
+
+    uint32_t m = 0;
+    for (int base = 0; base < steps; base += DM) {
+#pragma unroll
+        for (int i = 0; i < DM; ++i) {
+            const int step = base + i;            // wave-uniform
+            const PixMeta pm = mb[i];
+            const int lo = pm.lohi & 0xFFFF, hi = pm.lohi >> 16;
+            uint32_t C[KC];
+#pragma unroll
+            for (int j = 0; j < KC; ++j) C[j] = cb[i % DC][j];
+            // refill: the costs of step + DC (its meta arrived DM - DC steps ago),
+            // then the meta of step + DM
+            load_costs(mb[(i + DC) % DM], cb[i % DC]);
+            mb[i] = meta[in_vgpr(pix(step + DM))];
+            const bool live = step < li.len;
+            uint32_t* const prev = row0 + ((step + 1) & 1) * RP;    // written at step - 1
+            uint32_t* const cur = row0 + (step & 1) * RP;
+            const uint32_t tag = (uint32_t)(step - 1) << 16;
+            const uint32_t mP2 = m + P2;
+            uint32_t rmin = UINT_MAX;
+#pragma unroll
+            for (int j = 0; j < KC; ++j) {
+                const int k = lo + G * j + sub;
+                if (k <= hi) {
+                    uint32_t L;
+                    if (step == 0) {
+                        L = C[j];
+                    } else {
+                        const uint32_t e0 = prev[k + 1] - tag;      // k
+                        const uint32_t em = prev[k] - tag;          // k - 1
+                        const uint32_t ep = prev[k + 2] - tag;      // k + 1
+                        const uint32_t t = min(min(e0, min(em, ep) + P1), mP2);
+                        L = t + C[j] - m;
+                    }
+                    cur[k + 1] = L | ((uint32_t)step << 16);
+                    if (live) out[pm.base + k] = (uint16_t)L;
+                    rmin = min(rmin, L);
+                }
+            }
+            m = group_min<G>(rmin);
+            // the next step reads what the other lanes of this wave wrote
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+    }
+}
+
+template <class Src, int G, int KC>
+__global__ __launch_bounds__(64 * kB16Waves) void sgm_bounded_group_kernel(Src src) {
+    __shared__ uint32_t lds[kB16Waves * (64 / G) * 2 * b16_row(KC * G)];
+    for (uint32_t vb = blockIdx.x; vb < src.total; vb += gridDim.x) {
+        uint32_t b;
+        const BoundedArgs& a = member(src, vb, b);
+        __syncthreads();                          // the previous block's rows are done
+        bounded_group_wave<G, KC, 8, 4>(a, b, lds);
     }
 }
 
@@ -852,6 +996,47 @@ hipError_t bounded_variant(Runner& r, const std::vector<BoundedArgs>& args,
                   64 * kWavesPerBlock);
 }
 
+template <int G, int KC>
+hipError_t bounded_group_variant(Runner& r, const std::vector<BoundedArgs>& args) {
+    std::vector<uint32_t> blocks;
+    for (const BoundedArgs& a : args)
+        blocks.push_back(div_up(a.lines.base[a.lines.npaths], kB16Waves * (64 / G)));
+    return launch(r, kStSgmFinal, sgm_bounded_group_kernel<Single<BoundedArgs>, G, KC>,
+                  sgm_bounded_group_kernel<Group<BoundedArgs>, G, KC>, args, blocks,
+                  64 * kB16Waves);
+}
+
+// Chunks per line (hypotheses / G) rounded up to the compiled variants.
+int bounded_chunks(int N, int G) {
+    const int c = (N + G - 1) / G;
+    if (G == 16) {
+        for (int v : {2, 4, 7, 10, 13}) if (c <= v) return v;
+        return 16;
+    }
+    for (int v : {1, 2, 4, 6}) if (c <= v) return v;
+    return 8;
+}
+
+hipError_t bounded_group(Runner& r, int G, int KC, const std::vector<BoundedArgs>& args) {
+    if (G == 16) {
+        switch (KC) {
+            case 2: return bounded_group_variant<16, 2>(r, args);
+            case 4: return bounded_group_variant<16, 4>(r, args);
+            case 7: return bounded_group_variant<16, 7>(r, args);
+            case 10: return bounded_group_variant<16, 10>(r, args);
+            case 13: return bounded_group_variant<16, 13>(r, args);
+            default: return bounded_group_variant<16, 16>(r, args);
+        }
+    }
+    switch (KC) {
+        case 1: return bounded_group_variant<32, 1>(r, args);
+        case 2: return bounded_group_variant<32, 2>(r, args);
+        case 4: return bounded_group_variant<32, 4>(r, args);
+        case 6: return bounded_group_variant<32, 6>(r, args);
+        default: return bounded_group_variant<32, 8>(r, args);
+    }
+}
+
 hipError_t bounded_k(Runner& r, int K, const std::vector<BoundedArgs>& args,
                      const std::vector<uint32_t>& blocks) {
     switch (K) {
@@ -862,9 +1047,6 @@ hipError_t bounded_k(Runner& r, int K, const std::vector<BoundedArgs>& args,
     }
 }
 
-size_t round256(size_t x) { return (x + 255) / 256 * 256; }
-
-uint32_t div_up(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
 
 }  // namespace
 
@@ -1047,6 +1229,9 @@ hipError_t stage_sgm_final(Runner& r, const Jobs& jobs) {
     std::vector<uint32_t> meta_blocks;
     std::vector<BoundedArgs> paths[4];
     std::vector<uint32_t> path_blocks[4];
+    // G lanes per line: [chunks per line] of the compiled variants (at most 16)
+    const int G = r.tune.bounded_lanes;
+    std::vector<BoundedArgs> grouped[17];
     std::vector<BsumArgs> sums[2][2];              // [16/32-bit sums][8/16 paths]
     std::vector<uint32_t> sum_blocks[2][2];
     for (const Job* j : jobs) {
@@ -1057,7 +1242,7 @@ hipError_t stage_sgm_final(Runner& r, const Jobs& jobs) {
         uint16_t* Lbuf = (uint16_t*)((char*)j->sgm_ws + round256(HW * sizeof(PixMeta)));
         const size_t dir_stride = HW * N;          // worst-case cells per direction
 
-        meta.push_back(MetaArgs{j->offsets, j->lo, j->hi, pm, (int)HW});
+        meta.push_back(MetaArgs{j->offsets, j->lo, j->hi, pm, (int)HW, N});
         meta_blocks.push_back(div_up(HW, 256));
 
         BoundedArgs b{};
@@ -1068,11 +1253,16 @@ hipError_t stage_sgm_final(Runner& r, const Jobs& jobs) {
         b.lines = make_lines(H, W, sp.npaths);
         b.H = H;
         b.W = W;
+        b.N = N;
         b.P1 = (uint32_t)sp.P1;
         b.P2 = (uint32_t)sp.P2;
-        const int K = (N + 63) / 64 - 1;
-        paths[K].push_back(b);
-        path_blocks[K].push_back(div_up(b.lines.base[b.lines.npaths], kWavesPerBlock));
+        if (G == 16 || G == 32) {
+            grouped[bounded_chunks(N, G)].push_back(b);
+        } else {
+            const int K = (N + 63) / 64 - 1;
+            paths[K].push_back(b);
+            path_blocks[K].push_back(div_up(b.lines.base[b.lines.npaths], kWavesPerBlock));
+        }
 
         BsumArgs s{};
         s.Lbuf = Lbuf;
@@ -1092,6 +1282,10 @@ hipError_t stage_sgm_final(Runner& r, const Jobs& jobs) {
         if (paths[K].empty()) continue;
         e = bounded_k(r, K + 1, paths[K], path_blocks[K]);
         if (e != hipSuccess) return e;
+    }
+    for (int c = 1; c <= 16; ++c) {
+        if (grouped[c].empty()) continue;
+        if ((e = bounded_group(r, G, c, grouped[c])) != hipSuccess) return e;
     }
     using BA = BsumArgs;
     if (!sums[0][0].empty() &&

@@ -102,12 +102,14 @@ def test_batch_equals_alone(lf, items):
 
 
 @pytest.mark.parametrize("tuning", [
-    dict(cost_cells_per_thread=2, dense_prefetch=4, bounded_prefetch=4),
-    dict(cost_cells_per_thread=8, cost_stride=4, dense_prefetch=16, bounded_prefetch=8),
-    dict(cost_cells_per_thread=4, cost_stride=2, dense_prefetch=8),
+    dict(cost_cells_per_thread=2, dense_prefetch=4, bounded_prefetch=4, bounded_lanes=64),
+    dict(cost_cells_per_thread=8, cost_stride=4, dense_prefetch=16, bounded_prefetch=8,
+         bounded_lanes=64),
+    dict(cost_cells_per_thread=4, cost_stride=2, dense_prefetch=8, bounded_lanes=32),
+    dict(bounded_lanes=16),
 ])
 def test_batch_every_tuning(lf, items, tuning):
-    order = [3, 0, 1, 1, 9, 2]                       # repeats and a shuffled order
+    order = [3, 0, 1, 1, 9, 2, 10, 25, 23, 13]       # repeats and a shuffled order
     outs = _outputs(items, order)
     say("tuning", tuning)
     plan = _plan(lf, items, order, outs, tuning)
@@ -152,6 +154,7 @@ def test_autotune_keeps_results(lf, items):
     assert chosen["cost_stride"] in (1, 2, 4)
     assert chosen["dense_prefetch"] in (4, 8, 16)
     assert chosen["bounded_prefetch"] in (4, 8, 16)
+    assert chosen["bounded_lanes"] in (16, 32, 64)
     assert plan.tuning == chosen
     torch.cuda.synchronize()
     _check(items, order, outs)
