@@ -135,6 +135,8 @@ lf_status check_shape(int S, int T, int H, int W, int N) {
     if (S < 1 || T < 1 || S % 2 == 0 || T % 2 == 0)
         return fail(LF_EINVAL, "angular grid %dx%d: S and T must be odd and >= 1", S, T);
     if (S * T < 2) return fail(LF_EINVAL, "a light field needs at least 2 views");
+    if (S > 65535 || T > 65535)
+        return fail(LF_EUNSUPPORTED, "angular grid %dx%d (at most 65535 per side)", S, T);
     if (H < 1 || W < 1) return fail(LF_EINVAL, "image size %dx%d", H, W);
     if ((int64_t)H * W > (1 << 30) || H > LF_MAX_SIDE || W > LF_MAX_SIDE)
         return fail(LF_EUNSUPPORTED, "image of %d x %d pixels", H, W);

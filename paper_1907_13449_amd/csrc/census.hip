@@ -14,13 +14,13 @@ constexpr int kBX = 32, kBY = 8;
 // Up to kMaxBatchImages images of one size; image z starts at base + off[z]
 // elements, or at base + z * stride when n > kMaxBatchImages.
 struct CensusArgs {
-    const void* base;
+    gptr<const void> base;
     int64_t off[kMaxBatchImages];
     int64_t stride;
     int n;
     int H, W, pitch, win_h, win_w;
     int bx, by;               // tiles along x and y
-    uint64_t* out;            // [n][H*W]
+    gptr<uint64_t> out;            // [n][H*W]
 };
 
 // The bit string of one pixel from its window in the LDS tile (win points at the
@@ -70,7 +70,7 @@ __device__ __forceinline__ void census_block(const CensusArgs& a, uint32_t b, fl
     const int by = rem / a.bx, bx = rem - by * a.bx;
     const int H = a.H, W = a.W;
     const int64_t off = a.n > kMaxBatchImages ? (int64_t)z * a.stride : a.off[z];
-    const T* __restrict__ img = reinterpret_cast<const T*>(a.base) + off;
+    const T* __restrict__ img = (const T*)(a.base) + off;
     uint64_t* __restrict__ dst = a.out + (size_t)z * H * W;
 
     const int rh = (WH > 0 ? WH : a.win_h) / 2, rw = (WW > 0 ? WW : a.win_w) / 2;
@@ -99,7 +99,7 @@ __global__ __launch_bounds__(256) void census_kernel(Src src) {
     __shared__ float tile[(kBY + 2 * kMaxCensusRadius) * (kBX + 2 * kMaxCensusRadius)];
     for (uint32_t vb = blockIdx.x; vb < src.total; vb += gridDim.x) {
         uint32_t b;
-        const CensusArgs& a = member(src, vb, b);
+        const CensusArgs& a = member_ref(src, vb, b);   // off[] is indexed by image
         __syncthreads();                          // the tile of the previous block is read
         census_block<T, WH, WW>(a, b, tile);
     }

@@ -81,8 +81,8 @@ constexpr int kPadL = kGroup, kPadT = 1;
 static_assert(kPadW == 2 * kGroup && kPadH == 2, "view copy margins");
 
 struct PadArgs {
-    const void* src;          // [planes][H][pitch] (a view is C planes)
-    void* dst;                // [planes][H + 2][W + 2 kGroup]
+    gptr<const void> src;          // [planes][H][pitch] (a view is C planes)
+    gptr<void> dst;                // [planes][H + 2][W + 2 kGroup]
     int H, W, pitch;
 };
 
@@ -129,12 +129,12 @@ __global__ __launch_bounds__(kThreads) void pad_views_kernel(Src src) {
 }
 
 struct L2Args {
-    const void* views;        // padded: [T][S][C][H + 2][W + 2 kGroup]
-    const float* hyp;
-    const int16_t* lo;
-    const int64_t* off;       // [H*W + 1]
-    uint16_t* cost;
-    float* cost_f32;          // nullable
+    gptr<const void> views;        // padded: [T][S][C][H + 2][W + 2 kGroup]
+    gptr<const float> hyp;
+    gptr<const int16_t> lo;
+    gptr<const int64_t> off;       // [H*W + 1]
+    gptr<uint16_t> cost;
+    gptr<float> cost_f32;          // nullable
     int64_t cap_cells;
     int S, T, H, W, N;
     float alpha, cap;
@@ -470,12 +470,12 @@ __global__ __launch_bounds__(kThreads) void cost_l2_kernel(Src src) {
 // Census kind, Eq. (15): 64 pixels per workgroup, their cells strided over the
 // threads.
 struct CensusAllArgs {
-    const uint64_t* census;   // [S*T][C][H*W]
-    const float* hyp;
-    const int16_t* lo;
-    const int64_t* off;
-    uint16_t* cost;
-    float* cost_f32;
+    gptr<const uint64_t> census;   // [S*T][C][H*W]
+    gptr<const float> hyp;
+    gptr<const int16_t> lo;
+    gptr<const int64_t> off;
+    gptr<uint16_t> cost;
+    gptr<float> cost_f32;
     int64_t cap_cells;
     int S, T, C, H, W, N;
     uint32_t cap;

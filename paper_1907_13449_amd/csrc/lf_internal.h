@@ -21,7 +21,33 @@
 
 #include "../../include/lf.h"
 
+// Pointer fields of the kernels' argument records point into device memory.  On
+// the device they convert to pointers in the global address space: a kernel that
+// reads its record from a batch plan's table (not from its kernel arguments)
+// would otherwise access memory with flat instructions, which count against both
+// the vector-memory and the LDS wait counters (every LDS wait would then also wait
+// for the stores in flight).  gptr<T> has the layout of a plain pointer.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define LF_GLOBAL __attribute__((address_space(1)))
+#else
+#define LF_GLOBAL
+#endif
+
 namespace lf {
+
+template <class T>
+struct gptr {
+    union {
+        T* p;                 // as the host writes it
+        LF_GLOBAL T* g;       // as the device reads it: no generic-to-global cast
+    };                        // that the compiler could fold away
+    gptr() = default;
+    __host__ __device__ gptr(T* q) : p(q) {}
+    __device__ operator LF_GLOBAL T*() const { return g; }
+    // explicit casts to another element type keep the address space visible
+    template <class U>
+    __device__ explicit operator U*() const { return (U*)g; }
+};
 
 constexpr uint32_t kInf = 0x3FFFFFFFu;   // +inf of the SGM path recurrences
 constexpr int kMaxCensusRadius = 7;      // windows up to 15 x 15
@@ -46,21 +72,59 @@ template <class A> struct Group {
     uint32_t total;
 };
 
+// The argument record of virtual block vb, returned by value: a kernel keeps it in
+// registers, where global stores cannot invalidate it (read through a pointer
+// into the device table, every field would have to be re-read after each store
+// that might alias it).  Records are indexed with constant indices only.
 template <class A>
-__device__ __forceinline__ const A& member(const Single<A>& s, uint32_t vb, uint32_t& local) {
+__device__ __forceinline__ A member(const Single<A>& s, uint32_t vb, uint32_t& local) {
+    local = vb;
+    return s.a;
+}
+
+// A plan's launch tables are written before its launches and never by a kernel:
+// they are read through the constant address space, so that the reads are scalar
+// loads the compiler may keep (through a plain global pointer, a store anywhere in
+// the kernel would make every later read of the table a vector load).
+template <class T>
+__device__ __forceinline__ const __attribute__((address_space(4))) T* table_ptr(const T* p) {
+    return (const __attribute__((address_space(4))) T*)p;
+}
+
+template <class A>
+__device__ __forceinline__ int group_member(const Group<A>& g, uint32_t vb, uint32_t& local) {
+    const auto* prefix = table_ptr(g.prefix);
+    int lo = 0, hi = g.n;                     // prefix[lo] <= vb < prefix[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (prefix[mid] <= vb) lo = mid; else hi = mid;
+    }
+    local = vb - prefix[lo];
+    return lo;
+}
+
+template <class A>
+__device__ __forceinline__ A member(const Group<A>& g, uint32_t vb, uint32_t& local) {
+    static_assert(sizeof(A) % 4 == 0, "records are copied in 32-bit words");
+    const auto* src = table_ptr((const uint32_t*)(g.a + group_member(g, vb, local)));
+    A out;
+    uint32_t* dst = (uint32_t*)&out;
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(A) / 4); ++i) dst[i] = src[i];
+    return out;
+}
+
+// The record read in place (kernel arguments or the device table), for records
+// with tables a kernel indexes at run time, which a register copy cannot hold.
+template <class A>
+__device__ __forceinline__ const A& member_ref(const Single<A>& s, uint32_t vb, uint32_t& local) {
     local = vb;
     return s.a;
 }
 
 template <class A>
-__device__ __forceinline__ const A& member(const Group<A>& g, uint32_t vb, uint32_t& local) {
-    int lo = 0, hi = g.n;                     // prefix[lo] <= vb < prefix[hi]
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (g.prefix[mid] <= vb) lo = mid; else hi = mid;
-    }
-    local = vb - g.prefix[lo];
-    return g.a[lo];
+__device__ __forceinline__ const A& member_ref(const Group<A>& g, uint32_t vb, uint32_t& local) {
+    return g.a[group_member(g, vb, local)];
 }
 
 // Tunable schedule parameters.  None of them changes a result.

@@ -14,8 +14,8 @@ uint32_t blocks_for(int64_t n) { return (uint32_t)((n + kThreads - 1) / kThreads
 
 // --- fusion with confidence threshold phi (Sec. 3.4) -----------------------
 struct FuseArgs {
-    const int16_t* maps;      // [nv][HW]
-    int16_t* dinit;
+    gptr<const int16_t> maps;      // [nv][HW]
+    gptr<int16_t> dinit;
     int nv, HW, phi;
 };
 
@@ -45,8 +45,8 @@ __global__ __launch_bounds__(kThreads) void fuse_kernel(Src src) {
 
 // --- one median hole-filling pass: lower median of the valid 8-neighbours ---
 struct FillArgs {
-    const int16_t* in;
-    int16_t* out;
+    gptr<const int16_t> in;
+    gptr<int16_t> out;
     int H, W;
 };
 
@@ -103,10 +103,10 @@ __global__ __launch_bounds__(kThreads) void fill_kernel(Src src) {
 
 // --- Sobel edge exclusion and borders, Eq. (11) -----------------------------
 struct BordersArgs {
-    const int16_t* dinit;
-    const void* ref;          // C planes of H x pitch
-    int16_t* lo;
-    int16_t* hi;
+    gptr<const int16_t> dinit;
+    gptr<const void> ref;          // C planes of H x pitch
+    gptr<int16_t> lo;
+    gptr<int16_t> hi;
     int pitch, H, W, N, lambda, lambda_far, C;
     float alpha, tau;
 };
@@ -272,8 +272,8 @@ __global__ __launch_bounds__(kThreads) void prep_kernel(Src src) {
 
 // --- boundary-less search (Sec. 4.5): every pixel keeps the full range -------
 struct FullArgs {
-    int16_t* lo;
-    int16_t* hi;
+    gptr<int16_t> lo;
+    gptr<int16_t> hi;
     int HW, N;
 };
 
@@ -296,10 +296,10 @@ constexpr int kScanPerThread = 8;
 constexpr int kScanTile = kThreads * kScanPerThread;
 
 struct ScanArgs {
-    const int16_t* lo;
-    const int16_t* hi;
-    int64_t* bsum;            // [nb]: tile totals
-    int64_t* offsets;         // [HW + 1]
+    gptr<const int16_t> lo;
+    gptr<const int16_t> hi;
+    gptr<int64_t> bsum;            // [nb]: tile totals
+    gptr<int64_t> offsets;         // [HW + 1]
     int64_t HW;
     int nb;
 };
@@ -373,13 +373,13 @@ __global__ __launch_bounds__(kThreads) void scan_apply_kernel(Src src) {
 
 // --- WTA (Eq. 10) and the parabola sub-pixel step (Sec. 3.6) ----------------
 struct WtaArgs {
-    const void* csum;
-    const int64_t* off;
-    const int16_t* lo;
-    const int16_t* hi;
-    const float* hyp;
-    int16_t* d_index;
-    float* disp;
+    gptr<const void> csum;
+    gptr<const int64_t> off;
+    gptr<const int16_t> lo;
+    gptr<const int16_t> hi;
+    gptr<const float> hyp;
+    gptr<int16_t> d_index;
+    gptr<float> disp;
     int HW, N;
 };
 
@@ -428,8 +428,8 @@ __global__ __launch_bounds__(kThreads) void wta_subpixel_kernel(Src src) {
 
 // --- 3x3 median, clamp-to-edge ----------------------------------------------
 struct MedianArgs {
-    const float* in;
-    float* out;
+    gptr<const float> in;
+    gptr<float> out;
     int H, W;
 };
 

@@ -66,11 +66,11 @@ __host__ __device__ inline int num_lines(int H, int W, int du, int dv) {
 }
 
 // Lines of every direction, numbered consecutively: direction r owns global
-// lines [base[r], base[r+1]).
+// lines [base[r], base[r+1]); nlines = base[npaths].
 struct Lines {
     int base[kMaxPaths + 1];
     int8_t du[kMaxPaths], dv[kMaxPaths];
-    int npaths;
+    int npaths, nlines;
 };
 
 Lines make_lines(int H, int W, int npaths) {
@@ -82,6 +82,7 @@ Lines make_lines(int H, int W, int npaths) {
         L.dv[r] = (int8_t)kDirs[r][1];
         L.base[r + 1] = L.base[r] + num_lines(H, W, L.du[r], L.dv[r]);
     }
+    L.nlines = L.base[npaths];
     return L;
 }
 
@@ -94,11 +95,18 @@ struct LineInfo {
 // columns below / above them.
 __device__ __forceinline__ LineInfo locate(const Lines& L, int H, int W, int g) {
     LineInfo li;
-    int r = 0;
+    // the direction of line g and its fields, read with constant indices only (the
+    // argument record stays in registers)
+    int r = 0, lbase = 0, du = L.du[0], dv = L.dv[0];
 #pragma unroll
-    for (int i = 1; i < kMaxPaths; ++i) r += (i < L.npaths && g >= L.base[i]) ? 1 : 0;
-    const int line = g - L.base[r];
-    const int du = L.du[r], dv = L.dv[r];
+    for (int i = 1; i < kMaxPaths; ++i)
+        if (i < L.npaths && g >= L.base[i]) {
+            r = i;
+            lbase = L.base[i];
+            du = L.du[i];
+            dv = L.dv[i];
+        }
+    const int line = g - lbase;
     const int su = min(abs(du), W), sv = min(abs(dv), H);
     li.r = r;
     li.du = du;
@@ -176,13 +184,14 @@ __device__ __forceinline__ uint32_t lane_min(const uint32_t (&L)[K]) {
 constexpr int kTilePix = 64;
 
 struct CcvArgs {
-    const uint64_t* cref;     // [C][H*W]
-    const uint64_t* cview;    // [nv][C][H*W]
-    const float* hyp;
-    int cs[4], ct[4];         // s_hat - s, t_hat - t of each cross view
+    gptr<const uint64_t> cref;     // [C][H*W]
+    gptr<const uint64_t> cview;    // [nv][C][H*W]
+    gptr<const float> hyp;
+    uint64_t cs4, ct4;        // s_hat - s, t_hat - t of cross view z in bits 16z..16z+15
+                              // (int16; packed so that the record is never indexed)
     int nv, C, H, W, N, NP;   // NP: the row stride NPc
     uint32_t tiles;           // pixel tiles per view
-    uint8_t* cvol;            // [nv][H*W][NPc]
+    gptr<uint8_t> cvol;            // [nv][H*W][NPc]
 };
 
 __device__ __forceinline__ void ccv_block(const CcvArgs& a, uint32_t b, uint32_t* tile,
@@ -193,8 +202,9 @@ __device__ __forceinline__ void ccv_block(const CcvArgs& a, uint32_t b, uint32_t
     const uint32_t HW = (uint32_t)H * W;
     const uint32_t p0 = t * kTilePix;
     const int npix = (int)min((uint32_t)kTilePix, HW - p0);
-    const bool along_u = a.ct[z] == 0;
-    const int cs = along_u ? a.cs[z] : a.ct[z];
+    const int csz = (int16_t)(a.cs4 >> (16 * z)), ctz = (int16_t)(a.ct4 >> (16 * z));
+    const bool along_u = ctz == 0;
+    const int cs = along_u ? csz : ctz;
     for (int k = threadIdx.x; k < NP; k += 256)
         s_sh[k] = (int)rintf((float)cs * a.hyp[min(k, N - 1)]);
     __syncthreads();
@@ -269,8 +279,8 @@ __global__ __launch_bounds__(256) void census_cost_volume_kernel(Src src) {
 // SGM over the Census cost volume, every direction of every view in one launch.
 // Output: Lbuf[r][z][p][NP], storage type LT, NP a multiple of 4 elements.
 struct DenseArgs {
-    const uint8_t* cvol;      // [nv][H*W][NPc]
-    void* Lbuf;
+    gptr<const uint8_t> cvol;      // [nv][H*W][NPc]
+    gptr<void> Lbuf;
     Lines lines;
     int nv, H, W, N, NP, NPc;
     uint32_t P1, P2;
@@ -336,7 +346,7 @@ __device__ __forceinline__ void dense_wave(const DenseArgs& a, uint32_t b, uint8
     const int z = (int)(b / a.wblocks);
     const uint32_t wb = b - (uint32_t)z * a.wblocks;
     const int g = __builtin_amdgcn_readfirstlane(wb * kWavesPerBlock + (threadIdx.x >> 6));
-    if (g >= a.lines.base[a.lines.npaths]) return;        // wave-uniform exit
+    if (g >= a.lines.nlines) return;                      // wave-uniform exit
     const int H = a.H, W = a.W, N = a.N, NPc = a.NPc;
     const uint32_t P1 = a.P1, P2 = a.P2;
     const LineInfo li = locate(a.lines, H, W, g);
@@ -502,10 +512,10 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void sgm_dense_paths_kernel(Sr
 // Sum over directions + WTA (Eq. 9-10) of the initial stage: one wave per pixel,
 // lane l holds hypotheses 2l and 2l+1 (+128 per round); lowest index on ties.
 struct SumWtaArgs {
-    const void* Lbuf;
+    gptr<const void> Lbuf;
     int64_t HW;
     int nv, N, NP;
-    int16_t* dmap;            // [nv][H*W]
+    gptr<int16_t> dmap;            // [nv][H*W]
 };
 
 template <typename LT, int kPaths>
@@ -613,8 +623,8 @@ __global__ __launch_bounds__(256) void dense_sum_wta_kernel(Src src) {
 // and the aggregated cost of Eq. (9) of every cross view, [nv][H*W][N], copied
 // and summed out of the stage's own buffers (element e = (z*HW + p)*N + k).
 struct ExportArgs {
-    const void* src;          // cvol [nv][HW][NPc] (8-bit), or Lbuf [npaths][nv][HW][NP]
-    void* dst;                // [nv][HW][N]: 8-bit costs, or 16-bit sums
+    gptr<const void> src;          // cvol [nv][HW][NPc] (8-bit), or Lbuf [npaths][nv][HW][NP]
+    gptr<void> dst;                // [nv][HW][N]: 8-bit costs, or 16-bit sums
     int64_t rows;             // nv * HW
     int N, NP, npaths, lt;    // lt: bytes per path-cost element (sums)
 };
@@ -651,10 +661,10 @@ struct alignas(16) PixMeta {
 };
 
 struct MetaArgs {
-    const int64_t* off;
-    const int16_t* lo;
-    const int16_t* hi;
-    PixMeta* meta;
+    gptr<const int64_t> off;
+    gptr<const int16_t> lo;
+    gptr<const int16_t> hi;
+    gptr<PixMeta> meta;
     int HW, N;
 };
 
@@ -677,9 +687,9 @@ __global__ __launch_bounds__(256) void pix_meta_kernel(Src src) {
 }
 
 struct BoundedArgs {
-    const uint16_t* cost;
-    const PixMeta* meta;
-    uint16_t* Lbuf;           // [npaths][dir_stride]
+    gptr<const uint16_t> cost;
+    gptr<const PixMeta> meta;
+    gptr<uint16_t> Lbuf;           // [npaths][dir_stride]
     size_t dir_stride;
     Lines lines;
     int H, W, N;
@@ -691,7 +701,7 @@ __device__ __forceinline__ void bounded_wave(const BoundedArgs& a, uint32_t b) {
     constexpr int kMeta = D, kCost = D / 2;   // two-stage prefetch
     const int lane = threadIdx.x & 63;
     const int g = __builtin_amdgcn_readfirstlane(b * kWavesPerBlock + (threadIdx.x >> 6));
-    if (g >= a.lines.base[a.lines.npaths]) return;
+    if (g >= a.lines.nlines) return;
     const int H = a.H, W = a.W;
     const uint32_t P1 = a.P1, P2 = a.P2;
     const LineInfo li = locate(a.lines, H, W, g);
@@ -812,7 +822,7 @@ __device__ __forceinline__ void bounded_group_wave(const BoundedArgs& a, uint32_
     const int H = a.H, W = a.W, N = a.N;
     const uint32_t P1 = a.P1, P2 = a.P2;
     const int g = ((int)b * kB16Waves + wave) * kLines + grp;   // this group's line
-    const int nlines = a.lines.base[a.lines.npaths];
+    const int nlines = a.lines.nlines;
     LineInfo li{0, 0, 0, 0, 0, 0};
     if (g < nlines) li = locate(a.lines, H, W, g);
     // steps: the longest line of the wave (wave-uniform)
@@ -908,10 +918,10 @@ __global__ __launch_bounds__(64 * kB16Waves) void sgm_bounded_group_kernel(Src s
 // csum[c] = sum_r Lbuf[r][c] over the cells of the CSR volume; each of a light
 // field's nblk workgroups strides over its device-side cell count.
 struct BsumArgs {
-    const uint16_t* Lbuf;     // [npaths][dir_stride]
+    gptr<const uint16_t> Lbuf;     // [npaths][dir_stride]
     size_t dir_stride;
-    const int64_t* total;     // device-side cell count
-    void* csum;
+    gptr<const int64_t> total;     // device-side cell count
+    gptr<void> csum;
     uint32_t nblk;
 };
 
@@ -1104,8 +1114,8 @@ hipError_t stage_sgm_initial(Runner& r, const Jobs& jobs, int part) {
         c.cview = j->census + (size_t)j->C * HW;
         c.hyp = j->hyp;
         for (int i = 0; i < j->nv; ++i) {
-            c.cs[i] = sh - j->st[2 * i];
-            c.ct[i] = th - j->st[2 * i + 1];
+            c.cs4 |= (uint64_t)(uint16_t)(int16_t)(sh - j->st[2 * i]) << (16 * i);
+            c.ct4 |= (uint64_t)(uint16_t)(int16_t)(th - j->st[2 * i + 1]) << (16 * i);
         }
         c.nv = j->nv;
         c.C = j->C;
