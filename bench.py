@@ -13,20 +13,29 @@ paths (synthetic stand-in for the 4D light field benchmark's shape).
 Printed: one JSON line with Gcells/s (cells = |V|*H*W*N initial + the bounded
 cells sum_p w(p)), depth maps/s, p50/p99 step latency, per-stage times from HIP
 events recorded on the stream the kernels run on, the roofline of the dominant
-kernel, and the CPU oracle timed on this host as a reported baseline.
+unit (the initial stage's three kernels against the algorithmic bytes of that
+stage), every stage's roofline and the whole step's fraction of HBM bandwidth,
+with measured traffic from the committed rocprofv3 counter summaries when they
+were taken on the current sources, and the CPU oracle timed on this host as a
+reported baseline.
 
-Also in the same line: the accuracy of the map against the scene's ground truth
-(BadPix 0.07, MSE, M-metric of Sec. 4.2) beside the boundary-less search
-(lambda = -1, Sec. 4.5) on the same light field, and two more measurements
-(skip them with --no-batch / --no-serve):
+Also in the same line (skip them with --no-quality / --no-batch / --no-large /
+--no-serve):
+  quality  the map against the scene's ground truth (BadPix 0.07, MSE, M-metric of
+           Sec. 4.2) beside the boundary-less search (lambda = -1, Sec. 4.5);
   batched  64 light fields mixing 5x5x256^2, 7x7x384^2 and 9x9x512^2 float32
            scenes with 32..128 hypotheses: one autotuned, graph-captured batch
-           plan against the same 64 lf_depth calls one after another.
-  served   Poisson arrivals of requests drawn uniformly from the small 5x5x96^2
-           workload, the 9x9x512^2 N=100 workload and the mixed shapes above,
-           through the request loop (continuous batching, admission by workspace
-           footprint into a resident arena) against one-at-a-time lf_depth
-           calls on the same arrival times: p50/p99 latency and maps/s.
+           plan against the same 64 lf_depth calls one after another;
+  large    2 x 15x15 views of 625x434 f32 (N = 64) with 2 x 1x11 views of
+           1920x1080 u8 (N = 96): per shape and as one batch;
+  served   Poisson arrivals (2,000 requests, 100 warm-up) drawn uniformly from the
+           small 5x5x96^2 workload, the 9x9x512^2 N=100 workload and the mixed
+           shapes above, through the request loop at 0.8 (and 0.5, 0.95) of the
+           one-at-a-time capacity, against one-at-a-time lf_depth calls on the same
+           arrival times: p50/p99 latency and maps/s.
+
+Profile summaries (profiles/): --summarize-kernels and --summarize-counters turn
+rocprofv3 output of this script into the committed tables and records.
 """
 from __future__ import annotations
 
@@ -45,38 +54,77 @@ METRIC = ("Gcells/s (pixelÃ—hypothesis, cost+SGM) and depth maps/s at 9Ã—9Ã—512Â
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP32_PEAK_TFLOPS = 157.3       # MI355X fp32 vector
 
+# The paper's own runtime for this kind of light field (context, not a target):
+# Table 1 / Sec. 4.7, a single thread of an Intel Xeon E3-1245 V2 at 3.40 GHz,
+# 9x9 views of 512x512 8-bit RGB, 16 paths.
+PAPER_RUNTIME = {"seconds_per_map_median": 10 ** 0.25, "seconds_per_map_average": 10 ** 0.23,
+                 "hardware": "Intel Xeon E3-1245 V2 @ 3.40 GHz, one thread (C, GCC -O3)",
+                 "workload": "4D light field benchmark: 9x9 views of 512x512 8-bit RGB, "
+                             "16 SGM paths, sparse 7x7 Census",
+                 "source": "Table 1 (Sec. 4.4), Sec. 4.7",
+                 "note": "another machine, input and path count: context only"}
 
-def stage_models(S, T, cells_initial, cells_bounded, sum_bits, npaths):
-    """Algorithmic work of each stage (or kernel) per light field and the resource
-    that bounds it.
+# Where each kernel's source lives (counter records are valid only for the source
+# they were taken on) and which profiled stage launches it.
+KERNEL_SOURCE = {
+    "census_kernel": "census.hip", "census_cost_volume_kernel": "sgm.hip",
+    "sgm_dense_paths_kernel": "sgm.hip", "dense_sum_wta_rows_kernel": "sgm.hip",
+    "dense_sum_wta_kernel": "sgm.hip", "initial_export_kernel": "sgm.hip",
+    "prep_kernel": "post.hip", "fuse_kernel": "post.hip", "fill_kernel": "post.hip",
+    "borders_kernel": "post.hip", "full_range_kernel": "post.hip",
+    "scan_reduce_kernel": "post.hip", "scan_apply_kernel": "post.hip",
+    "pad_views_kernel": "cost.hip", "cost_l2_kernel": "cost.hip",
+    "cost_census_all_kernel": "cost.hip", "pix_meta_kernel": "sgm.hip",
+    "sgm_bounded_paths_kernel": "sgm.hip", "sgm_bounded_group_kernel": "sgm.hip",
+    "bounded_sum_kernel": "sgm.hip", "wta_subpixel_kernel": "post.hip",
+    "median3_kernel": "post.hip",
+}
+STAGE_KERNELS = {
+    "census": ["census_kernel"],
+    "sgm_initial": ["census_cost_volume_kernel", "sgm_dense_paths_kernel",
+                    "dense_sum_wta_rows_kernel", "dense_sum_wta_kernel"],
+    "fuse_fill_borders": ["prep_kernel", "fuse_kernel", "fill_kernel", "borders_kernel"],
+    "offsets": ["scan_reduce_kernel", "scan_apply_kernel"],
+    "cost_inputs": ["pad_views_kernel"],
+    "cost_bounded": ["cost_l2_kernel", "cost_census_all_kernel"],
+    "sgm_bounded": ["pix_meta_kernel", "sgm_bounded_paths_kernel", "sgm_bounded_group_kernel",
+                    "bounded_sum_kernel"],
+    "wta_subpixel_median": ["wta_subpixel_kernel", "median3_kernel"],
+}
 
-    sgm_initial   (Census cost + SGM + WTA over the cross views, three kernels):
-                  HBM, 12 B/cell -- the 16-bit aggregated cost must make 4
-                  orientation round trips (write, 3 x read+write, the last read
-                  fused into WTA).
-    initial_paths (the path-cost kernel of that stage, one launch): HBM, the
-                  8-bit cost volume read once and the path costs of every
-                  direction written once, (1 + npaths) B/cell.
-    cost_bounded  (l2 over all views, Eq. 12): fp32 ALU, 11 flop per view and cell
-                  (3 FMA, 3 differences, |ref - val|, the running sum) over the
-                  S*T - 1 views that are not the reference.
-    sgm_bounded   (bounded SGM): HBM, 8 B/cell of cost reads (one per orientation)
-                  plus 12 (16-bit sums) or 24 (32-bit sums) B/cell of sum state.
+
+def algorithmic_work(S, T, H, W, N, nv, px_bytes, cells_initial, cells_bounded, sum_bits):
+    """Algorithmic work of every stage of one light field and the resource that bounds
+    it, from the data each step must move (not what this design moves):
+
+    census               (pixel bytes + 8) per pixel of the reference and cross views
+    sgm_initial          12 B per initial cell -- the 16-bit aggregated cost makes its
+                         round trips between the four orientation passes (written once,
+                         read and written twice, read once by the WTA) -- plus
+                         (2*8 + 2)/N B per cell for the two Census strings and D_i
+    fuse_fill_borders    ~40 B per pixel (maps, d_init, bounds), offsets included
+    cost_inputs          0 (the edge-replicated view copy is this design's choice)
+    cost_bounded         fp32 ALU: 11 flop per view and cell (3 FMA, 3 differences,
+                         |ref - val|, the running sum) over the S*T - 1 views that are
+                         not the reference; bytes: the 16-bit cost written and every
+                         view read once
+    sgm_bounded          8 B per cell of cost reads (one per orientation) + 12 (16-bit
+                         sums) or 24 (32-bit sums) B per cell of aggregated-cost state
+    wta_subpixel_median  ~12 B per pixel
     """
-    return {
-        "sgm_initial": dict(bound="hbm", unit="GB/s", peak=HBM_PEAK_GBS,
-                            work=12.0 * cells_initial / 1e9,
-                            kernel="census_cost_volume + sgm_dense_paths + dense_sum_wta"),
-        "initial_paths": dict(bound="hbm", unit="GB/s", peak=HBM_PEAK_GBS,
-                              work=(1.0 + npaths) * cells_initial / 1e9,
-                              kernel="sgm_dense_paths_kernel"),
-        "cost_bounded": dict(bound="alu", unit="TFLOP/s", peak=FP32_PEAK_TFLOPS,
-                             work=11.0 * (S * T - 1) * cells_bounded / 1e12,
-                             kernel="cost_l2_kernel"),
-        "sgm_bounded": dict(bound="hbm", unit="GB/s", peak=HBM_PEAK_GBS,
-                            work=(8.0 + (12.0 if sum_bits == 16 else 24.0)) * cells_bounded / 1e9,
-                            kernel="sgm_bounded_paths + bounded_sum"),
+    HW = H * W
+    work = {
+        "census": dict(bytes=(px_bytes + 8) * HW * (1 + nv)),
+        "sgm_initial": dict(bytes=(12.0 + 18.0 / N) * cells_initial),
+        "fuse_fill_borders": dict(bytes=40.0 * HW),
+        "offsets": dict(bytes=0.0),
+        "cost_inputs": dict(bytes=0.0),
+        "cost_bounded": dict(bytes=2.0 * cells_bounded + (S * T * px_bytes + 8.0) * HW,
+                             flop=11.0 * (S * T - 1) * cells_bounded),
+        "sgm_bounded": dict(bytes=(8.0 + (12.0 if sum_bits == 16 else 24.0)) * cells_bounded),
+        "wta_subpixel_median": dict(bytes=12.0 * HW),
     }
+    return work
 
 
 def log(*a):
@@ -88,56 +136,167 @@ def source_sha(path):
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def load_record(kernel, kind, src):
-    """The key = value record profiles/<kernel>.<kind>.txt written from rocprofv3
-    counters, or None if it is missing or was taken on another version of the
-    kernel's source."""
-    path = os.path.join(ROOT, "profiles", f"{kernel}.{kind}.txt")
+CSRC = os.path.join(ROOT, "paper_1907_13449_amd", "csrc")
+
+
+def current_sources():
+    """sha256 (16 hex) of every kernel source and the shared internal header."""
+    names = sorted(set(KERNEL_SOURCE.values())) + ["lf_internal.h"]
+    return {n: source_sha(os.path.join(CSRC, n)) for n in names}
+
+
+def load_counter_record(workload_name):
+    """Per-kernel HBM traffic (rocprofv3 FETCH_SIZE / WRITE_SIZE, calibrated) of the
+    workload from profiles/traffic_<workload>.json, keeping only the kernels whose
+    source (and the shared header) is the one the counters were taken on."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload_name}.json")
     if not os.path.exists(path):
-        return None
-    rec = {}
-    for line in open(path):
-        if "=" in line and not line.startswith("#"):
-            k, v = line.split("=", 1)
-            rec[k.strip()] = v.strip()
-    return rec if rec.get("source_sha") == source_sha(src) else None
+        return {}
+    rec = json.load(open(path))
+    cur = current_sources()
+    srcs = rec.get("sources", {})
+    ok = {}
+    for k, v in rec.get("kernels", {}).items():
+        src = KERNEL_SOURCE.get(k)
+        if src and srcs.get(src) == cur.get(src) and srcs.get("lf_internal.h") == cur.get(
+                "lf_internal.h"):
+            ok[k] = v
+    return ok
 
 
-def load_traffic(kernel, src):
-    """HBM bytes per launch of `kernel` measured by rocprofv3 counters (profiles/), or None
-    if the counters were taken on another version of its source."""
-    rec = load_record(kernel, "traffic", src)
+def cpu_info():
+    model = ""
     try:
-        return float(rec["bytes_per_launch"]) if rec else None
-    except (KeyError, ValueError):
-        return None
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(),
+            "affinity_cpus": len(os.sched_getaffinity(0))}
 
 
-def load_units(kernel, src):
-    """Busy fractions of the kernel's texture address / data units and VALU over its
-    cycles (rocprofv3 counters, profiles/), or None for another source version."""
-    rec = load_record(kernel, "units", src)
-    try:
-        return {k: float(rec[k]) for k in ("ta_busy", "td_busy", "valu_busy")} if rec else None
-    except (KeyError, ValueError):
-        return None
-
-
-def cpu_baseline(lfd, cells_per_map, min_seconds=10.0):
-    """The oracle on whole light fields of the workload, repeated until at least
-    min_seconds of CPU work (at most 4 runs)."""
+def time_oracle(lfd, runs):
+    """Seconds per whole light field of the oracle, over `runs` runs, this thread
+    pinned to one core (the affinity is restored afterwards)."""
     import oracle
     oracle.build(force=False)
-    runs, t0 = 0, time.perf_counter()
-    while runs < 4 and (runs == 0 or time.perf_counter() - t0 < min_seconds):
-        oracle.depth(lfd.views, lfd.hyp, lfd.params)
-        runs += 1
-    dt = (time.perf_counter() - t0) / runs
-    return {"value": cells_per_map / dt / 1e9, "unit": "Gcells/s", "cores": 1,
-            "kind": "oracle", "seconds_per_map": dt, "maps_per_s": 1.0 / dt, "runs": runs,
-            "sample": f"{runs} runs on one whole light field of the workload ({lfd.S}x{lfd.T} "
-                      f"views of {lfd.H}x{lfd.W}, N={lfd.N}; {runs * dt:.1f} s of CPU work), "
-                      "single-threaded C oracle, -O3"}
+    before = os.sched_getaffinity(0)
+    core = min(before)
+    os.sched_setaffinity(0, {core})
+    try:
+        times = []
+        for _ in range(runs):
+            t0 = time.perf_counter()
+            oracle.depth(lfd.views, lfd.hyp, lfd.params)
+            times.append(time.perf_counter() - t0)
+    finally:
+        os.sched_setaffinity(0, before)
+    return times, core
+
+
+def cpu_baseline(lfd, cells_per_map, small=None, small_cells=None, runs=3):
+    """The oracle (single-threaded C, -O3) on whole light fields of the benchmark
+    workload, `runs` runs pinned to one core, plus five runs of the small workload."""
+    times, core = time_oracle(lfd, runs)
+    dt = sum(times) / len(times)
+    res = {"value": cells_per_map / dt / 1e9, "unit": "Gcells/s", "cores": 1, "kind": "oracle",
+           "seconds_per_map": dt, "seconds_per_map_runs": times, "maps_per_s": 1.0 / dt,
+           "runs": runs, "pinned_core": core, **cpu_info(),
+           "sample": f"{runs} runs of the oracle on one whole light field of the workload "
+                     f"({lfd.S}x{lfd.T} views of {lfd.H}x{lfd.W}, N={lfd.N}; "
+                     f"{sum(times):.1f} s of CPU work), one thread pinned to one core"}
+    if small is not None:
+        st, _ = time_oracle(small, 5)
+        sd = sum(st) / len(st)
+        res["small"] = {"workload": f"{small.S}x{small.T} views of {small.H}x{small.W} u8, "
+                                    f"N={small.N}", "seconds_per_map": sd,
+                        "gcells_s": small_cells / sd / 1e9 if small_cells else None, "runs": 5}
+    return res
+
+
+# ----------------------------------------------------- rocprofv3 summaries
+def _short_kernel(name):
+    """'void lf::(anonymous namespace)::foo_kernel<lf::Single<...>, ...>(...)' ->
+    ('foo_kernel', 'Single')."""
+    import re
+    m = re.search(r"::(\w+_kernel)<lf::(Single|Group)<", name)
+    if m:
+        return m.group(1), m.group(2)
+    return name.split("(")[0].split("<")[0].split("::")[-1], ""
+
+
+def summarize_kernel_stats(stats_csv, command):
+    """Markdown of a rocprofv3 --kernel-trace --stats summary: calls and average
+    microseconds per kernel (liblf kernels by short name and launch form)."""
+    import csv
+    rows = list(csv.DictReader(open(stats_csv)))
+    out = [f"Command (from the repository root, on one MI355X):", "", f"    {command}", "",
+           "Sources: " + ", ".join(f"{k} {v}" for k, v in current_sources().items()) +
+           " (sha256, 16 hex).", "",
+           "| kernel | form | calls | avg us | total % |", "|---|---|---:|---:|---:|"]
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
+        k, form = _short_kernel(r["Name"])
+        out.append(f"| {k} | {form} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                   f"{float(r['Percentage']):.2f} |")
+    return "\n".join(out)
+
+
+def summarize_counters(fetch_csv, write_csv, calib_bytes, workload_name, commands):
+    """Per-kernel HBM bytes per launch from two rocprofv3 --pmc runs (FETCH_SIZE and
+    WRITE_SIZE, KiB per dispatch).  Each counter is scaled by what it reads for the
+    plain device copy of calib_bytes in the same run (the largest non-liblf dispatch):
+    fetched bytes = FETCH_SIZE x calib_bytes / FETCH_SIZE(copy), likewise written.
+    Returns (record dict, markdown)."""
+    import csv
+    import statistics
+
+    def per_dispatch(path, counter):
+        vals = {}
+        for r in csv.DictReader(open(path)):
+            if r.get("Counter_Name") != counter:
+                continue
+            key = (r["Dispatch_Id"], r["Kernel_Name"])
+            vals[key] = vals.get(key, 0.0) + float(r["Counter_Value"])
+        return vals
+
+    f, w = per_dispatch(fetch_csv, "FETCH_SIZE"), per_dispatch(write_csv, "WRITE_SIZE")
+
+    def calib(vals):
+        other = [v for (d, n), v in vals.items() if "lf::" not in n]
+        return calib_bytes / (max(other) * 1024.0)
+
+    ff, wf = calib(f), calib(w)
+
+    def by_kernel(vals, factor):
+        acc = {}
+        for (d, n), v in vals.items():
+            if "lf::" not in n:
+                continue
+            k, form = _short_kernel(n)
+            acc.setdefault(k, []).append(v * 1024.0 * factor)
+        return {k: (statistics.median(v), len(v)) for k, v in acc.items()}
+
+    fk, wk = by_kernel(f, ff), by_kernel(w, wf)
+    kernels = {}
+    for k in sorted(set(fk) | set(wk)):
+        kernels[k] = {"fetch_bytes": fk.get(k, (0.0, 0))[0], "write_bytes": wk.get(k, (0.0, 0))[0],
+                      "launches": max(fk.get(k, (0, 0))[1], wk.get(k, (0, 0))[1])}
+    rec = {"workload": workload_name, "commands": commands, "calib_bytes": calib_bytes,
+           "fetch_factor": ff, "write_factor": wf, "sources": current_sources(),
+           "kernels": kernels}
+    md = [f"Commands (from the repository root, one counter per run, on one MI355X):", ""]
+    md += [f"    {c}" for c in commands]
+    md += ["", f"Calibration: the plain {calib_bytes / 2**30:.0f} GiB device copy in the same run "
+           f"reads FETCH_SIZE x {ff:.3f} KiB and WRITE_SIZE x {wf:.3f} KiB per byte moved, "
+           "so fetched bytes = FETCH_SIZE x 1024 x that factor, likewise written.", "",
+           "Per launch (median over the run's dispatches of each kernel):", "",
+           "| kernel | launches | fetched MB | written MB |", "|---|---:|---:|---:|"]
+    for k, v in sorted(kernels.items(), key=lambda x: -(x[1]["fetch_bytes"] + x[1]["write_bytes"])):
+        md.append(f"| {k} | {v['launches']} | {v['fetch_bytes'] / 1e6:.1f} | "
+                  f"{v['write_bytes'] / 1e6:.1f} |")
+    return rec, "\n".join(md)
 
 
 # --------------------------------------------------------------- quality
@@ -309,101 +468,222 @@ def run_batched(scenes, n, dev):
     return res
 
 
-def run_served(scenes, n, dev):
+def run_large(dev, reps=3):
+    """The large workload: two 15x15-view plenoptic-like light fields of 625x434 f32
+    (N = 64, d in [-1.5, 1.5], noise 0.01; seeds 4001, 4002) and two 1x11
+    moving-stage light fields of 1920x1080 u8 (N = 96, d in [0, 24]; seeds 4003,
+    4004), 8 paths.  Plain: one lf_depth per light field back to back, with
+    per-stage times of each shape from the library's event hook; batched: the four
+    as one autotuned, graph-captured plan."""
+    import numpy as np
+    import torch
+    import lfsynth
+    from paper_1907_13449_amd import lf
+    t0 = time.perf_counter()
+    lfds = [lfsynth.workload("plenoptic", seed=4001), lfsynth.workload("plenoptic", seed=4002),
+            lfsynth.workload("stage", seed=4003), lfsynth.workload("stage", seed=4004)]
+    log(f"[bench] large workload generated in {time.perf_counter() - t0:.1f}s")
+    reqs = [dict(kind="plenoptic" if l.S == 15 else "stage", lfd=l,
+                 views=torch.from_numpy(l.views).to(dev), hyp=torch.from_numpy(l.hyp).to(dev),
+                 params=l.params) for l in lfds]
+    cells = [request_cells(lf, r) for r in reqs]
+    outs = [torch.empty((r["lfd"].H, r["lfd"].W), dtype=torch.float32, device=dev) for r in reqs]
+    need = max(lf.depth_workspace_bytes(r["lfd"].S, r["lfd"].T, r["lfd"].H, r["lfd"].W,
+                                        r["lfd"].N, r["params"]) for r in reqs)
+    ws = lf.workspace(need, dev)
+    stream = torch.cuda.current_stream()
+
+    def one(r, o):
+        lf.lf_depth(r["views"], r["hyp"], r["params"], ws=ws, out=o, stream=stream)
+
+    for r, o in zip(reqs, outs):
+        one(r, o)
+    torch.cuda.synchronize()
+    ref = [o.clone() for o in outs]
+    # per light field: time and stages (hook on), then the whole sequence (hook off)
+    per = {}
+    for r, o, c in zip(reqs, outs, cells):
+        lf.profile_enable(True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            one(r, o)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        lf.profile_enable(False)
+        st = lf.profile_read()
+        d = per.setdefault(r["kind"], {"ms": [], "cells": [], "stage_ms": {}})
+        d["ms"].append(e0.elapsed_time(e1) / reps)
+        d["cells"].append(c)
+        for k, v in st.items():
+            d["stage_ms"][k] = d["stage_ms"].get(k, 0.0) + v[0] / reps / 2.0
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        for r, o in zip(reqs, outs):
+            one(r, o)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    plain_ms = e0.elapsed_time(e1) / reps
+    del ws
+    torch.cuda.empty_cache()
+    t0 = time.perf_counter()
+    plan = lf.Plan([(r["views"], r["hyp"], r["params"], o, None) for r, o in zip(reqs, outs)])
+    tuning = plan.autotune(reps=1)
+    plan.capture()
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    for o in outs:
+        o.fill_(float("nan"))
+    plan.run(stream)
+    torch.cuda.synchronize()
+    same = all(torch.equal(a, b) for a, b in zip(outs, ref))
+    e0.record(stream)
+    for _ in range(reps):
+        plan.run(stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    batch_ms = e0.elapsed_time(e1) / reps
+    plan.close()
+    total = float(sum(cells))
+    shapes = {}
+    for kind, d in per.items():
+        l = next(r["lfd"] for r in reqs if r["kind"] == kind)
+        ms = float(np.mean(d["ms"]))
+        shapes[kind] = {"shape": f"{l.S}x{l.T} views of {l.W}x{l.H} "
+                                 f"{'u8' if l.views.dtype == np.uint8 else 'f32'}, N={l.N}, "
+                                 f"d in [{l.hyp[0]:.1f}, {l.hyp[-1]:.1f}]",
+                        "ms_per_map": ms, "cells_per_map": float(np.mean(d["cells"])),
+                        "gcells_s": float(np.mean(d["cells"])) / (ms * 1e-3) / 1e9,
+                        "stage_ms": {k: v for k, v in d["stage_ms"].items() if v > 0}}
+    res = {"workload": "2 x 15x15x625x434 f32 (N=64) + 2 x 1x11x1920x1080 u8 (N=96), 8 paths",
+           "light_fields": len(reqs), "cells": total, "plain_ms": plain_ms, "batched_ms": batch_ms,
+           "plain_gcells_s": total / (plain_ms * 1e-3) / 1e9,
+           "batched_gcells_s": total / (batch_ms * 1e-3) / 1e9,
+           "plain_maps_s": len(reqs) / (plain_ms * 1e-3),
+           "batched_maps_s": len(reqs) / (batch_ms * 1e-3), "speedup": plain_ms / batch_ms,
+           "identical_to_plain": bool(same), "tuning": tuning, "plan_setup_s": setup_s,
+           "per_shape": shapes}
+    log(f"[bench] large: batched {batch_ms:.2f} ms vs plain {plain_ms:.2f} ms "
+        f"({plain_ms / batch_ms:.2f}x), {res['plain_gcells_s']:.1f} Gcells/s plain")
+    return res
+
+
+def run_served(scenes, n, warmup, dev, rates=(0.8, 0.5, 0.95)):
+    """Poisson arrivals of requests drawn uniformly from the small 5x5x96^2 u8
+    workload, the 9x9x512^2 N=100 workload and the mixed shapes (5x5x256^2,
+    7x7x384^2, 9x9x512^2 f32, N in 32..128), each at a fixed rate rho x the
+    one-at-a-time capacity measured from the requests' own service times: rho = 0.8
+    reported, 0.5 and 0.95 as a sweep.  n requests, the first `warmup` of them not
+    counted.  Plain = a FIFO loop of lf_depth calls, each started at or after its
+    arrival; served = the request loop over a resident arena, on the same arrivals.
+    Latency = completion - arrival."""
     import numpy as np
     import torch
     from paper_1907_13449_amd import lf
     reqs = mixed_requests(scenes, n, 11, dev, kinds=("small", "paper", "mix"))
-    rng = np.random.default_rng(12)
     outs = [torch.empty(r["views"].shape[2:], dtype=torch.float32, device=dev) for r in reqs]
     need = max(lf.depth_workspace_bytes(r["views"].shape[1], r["views"].shape[0],
                                         r["views"].shape[2], r["views"].shape[3],
                                         r["hyp"].shape[0], r["params"]) for r in reqs)
     ws = lf.workspace(need, dev)
     stream = torch.cuda.current_stream()
-    # service time of each request alone (plain launch), for the arrival rate
-    svc = []
     for r, o in zip(reqs, outs):
         lf.lf_depth(r["views"], r["hyp"], r["params"], ws=ws, out=o, stream=stream)
     torch.cuda.synchronize()
     ref = [o.clone() for o in outs]
+    # service time of each request alone (plain launch), for the arrival rate
+    svc = []
     for r, o in zip(reqs, outs):
         t = time.perf_counter()
         lf.lf_depth(r["views"], r["hyp"], r["params"], ws=ws, out=o, stream=stream)
         torch.cuda.synchronize()
         svc.append(time.perf_counter() - t)
     mean_svc = float(np.mean(svc))
-    rate = 0.8 / mean_svc               # 80 % of what one-at-a-time can sustain
-    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n))
+    counted = slice(warmup, n)
 
     def pct(lat):
+        lat = np.asarray(lat)[counted]
         return {"p50_ms": float(np.percentile(lat, 50) * 1e3),
                 "p99_ms": float(np.percentile(lat, 99) * 1e3)}
 
-    # plain: FIFO, one lf_depth at a time, each started no earlier than its arrival
-    t0 = time.perf_counter()
-    lat, done = [], 0.0
-    for r, o, a in zip(reqs, outs, arrivals):
+    def wait_until(t0, a):
         while time.perf_counter() - t0 < a:
-            time.sleep(0.0001)
-        lf.lf_depth(r["views"], r["hyp"], r["params"], ws=ws, out=o, stream=stream)
-        torch.cuda.synchronize()
-        done = time.perf_counter() - t0
-        lat.append(done - a)
-    plain = dict(pct(np.array(lat)), maps_s=n / done)
-    del ws
-    torch.cuda.empty_cache()
+            pass
+
+    def plain(arr):
+        t0 = time.perf_counter()
+        lat, done, first = [], 0.0, None
+        for i, (r, o, a) in enumerate(zip(reqs, outs, arr)):
+            wait_until(t0, a)
+            lf.lf_depth(r["views"], r["hyp"], r["params"], ws=ws, out=o, stream=stream)
+            torch.cuda.synchronize()
+            done = time.perf_counter() - t0
+            lat.append(done - a)
+            if i == warmup:
+                first = a
+        return dict(pct(lat), maps_s=(n - warmup) / (done - first))
+
+    arena_gb = 64
+    srv_cfgs = [dict(max_inflight=2, max_batch=1), dict(max_inflight=2, max_batch=8, group_ratio=2),
+                dict(max_inflight=3, max_batch=4, group_ratio=2)]
 
     def serve(arr, cfg):
-        inflight, max_batch, ratio = cfg
-        srv = lf.Server(64 << 30, dev, max_batch=max_batch, max_inflight=inflight,
-                        group_ratio=ratio)
+        srv = lf.Server(arena_gb << 30, dev, max_queue=n + 16, **cfg)
         for o in outs:
             o.fill_(float("nan"))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         tickets = []
         for r, o, a in zip(reqs, outs, arr):
-            while time.perf_counter() - t0 < a:
-                time.sleep(0.0001)
+            wait_until(t0, a)
             tickets.append(srv.submit(r["views"], r["hyp"], r["params"], o))
         infos = [srv.wait(t) for t in tickets]
         st = srv.stats()
         srv.close()
         ok = all(i["status"] == 0 for i in infos)
-        lat = np.array([i["t_done"] - i["t_submit"] for i in infos])
-        span = max(i["t_done"] for i in infos) - min(i["t_submit"] for i in infos)
+        lat = [i["t_done"] - i["t_submit"] for i in infos]
+        span = max(i["t_done"] for i in infos[warmup:]) - infos[warmup]["t_submit"]
+        torch.cuda.synchronize()
         same = ok and all(torch.equal(a, b) for a, b in zip(outs, ref))
-        sizes = [i["batch_size"] for i in infos]
-        phase = {"queue_ms": np.mean([i["t_admit"] - i["t_submit"] for i in infos]) * 1e3,
-                 "plan_launch_ms": np.mean([i["t_launch"] - i["t_admit"] for i in infos]) * 1e3,
-                 "device_ms": np.mean([i["t_done"] - i["t_launch"] for i in infos]) * 1e3}
-        return dict(pct(lat), maps_s=n / span, batches=st["batches"],
+        sizes = [i["batch_size"] for i in infos[counted]]
+        c = infos[counted]
+        phase = {"queue_ms": float(np.mean([i["t_admit"] - i["t_submit"] for i in c]) * 1e3),
+                 "plan_launch_ms": float(np.mean([i["t_launch"] - i["t_admit"] for i in c]) * 1e3),
+                 "device_ms": float(np.mean([i["t_done"] - i["t_launch"] for i in c]) * 1e3)}
+        return dict(pct(lat), maps_s=(n - warmup) / span, batches=st["batches"],
                     mean_batch=float(np.mean(sizes)), arena_peak_gb=st["arena_peak"] / 2**30,
-                    identical_to_plain=bool(same),
-                    config={"max_inflight": inflight, "max_batch": max_batch,
-                            "group_ratio": ratio},
-                    mean_phase=phase)
+                    identical_to_plain=bool(same), config=cfg, mean_phase=phase)
 
-    # server configurations tried on the same arrivals; the one with the lowest
-    # p99 is reported (and the highest saturated throughput)
-    configs = [(1, 8, 0), (2, 8, 0), (2, 8, 2), (3, 4, 2), (4, 4, 2), (4, 8, 0), (4, 1, 0)]
-    runs = [serve(arrivals, c) for c in configs]
-    served = min(runs, key=lambda x: x["p99_ms"])
-    saturated = max((serve(np.zeros(n), c) for c in configs), key=lambda x: x["maps_s"])
-    # one-at-a-time capacity with everything queued at t=0 (no idle gaps)
-    res = {"workload": "Poisson arrivals, requests uniform over the 5x5x96^2 u8 N=32, "
-                       "9x9x512^2 N=100 and mixed 5x5x256^2 / 7x7x384^2 / 9x9x512^2 "
-                       "(N 32..128) light fields",
-           "requests": n, "rate_per_s": rate, "mean_alone_ms": mean_svc * 1e3,
-           "served": served, "plain": plain, "served_all": runs,
-           "saturated_served_maps_s": saturated["maps_s"],
-           "saturated_served_config": saturated["config"],
-           "saturated_plain_maps_s": 1.0 / mean_svc,
-           "server": dict(arena_gb=64, **served["config"])}
-    log(f"[bench] served {n} at {rate:.0f}/s: p50 {served['p50_ms']:.2f} p99 "
-        f"{served['p99_ms']:.2f} ms vs plain p50 {plain['p50_ms']:.2f} p99 {plain['p99_ms']:.2f}")
-    return res
+    rng = np.random.default_rng(12)
+    gaps = rng.exponential(1.0, size=n)
+    results = {}
+    for rho in rates:
+        rate = rho / mean_svc
+        arr = np.cumsum(gaps / rate)
+        pl = plain(arr)
+        runs = [serve(arr, c) for c in srv_cfgs]
+        results[rho] = dict(rate_per_s=rate, plain=pl, served_all=runs)
+        log(f"[bench] rho {rho}: plain p50 {pl['p50_ms']:.2f} p99 {pl['p99_ms']:.2f} ms; served "
+            + "; ".join(f"{r['config']}: p50 {r['p50_ms']:.2f} p99 {r['p99_ms']:.2f}"
+                        for r in runs))
+    del ws
+    # the configuration with the lowest p99 at rho = 0.8, at every rate
+    best = min(range(len(srv_cfgs)), key=lambda i: results[rates[0]]["served_all"][i]["p99_ms"])
+    sweep = {str(rho): {"rate_per_s": v["rate_per_s"], "plain": v["plain"],
+                        "served": v["served_all"][best]} for rho, v in results.items()}
+    head = results[rates[0]]
+    saturated = serve(np.zeros(n), srv_cfgs[best])
+    return {"workload": "Poisson arrivals, requests uniform over the 5x5x96^2 u8 N=32, "
+                        "9x9x512^2 N=100 and mixed 5x5x256^2 / 7x7x384^2 / 9x9x512^2 "
+                        "(N 32..128) light fields",
+            "requests": n, "warmup_requests": warmup, "rho": rates[0],
+            "rate_per_s": head["rate_per_s"], "mean_alone_ms": mean_svc * 1e3,
+            "served": head["served_all"][best], "plain": head["plain"],
+            "served_all": head["served_all"], "sweep": sweep,
+            "saturated_served_maps_s": saturated["maps_s"],
+            "saturated_plain_maps_s": 1.0 / mean_svc,
+            "server": dict(arena_gb=arena_gb, **srv_cfgs[best])}
 
 
 def main():
@@ -419,9 +699,30 @@ def main():
                     help="skip the accuracy / boundary-less comparison")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched measurement")
     ap.add_argument("--no-serve", action="store_true", help="skip the request-loop measurement")
+    ap.add_argument("--no-large", action="store_true", help="skip the large-workload measurement")
     ap.add_argument("--batch-n", type=int, default=64)
-    ap.add_argument("--serve-n", type=int, default=160)
+    ap.add_argument("--serve-n", type=int, default=2000)
+    ap.add_argument("--serve-warmup", type=int, default=100)
+    ap.add_argument("--summarize-kernels", nargs=2, metavar=("STATS_CSV", "COMMAND"),
+                    help="print a markdown summary of a rocprofv3 kernel-stats CSV and exit")
+    ap.add_argument("--summarize-counters", nargs=4,
+                    metavar=("FETCH_CSV", "WRITE_CSV", "WORKLOAD", "OUT_PREFIX"),
+                    help="write OUT_PREFIX.json/.md from two rocprofv3 --pmc runs "
+                         "(FETCH_SIZE, WRITE_SIZE) of a --calib-copy run, and exit")
+    ap.add_argument("--commands", nargs="*", default=[],
+                    help="the rocprofv3 commands recorded with --summarize-counters")
     args = ap.parse_args()
+    if args.summarize_kernels:
+        print(summarize_kernel_stats(*args.summarize_kernels))
+        return
+    if args.summarize_counters:
+        fetch, write, name, out = args.summarize_counters
+        rec, md = summarize_counters(fetch, write, float(1 << 30), name, args.commands)
+        json.dump(rec, open(out + ".json", "w"), indent=1)
+        open(out + ".md", "w").write(f"# HBM traffic per launch (rocprofv3 counters): {name}\n\n"
+                                     + md + "\n")
+        print(md)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this implementation runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
@@ -488,31 +789,86 @@ def main():
 
     stage_ms = {k: v[0] / args.steps for k, v in stages.items()}
     stage_launches = {k: v[1] // args.steps for k, v in stages.items()}
-    # the initial stage as a whole: its three timed parts
+    # the initial stage as a whole: its three timed parts, one kernel each
     parts = ("initial_cost", "initial_paths", "initial_sum_wta")
     stage_ms["sgm_initial"] = sum(stage_ms[k] for k in parts)
     stage_launches["sgm_initial"] = sum(stage_launches[k] for k in parts)
-    models = stage_models(S, T, cells_initial, cells_bounded, p["sum_bits"], p["npaths"])
-    roofs = {}
-    for name, m in models.items():
-        sec = stage_ms[name] * 1e-3
-        achieved = m["work"] / sec          # GB/s or TFLOP/s
-        roofs[name] = {"kernel": m["kernel"], "bound": m["bound"], "achieved": achieved,
-                       "peak": m["peak"], "unit": m["unit"], "frac": achieved / m["peak"],
-                       "ms": stage_ms[name], "launches": stage_launches[name],
-                       "avg_launch_ms": stage_ms[name] / max(stage_launches[name], 1)}
-    # the dominant kernel: the timed stage of one launch that takes longest (the
-    # initial path costs or the bounded cost)
-    dominant = max((k for k in roofs if roofs[k]["launches"] == 1),
-                   key=lambda k: roofs[k]["avg_launch_ms"])
-    src = {"sgm_initial": "sgm.hip", "initial_paths": "sgm.hip", "sgm_bounded": "sgm.hip",
-           "cost_bounded": "cost.hip"}
-    roofline = dict(roofs[dominant])
-    roofline["stage"] = dominant
-    src_path = os.path.join(ROOT, "paper_1907_13449_amd", "csrc", src[dominant])
-    roofline["traffic"] = load_traffic(dominant, src_path)
-    # what bounds it in practice: the vector memory path's units (not in the model)
-    roofline["units"] = load_units(dominant, src_path)
+
+    px_bytes = 1 if lfd.views.dtype == np.uint8 else 4
+    work = algorithmic_work(S, T, H, W, N, nv, px_bytes, cells_initial, cells_bounded,
+                            p["sum_bits"])
+    counters = load_counter_record(lfd.name)
+
+    def counter_bytes(stage):
+        ks = [k for k in STAGE_KERNELS.get(stage, []) if k in counters]
+        if not ks:
+            return None
+        return sum(counters[k]["fetch_bytes"] + counters[k]["write_bytes"] for k in ks)
+
+    stage_roofline = {}
+    for name, wk in work.items():
+        ms = stage_ms.get(name, 0.0)
+        if ms <= 0:
+            continue
+        e = {"ms": ms, "launches": stage_launches.get(name, 0), "bytes": wk["bytes"],
+             "achieved_gbs": wk["bytes"] / (ms * 1e-3) / 1e9,
+             "frac_hbm": wk["bytes"] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+             "kernels": STAGE_KERNELS[name]}
+        if "flop" in wk:
+            e.update(flop=wk["flop"], achieved_tflops=wk["flop"] / (ms * 1e-3) / 1e12,
+                     frac_fp32=wk["flop"] / (ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, bound="alu")
+        else:
+            e["bound"] = "hbm"
+        tb = counter_bytes(name)
+        e["traffic"] = tb
+        e["traffic_ratio"] = tb / wk["bytes"] if tb and wk["bytes"] else None
+        stage_roofline[name] = e
+
+    # the dominant unit: the initial stage (Census cost volume, path costs, their sum
+    # and WTA), its algorithmic bytes over the time of its three launches
+    ini = stage_roofline["sgm_initial"]
+    npaths = p["npaths"]
+    kernel_model = {
+        "note": "this design's own traffic per kernel (8-bit cost volume and path costs), "
+                "not the algorithmic figure",
+        "census_cost_volume_kernel": {"ms": stage_ms["initial_cost"],
+                                      "bytes_per_cell": 1.0,
+                                      "achieved_gbs": cells_initial / (stage_ms["initial_cost"]
+                                                                       * 1e-3) / 1e9},
+        "sgm_dense_paths_kernel": {"ms": stage_ms["initial_paths"],
+                                   "bytes_per_cell": 1.0 + npaths,
+                                   "achieved_gbs": (1.0 + npaths) * cells_initial /
+                                   (stage_ms["initial_paths"] * 1e-3) / 1e9},
+        "dense_sum_wta_rows_kernel": {"ms": stage_ms["initial_sum_wta"],
+                                      "bytes_per_cell": float(npaths),
+                                      "achieved_gbs": npaths * cells_initial /
+                                      (stage_ms["initial_sum_wta"] * 1e-3) / 1e9},
+    }
+    for k, v in kernel_model.items():
+        if isinstance(v, dict):
+            v["frac"] = v["achieved_gbs"] / HBM_PEAK_GBS
+            c = counters.get(k)
+            v["traffic"] = c["fetch_bytes"] + c["write_bytes"] if c else None
+    roofline = {"bound": "hbm", "achieved": ini["achieved_gbs"], "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": ini["frac_hbm"], "traffic": ini["traffic"],
+                "traffic_ratio": ini["traffic_ratio"], "stage": "sgm_initial",
+                "kernels": ["census_cost_volume_kernel", "sgm_dense_paths_kernel",
+                            "dense_sum_wta_rows_kernel"],
+                "launches": ini["launches"], "ms": ini["ms"],
+                "bytes_per_cell": 12.0 + 18.0 / N, "cells": cells_initial,
+                "bytes": ini["bytes"], "kernel_model": kernel_model}
+    total_bytes = sum(wk["bytes"] for wk in work.values())
+    all_k = [k for st in work for k in STAGE_KERNELS.get(st, [])]
+    present = [k for k in all_k if k in counters]
+    step_traffic = (sum(counters[k]["fetch_bytes"] + counters[k]["write_bytes"]
+                        for k in present) if present else None)
+    whole_step = {"bytes": total_bytes, "ms": ms_per_step,
+                  "achieved_gbs": total_bytes / (ms_per_step * 1e-3) / 1e9,
+                  "frac": total_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                  "traffic": step_traffic,
+                  "traffic_ratio": step_traffic / total_bytes if step_traffic else None,
+                  "note": "every stage's algorithmic bytes (the bounded cost's included, "
+                          "although its bound is fp32 arithmetic) over the step time"}
 
     if args.calib_copy:
         a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
@@ -521,6 +877,7 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
+    sum_t = "u16" if p["sum_bits"] == 16 else "u32"
     res = {
         "metric": METRIC,
         "value": cells * args.steps / (gpu_ms * 1e-3) / 1e9,
@@ -532,7 +889,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+u16",
+        "dtype": f"f32+u8/u16/{sum_t}",
+        "dtypes": {"views": "f32" if px_bytes == 4 else "u8",
+                   "initial_cost_volume": "u8", "initial_path_costs": "u8 (u16 when "
+                   "bits + P2 > 255)", "initial_sums": "u16 (in registers)",
+                   "l2_cost": "f32", "bounded_cost": "u16", "bounded_path_costs": "u16",
+                   "bounded_sums": sum_t, "disparity": "f32"},
         "data": "synthetic",
         "config": {"workload": f"{lfd.name}: {S}x{T} views of {H}x{W} "
                                f"{'u8' if lfd.views.dtype == np.uint8 else 'f32'}, N={N} over "
@@ -546,7 +908,9 @@ def main():
         "p99_ms": float(np.percentile(lat, 99)),
         "stage_ms": stage_ms,
         "roofline": roofline,
-        "stage_roofline": roofs,
+        "whole_step": whole_step,
+        "stage_roofline": stage_roofline,
+        "paper_runtime": PAPER_RUNTIME,
     }
     if not args.no_quality:
         res["quality"] = quality_vs_boundless(lf, lfd, views, hyp, out, ms_per_step,
@@ -557,11 +921,20 @@ def main():
         scenes = mixed_scenes(lfd, dev)
     if not args.no_batch and scenes is not None:
         res["batched"] = run_batched(scenes, args.batch_n, dev)
+    if not args.no_large and args.workload == "paper":
+        res["large"] = run_large(dev)
+        torch.cuda.empty_cache()
     if not args.no_serve and scenes is not None:
-        res["served"] = run_served(scenes, args.serve_n, dev)
+        res["served"] = run_served(scenes, args.serve_n, args.serve_warmup, dev)
     if not args.no_cpu_baseline:
-        log("[bench] timing the CPU oracle on one light field")
-        res["cpu_baseline"] = cpu_baseline(lfd, cells)
+        log("[bench] timing the CPU oracle (3 whole light fields, one core)")
+        small = lfsynth.workload("small") if args.workload == "paper" else None
+        small_cells = None
+        if small is not None:
+            sv = torch.from_numpy(small.views).to(dev)
+            sh = torch.from_numpy(small.hyp).to(dev)
+            small_cells = request_cells(lf, dict(views=sv, hyp=sh, params=small.params))
+        res["cpu_baseline"] = cpu_baseline(lfd, cells, small, small_cells)
     print(json.dumps(res), flush=True)
 
 

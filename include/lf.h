@@ -361,7 +361,9 @@ void lf_plan_destroy(lf_plan* plan);
  * later requests may pass one that does not fit yet), groups those admitted
  * together into one batch plan and launches it on one of its streams while
  * earlier batches are still running; when a batch completes its memory returns
- * to the arena and waiting requests are admitted.  The arena (cost and
+ * to the arena and waiting requests are admitted.  A batch of one runs the
+ * lf_depth launches directly (no plan, no table upload).  At most max_large
+ * large requests run at once; smaller ones run beside them.  The arena (cost and
  * aggregation buffers included) stays resident for the server's life. */
 
 typedef struct lf_server lf_server;
@@ -377,6 +379,10 @@ typedef struct {
                                    (similar sizes: a small request does not wait for a
                                    large one's batch) */
     lf_tuning tuning;           /* schedule of every batch (zeros: defaults) */
+    int64_t large_bytes;        /* a request whose workspace exceeds this is "large" (it
+                                   fills the GPU by itself); 0: 256 MiB */
+    int32_t max_large;          /* large requests on the device at once (two would only
+                                   share the GPU and both finish late); 0: 1 */
 } lf_server_config;
 
 /* Times of one request on the host steady clock, in seconds since the server

@@ -50,6 +50,7 @@ struct Batch {
     size_t off = 0, len = 0;  // arena extent
     lf_plan* plan = nullptr;
     int slot = -1;            // stream / event index
+    int large = 0;            // large requests among its members
 };
 
 }  // namespace
@@ -74,6 +75,7 @@ struct lf_server {
     size_t in_use = 0, peak = 0;
 
     std::vector<Batch> inflight;
+    int large_inflight = 0;             // large requests of the batches on the device
     hipStream_t streams[kMaxInflight] = {};
     hipEvent_t events[kMaxInflight] = {};
     bool slot_busy[kMaxInflight] = {};
@@ -151,12 +153,15 @@ struct lf_server {
         return hipSuccess;
     }
 
+    bool is_large(const Pending& r) const { return (int64_t)r.bytes > cfg.large_bytes; }
+
     // Picks the members of the next batch (called with the lock held).
     bool form_batch(Batch& b) {
         const size_t room = largest_free();
         size_t total = 0;
         std::vector<lf_request> qs;
         size_t head = 0;                          // workspace of the first member
+        int large = large_inflight;
         for (auto it = pending.begin(); it != pending.end() && (int)qs.size() < cfg.max_batch;) {
             if (head && cfg.group_ratio >= 2 &&
                 (it->bytes > head * (size_t)cfg.group_ratio ||
@@ -164,11 +169,19 @@ struct lf_server {
                 ++it;                                 // another size class: a later batch
                 continue;
             }
+            if (is_large(*it) && large >= cfg.max_large) {
+                ++it;                                 // waits for a large one to finish
+                continue;
+            }
             qs.push_back(it->q);
             const size_t need = lf_batch_workspace_size(qs.data(), (int)qs.size());
             if (need != 0 && need <= room) {
                 total = need;
                 if (!head) head = it->bytes;
+                if (is_large(*it)) {
+                    ++large;
+                    ++b.large;
+                }
                 b.reqs.push_back(*it);
                 it = pending.erase(it);
             } else {
@@ -177,12 +190,14 @@ struct lf_server {
             }
         }
         if (b.reqs.empty()) return false;
-        b.len = align_up(total);
+        // a batch of one runs lf_depth's launches directly: its own workspace only
+        b.len = align_up(b.reqs.size() == 1 ? b.reqs[0].bytes : total);
         if (!alloc(b.len, &b.off)) {   // cannot happen: total <= the largest extent
             for (auto r = b.reqs.rbegin(); r != b.reqs.rend(); ++r) pending.push_front(*r);
             b.reqs.clear();
             return false;
         }
+        large_inflight += b.large;
         b.id = next_batch++;
         const double t = now();
         for (Pending& r : b.reqs) {
@@ -210,16 +225,27 @@ struct lf_server {
                 return lf::record_error(LF_EDEVICE, "server stream wait: %s",
                                         hipGetErrorString(e));
         }
-        lf_status s = lf_plan_create(qs.data(), (int)qs.size(), (char*)cfg.arena + b.off, b.len,
-                                     &cfg.tuning, st, &b.plan);
-        if (s != LF_OK) return s;
-        if ((s = lf_plan_run(b.plan, st)) != LF_OK) return s;
+        void* ws = (char*)cfg.arena + b.off;
+        lf_status s = LF_OK;
+        if (b.reqs.size() == 1) {
+            // one light field: its launches directly, no plan tables to build or upload
+            const lf_request& q = b.reqs[0].q;
+            if ((s = lf_depth(&q.views, q.hyp, q.N, &q.params, q.disparity, q.d_index, ws,
+                              b.len, st)) != LF_OK)
+                return s;
+        } else {
+            if ((s = lf_plan_create(qs.data(), (int)qs.size(), ws, b.len, &cfg.tuning, st,
+                                    &b.plan)) != LF_OK)
+                return s;
+            if ((s = lf_plan_run(b.plan, st)) != LF_OK) return s;
+        }
         if (hipError_t e = hipEventRecord(events[b.slot], st); e != hipSuccess)
             return lf::record_error(LF_EDEVICE, "server event: %s", hipGetErrorString(e));
         return LF_OK;
     }
 
     void retire(Batch& b, int32_t status) {
+        large_inflight -= b.large;
         for (Pending& r : b.reqs) finish(r, status);
         if (b.plan) lf_plan_destroy(b.plan);
         b.plan = nullptr;
@@ -265,7 +291,7 @@ struct lf_server {
                 lk.lock();
                 if (s != LF_OK) {
                     // a batch that could not be enqueued completes at once with the error
-                    if (b.plan) {
+                    if (b.plan || b.reqs.size() == 1) {
                         // work may have been enqueued before the failure: wait for the stream
                         lk.unlock();
                         (void)hipStreamSynchronize(streams[b.slot]);
@@ -302,12 +328,15 @@ lf_status lf_server_create(const lf_server_config* cfg, lf_server** out) {
     if (!cfg->arena || (uintptr_t)cfg->arena % kAlign || cfg->arena_bytes < kAlign)
         return lf::record_error(LF_EINVAL, "%s", "arena NULL, unaligned or empty");
     if (cfg->max_batch < 1 || cfg->max_inflight < 1 || cfg->max_inflight > kMaxInflight ||
-        cfg->max_queue < 1 || cfg->group_ratio < 0 || cfg->group_ratio == 1)
+        cfg->max_queue < 1 || cfg->group_ratio < 0 || cfg->group_ratio == 1 ||
+        cfg->large_bytes < 0 || cfg->max_large < 0 || cfg->max_large > kMaxInflight)
         return lf::record_error(LF_EINVAL, "%s",
                                 "max_batch >= 1, 1 <= max_inflight <= 4, max_queue >= 1, "
-                                "group_ratio 0 or >= 2");
+                                "group_ratio 0 or >= 2, large_bytes >= 0, 0 <= max_large <= 4");
     lf_server* s = new lf_server();
     s->cfg = *cfg;
+    if (s->cfg.large_bytes == 0) s->cfg.large_bytes = (int64_t)256 << 20;
+    if (s->cfg.max_large == 0) s->cfg.max_large = 1;
     s->cfg.arena_bytes = cfg->arena_bytes / kAlign * kAlign;
     s->t0 = Clock::now();
     s->free_ext[0] = s->cfg.arena_bytes;

@@ -79,7 +79,8 @@ class Tuning(C.Structure):
 class ServerConfig(C.Structure):
     _fields_ = [("arena", C.c_void_p), ("arena_bytes", C.c_size_t), ("max_batch", C.c_int32),
                 ("max_inflight", C.c_int32), ("max_queue", C.c_int32),
-                ("group_ratio", C.c_int32), ("tuning", Tuning)]
+                ("group_ratio", C.c_int32), ("tuning", Tuning), ("large_bytes", C.c_int64),
+                ("max_large", C.c_int32)]
 
 
 class RequestInfo(C.Structure):
@@ -462,11 +463,12 @@ class Server:
     """The request loop (lf_server_*) over a device arena of `arena_bytes`."""
 
     def __init__(self, arena_bytes: int, device, max_batch=16, max_inflight=2, max_queue=1024,
-                 tuning: dict | None = None, arena=None, group_ratio=0):
+                 tuning: dict | None = None, arena=None, group_ratio=0, large_bytes=0,
+                 max_large=0):
         self.arena = arena if arena is not None else workspace(arena_bytes, device)
         t = make_tuning(tuning) or Tuning()
         cfg = ServerConfig(self.arena.data_ptr(), self.arena.numel(), max_batch, max_inflight,
-                           max_queue, group_ratio, t)
+                           max_queue, group_ratio, t, large_bytes, max_large)
         self._h = C.c_void_p()
         _check(lib.lf_server_create(C.byref(cfg), C.byref(self._h)))
         self._keep = {}

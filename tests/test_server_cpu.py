@@ -26,8 +26,10 @@ def _req(lf, S=5, T=5, H=32, W=40, N=16, data=FAKE, dtype=1, **prm):
     return lf.Request(vs, FAKE, N, lf.make_params(p), FAKE, 0)
 
 
-def _cfg(lf, arena=FAKE, nbytes=1 << 30, max_batch=4, max_inflight=2, max_queue=64, ratio=0):
-    return lf.ServerConfig(arena, nbytes, max_batch, max_inflight, max_queue, ratio, lf.Tuning())
+def _cfg(lf, arena=FAKE, nbytes=1 << 30, max_batch=4, max_inflight=2, max_queue=64, ratio=0,
+         large=0, max_large=0):
+    return lf.ServerConfig(arena, nbytes, max_batch, max_inflight, max_queue, ratio, lf.Tuning(),
+                           large, max_large)
 
 
 def _create(lf, cfg):
@@ -70,6 +72,7 @@ def test_plan_create_rejects_bad_input(lf):
 def test_server_config_checks(lf):
     for cfg in (_cfg(lf, arena=0), _cfg(lf, arena=FAKE + 8), _cfg(lf, max_batch=0),
                 _cfg(lf, max_inflight=5), _cfg(lf, max_queue=0), _cfg(lf, ratio=1),
+                _cfg(lf, large=-1), _cfg(lf, max_large=-1), _cfg(lf, max_large=5),
                 _cfg(lf, ratio=-2)):
         st, h = _create(lf, cfg)
         assert st == lf.LF_EINVAL and not h.value
