@@ -348,6 +348,17 @@ def _params(census=(5, 5), p_init=(10, 120), p_final=(10, 120), lam=2, phi=3, fi
                 cost_kind=cost_kind, median=median)
 
 
+def checkerboard_census_offsets(win_h, win_w):
+    """A sparse Census window (Sec. 3.2) as a neighbour list: the pixels of the
+    win_h x win_w window whose offsets (dy, dx) have an even sum, the centre left
+    out, in row-major order (24 comparisons for 7 x 7).  The paper's own sparse
+    7 x 7 pattern comes from another publication and is not reproduced here; this
+    one is a stand-in of the same size class."""
+    return [(i, j) for i in range(-(win_h // 2), win_h // 2 + 1)
+            for j in range(-(win_w // 2), win_w // 2 + 1)
+            if (i + j) % 2 == 0 and (i, j) != (0, 0)]
+
+
 def _small_plain(seed=1, H=96, W=96, S=5, T=5, N=32):
     scene = two_plane_scene(seed, H, W, S=S, T=T)
     views, gt = render(scene, S, T, dtype=np.uint8)

@@ -41,7 +41,8 @@ class _Params(C.Structure):
                 ("npaths", C.c_int), ("phi", C.c_int), ("lambda_", C.c_int),
                 ("fill_passes", C.c_int), ("lambda_far", C.c_int), ("channels", C.c_int),
                 ("edge_tau", C.c_float), ("alpha", C.c_float),
-                ("cost_kind", C.c_int), ("median", C.c_int), ("cost_cap", C.c_int32)]
+                ("cost_kind", C.c_int), ("median", C.c_int), ("cost_cap", C.c_int32),
+                ("n_offsets", C.c_int), ("off_dy", C.c_int * 64), ("off_dx", C.c_int * 64)]
 
 
 def lib():
@@ -66,12 +67,25 @@ def _i16(a):
 
 
 # --------------------------------------------------------------------- stages
-def census(img, win_h, win_w):
+def census(img, win_h, win_w, offsets=None):
+    """Census strings of one plane; offsets: a list of (dy, dx) neighbours (the
+    sparse window), else the dense win_h x win_w window."""
     img = _f32(img)
     H, W = img.shape
     out = np.zeros((H, W), dtype=np.uint64)
-    lib().lfo_census(_p(img), H, W, win_h, win_w, _p(out))
+    if offsets:
+        dy, dx = _offsets(offsets)
+        lib().lfo_census_offsets(_p(img), H, W, len(offsets), _p(dy), _p(dx), _p(out))
+    else:
+        lib().lfo_census(_p(img), H, W, win_h, win_w, _p(out))
     return out
+
+
+def _offsets(offsets):
+    o = np.asarray(offsets, dtype=np.int32).reshape(-1, 2)
+    if not 1 <= o.shape[0] <= 64:
+        raise ValueError("1..64 Census offsets")
+    return np.ascontiguousarray(o[:, 0]), np.ascontiguousarray(o[:, 1])
 
 
 def hamming(a, b):
@@ -253,6 +267,11 @@ def depth(views, hyp, params, want_intermediates=False, want_initial_volumes=Fal
                   pr.get("lam_far", 0), Cn,
                   pr["edge_tau"], pr["alpha"], pr["cost_kind"], pr["median"],
                   cost_cap(pr["P2_final"], pr["npaths"], pr["sum_bits"]))
+    if pr.get("census_offsets"):
+        dy, dx = _offsets(pr["census_offsets"])
+        prm.n_offsets = len(dy)
+        prm.off_dy[:len(dy)] = dy.tolist()
+        prm.off_dx[:len(dx)] = dx.tolist()
     nv = len(cross_views(S, T))
     disp = np.zeros((H, W), dtype=np.float32)
     idx = np.zeros((H, W), dtype=np.int16)

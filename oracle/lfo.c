@@ -41,6 +41,34 @@ void lfo_census(const float* img, int H, int W, int win_h, int win_w, uint64_t* 
     }
 }
 
+/* Sec. 3.2, sparse window: the same comparison of Eq. (3), over the listed
+ * neighbours only, bit n for the n-th entry of the list. */
+void lfo_census_offsets(const float* img, int H, int W, int n_off, const int* dy,
+                        const int* dx, uint64_t* out)
+{
+    for (int v = 0; v < H; ++v) {
+        for (int u = 0; u < W; ++u) {
+            float centre = img[(size_t)v * W + u];
+            uint64_t bits = 0;
+            for (int n = 0; n < n_off; ++n) {
+                int y = clampi(v + dy[n], 0, H - 1);
+                int x = clampi(u + dx[n], 0, W - 1);
+                if (centre > img[(size_t)y * W + x]) bits |= (uint64_t)1 << n;
+            }
+            out[(size_t)v * W + u] = bits;
+        }
+    }
+}
+
+/* Census of one plane with the window the parameters name. */
+static void census_of(const lfo_params* prm, const float* img, int H, int W, uint64_t* out)
+{
+    if (prm->n_offsets > 0)
+        lfo_census_offsets(img, H, W, prm->n_offsets, prm->off_dy, prm->off_dx, out);
+    else
+        lfo_census(img, H, W, prm->win_h, prm->win_w, out);
+}
+
 /* Eq. (5): number of differing bit positions. */
 int lfo_hamming(uint64_t a, uint64_t b)
 {
@@ -436,6 +464,7 @@ int lfo_depth(const float* views, int S, int T, int H, int W, const float* hyp, 
 {
     if (S < 1 || T < 1 || (S % 2) == 0 || (T % 2) == 0 || S * T < 2 || H < 1 || W < 1 || N < 2)
         return -1;
+    if (prm->n_offsets < 0 || prm->n_offsets > 64) return -1;
     const int C = prm->channels < 1 ? 1 : prm->channels;
     size_t plane = (size_t)H * W, vol = plane * N;
     int sh = (S - 1) / 2, th = (T - 1) / 2;
@@ -453,13 +482,12 @@ int lfo_depth(const float* views, int S, int T, int H, int W, const float* hyp, 
     int32_t* cpart = (int32_t*)malloc(vol * sizeof(int32_t));
     int64_t* csum = (int64_t*)malloc(vol * sizeof(int64_t));
     for (int ch = 0; ch < C; ++ch)
-        lfo_census(ref + ch * plane, H, W, prm->win_h, prm->win_w, cref + ch * plane);
+        census_of(prm, ref + ch * plane, H, W, cref + ch * plane);
     for (int i = 0; i < nv; ++i) {
         int s = vset[2 * i], t = vset[2 * i + 1];
         memset(cost, 0, vol * sizeof(int32_t));
         for (int ch = 0; ch < C; ++ch) {
-            lfo_census(views + (((size_t)t * S + s) * C + ch) * plane, H, W, prm->win_h,
-                       prm->win_w, cview);
+            census_of(prm, views + (((size_t)t * S + s) * C + ch) * plane, H, W, cview);
             lfo_cost_census_view(cref + ch * plane, cview, H, W, sh - s, th - t, hyp, N, cpart);
             for (size_t e = 0; e < vol; ++e) cost[e] += cpart[e];
         }
@@ -494,7 +522,7 @@ int lfo_depth(const float* views, int S, int T, int H, int W, const float* hyp, 
     } else {
         uint64_t* call = (uint64_t*)malloc((size_t)S * T * C * plane * sizeof(uint64_t));
         for (int v = 0; v < S * T * C; ++v)
-            lfo_census(views + (size_t)v * plane, H, W, prm->win_h, prm->win_w, call + (size_t)v * plane);
+            census_of(prm, views + (size_t)v * plane, H, W, call + (size_t)v * plane);
         lfo_cost_census_all(call, S, T, C, H, W, hyp, N, lo, hi, prm->cost_cap, cost);
         free(call);
     }

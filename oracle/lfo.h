@@ -34,6 +34,15 @@ extern "C" {
  * Window: win_h rows x win_w cols, both odd, win_h*win_w - 1 <= 64. */
 void lfo_census(const float* img, int H, int W, int win_h, int win_w, uint64_t* out);
 
+/* Census transform over a caller-given neighbour set (Sec. 3.2: a sparse window
+ * compares the centre with only some of the window's pixels): bit n (LSB first)
+ * compares the centre with the pixel at row offset dy[n], column offset dx[n]; 1
+ * iff centre > neighbour; clamped to the edge.  0 <= n_off <= 64.  The dense
+ * window is the special case of every offset of the window in row-major order,
+ * the centre skipped. */
+void lfo_census_offsets(const float* img, int H, int W, int n_off, const int* dy,
+                        const int* dx, uint64_t* out);
+
 /* Hamming distance, Eq. (5). */
 int lfo_hamming(uint64_t a, uint64_t b);
 
@@ -153,6 +162,9 @@ typedef struct {
     int cost_kind;            /* 0 = l2 (Eq. 12), 1 = Census (Eq. 15) */
     int median;               /* 0 = off, 3 = 3x3 */
     int32_t cost_cap;         /* quantisation cap of the final cost */
+    int n_offsets;            /* 0: the dense win_h x win_w window; 1..64: the sparse
+                                 neighbour set off_dy/off_dx (lfo_census_offsets) */
+    int off_dy[64], off_dx[64];
 } lfo_params;
 
 /* The whole method, Sec. 3.3-3.6.  Optional outputs may be NULL:

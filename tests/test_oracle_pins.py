@@ -54,6 +54,96 @@ def test_census_window_bits_and_orientation():
     assert int(lfo.census(img, 7, 9)[7, 7]) == 1 << 4
 
 
+def _window_offsets(win_h, win_w):
+    # the dense window as a neighbour list: row-major, the centre skipped (Eq. 2)
+    return [(i, j) for i in range(-(win_h // 2), win_h // 2 + 1)
+            for j in range(-(win_w // 2), win_w // 2 + 1) if (i, j) != (0, 0)]
+
+
+@pytest.mark.parametrize("win", [(3, 3), (5, 5), (7, 9), (1, 15), (9, 7)])
+def test_sparse_census_with_the_whole_window_is_the_dense_census(win):
+    # Sec. 3.2: a sparse window is a subset of the window's comparisons; with all
+    # of them, in the dense order, it must be the dense Census, on images with
+    # ties (8-bit values) and clamped borders.
+    img = rng.integers(0, 6, size=(13, 17)).astype(np.float32)
+    offs = _window_offsets(*win)
+    assert np.array_equal(lfo.census(img, win[0], win[1], offsets=offs),
+                          lfo.census(img, *win))
+
+
+def test_sparse_census_bits_follow_the_list():
+    # any subset of the window's offsets, in any order: bit n of the sparse string
+    # is the dense string's bit of the n-th listed offset.  A swapped dy/dx (the
+    # 7x9 window is not square), a flipped sign or an off-by-one order fails it.
+    img = rng.integers(0, 9, size=(21, 23)).astype(np.float32)
+    dense_list = _window_offsets(7, 9)
+    dense = lfo.census(img, 7, 9)
+    for trial in range(5):
+        pick = rng.permutation(len(dense_list))[: int(rng.integers(1, len(dense_list) + 1))]
+        offs = [dense_list[i] for i in pick]
+        sparse = lfo.census(img, 7, 9, offsets=offs)
+        want = np.zeros_like(dense)
+        for n, i in enumerate(pick):
+            want |= ((dense >> np.uint64(i)) & np.uint64(1)) << np.uint64(n)
+        assert np.array_equal(sparse, want)
+
+
+def test_sparse_census_hand_cases():
+    img = np.array([[1, 5, 2],
+                    [4, 3, 9],
+                    [7, 0, 8]], np.float32)
+    # one neighbour to the right: 1>5, 5>2, 2>2 (clamped) | 4>3, 3>9, 9>9 | 7>0, 0>8, 8>8
+    c = lfo.census(img, 3, 3, offsets=[(0, 1)])
+    assert c.astype(int).tolist() == [[0, 1, 0], [1, 0, 0], [1, 0, 0]]
+    # the list order sets the bit order: below first, then left
+    c = lfo.census(img, 3, 3, offsets=[(1, 0), (0, -1)])
+    # centre 3: below 0 -> bit 0 = 1; left 4 -> bit 1 = 0
+    assert int(c[1, 1]) == 0b01
+    # centre 9: below 8 -> 1; left 3 -> 1
+    assert int(c[1, 2]) == 0b11
+    # centre 5 (top middle): below 3 -> 1; left 1 -> 1
+    assert int(c[0, 1]) == 0b11
+    # centre 7 (bottom left): below is itself (clamped) -> 0; left is itself -> 0
+    assert int(c[2, 0]) == 0
+    # 64 offsets, the most a string holds: a spike sets all 64 bits
+    img = np.zeros((31, 31), np.float32)
+    img[15, 15] = 1.0
+    offs = [o for o in _window_offsets(15, 15) if (o[0] + o[1]) % 2 == 0][:64]
+    assert len(offs) == 64
+    assert int(lfo.census(img, 15, 15, offsets=offs)[15, 15]) == (1 << 64) - 1
+
+
+def test_depth_with_the_whole_window_as_a_list_equals_the_dense_window():
+    # the parameter path of lfo_depth: both stages' Census (initial, and Eq. (15)
+    # as the final cost) take the list when one is given
+    lf = lfsynth.workload("paper_s", seed=31, H=20, W=24, S=5, T=5, N=12)
+    for kind in (0, 1):
+        p = dict(lf.params, win_h=5, win_w=5, cost_kind=kind)
+        a = lfo.depth(lf.views, lf.hyp, p, want_intermediates=True)
+        b = lfo.depth(lf.views, lf.hyp, dict(p, census_offsets=_window_offsets(5, 5)),
+                      want_intermediates=True)
+        for k in ("maps", "dinit", "lo", "hi", "cost", "csum", "d_index", "disparity"):
+            assert np.array_equal(a[k], b[k]), (kind, k)
+        # a different list changes the result (the list is really used)
+        c = lfo.depth(lf.views, lf.hyp, dict(p, census_offsets=[(0, 1), (1, 0)]),
+                      want_intermediates=True)
+        assert not np.array_equal(a["maps"], c["maps"])
+
+
+def test_sparse_window_recovers_an_integer_plane():
+    # a checkerboard 7x7 pattern (24 of the 48 comparisons) still finds the true
+    # disparity of a fronto-parallel plane at an integer shift
+    S = T = 5
+    views = _shifted_lf(S, T, 36, 40, 1, seed=33)
+    hyp = lfsynth.hypotheses(-2, 2, 17)
+    prm = lfsynth._params(census=(7, 7), p_init=(10, 40), p_final=(10, 40))
+    prm["census_offsets"] = lfsynth.checkerboard_census_offsets(7, 7)
+    assert len(prm["census_offsets"]) == 24
+    out = lfo.depth(views, hyp, prm)
+    k = int(np.argmin(np.abs(hyp - 1)))
+    assert (out["d_index"][8:-8, 8:-8] == k).all()
+
+
 def test_hamming_matches_python_popcount():
     for _ in range(200):
         a, b = (int(x) for x in rng.integers(0, 2**63, size=2, dtype=np.int64))
