@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define LF_ABI_VERSION 4
+#define LF_ABI_VERSION 5
 #define LF_MAX_HYPOTHESES 256
 #define LF_MAX_SIDE 65536
 
@@ -76,11 +76,25 @@ typedef struct {
                            is the Euclidean norm of the colour difference) */
 } lf_view_set;
 
-/* Census window, Sec. 3.2 Eq. (2): win_h rows x win_w columns, both odd and at
- * most 15, win_h*win_w - 1 <= 64 bits; bit n (LSB first) is the n-th neighbour in
- * row-major order with the centre skipped, 1 iff centre > neighbour, Eq. (3);
- * neighbours outside the image are clamped to the edge. */
-typedef struct { int32_t win_h, win_w; } lf_census_window;
+/* Census window, Sec. 3.2 Eq. (2)-(3): win_h rows x win_w columns, both odd and
+ * at most 15.  Bit n of a pixel's string (LSB first) is 1 iff the centre is larger
+ * than its n-th neighbour, Eq. (3); neighbours outside the image are clamped to
+ * the edge.
+ *   n_offsets = 0: the dense window, win_h*win_w - 1 <= 64 neighbours in row-major
+ *     order with the centre skipped.
+ *   n_offsets = 1..LF_MAX_CENSUS_BITS: a sparse window (Sec. 3.2 notes that one
+ *     cuts the comparisons; Sec. 4.3 uses a sparse 7x7 one): neighbour n is at row
+ *     offset dy[n], column offset dx[n], with (dy, dx) != (0, 0), |dy| <= win_h/2
+ *     and |dx| <= win_w/2 (win_h x win_w bounds the pattern); entries from
+ *     n_offsets on are ignored.  Repeated offsets are allowed (equal bits).
+ * Invalid windows are rejected with LF_EINVAL (LF_EUNSUPPORTED for a side > 15). */
+#define LF_MAX_CENSUS_BITS 64
+typedef struct {
+    int32_t win_h, win_w;
+    int32_t n_offsets;
+    int8_t dy[LF_MAX_CENSUS_BITS];
+    int8_t dx[LF_MAX_CENSUS_BITS];
+} lf_census_window;
 
 /* SGM penalties of Eq. (8) (0 <= P1 <= P2 <= 16383) and the number of path
  * directions: 8 (the axis and diagonal neighbours) or 16 (those and the eight

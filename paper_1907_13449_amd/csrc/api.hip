@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -161,11 +162,19 @@ int channels_of(const lf_view_set* v) { return v->channels == 3 ? 3 : 1; }
 lf_status check_window(lf_census_window w) {
     if (w.win_h < 1 || w.win_w < 1 || w.win_h % 2 == 0 || w.win_w % 2 == 0)
         return fail(LF_EINVAL, "Census window %dx%d must be odd", w.win_h, w.win_w);
-    if (w.win_h * w.win_w - 1 > 64)
+    if (w.n_offsets < 0 || w.n_offsets > LF_MAX_CENSUS_BITS)
+        return fail(LF_EINVAL, "Census n_offsets=%d (0..%d)", w.n_offsets, LF_MAX_CENSUS_BITS);
+    if (w.n_offsets == 0 && w.win_h * w.win_w - 1 > 64)
         return fail(LF_EINVAL, "Census window %dx%d has more than 64 bits", w.win_h, w.win_w);
     if (w.win_h > 2 * lf::kMaxCensusRadius + 1 || w.win_w > 2 * lf::kMaxCensusRadius + 1)
         return fail(LF_EUNSUPPORTED, "Census window %dx%d (max side %d)", w.win_h, w.win_w,
                     2 * lf::kMaxCensusRadius + 1);
+    for (int n = 0; n < w.n_offsets; ++n) {
+        const int dy = w.dy[n], dx = w.dx[n];
+        if ((dy == 0 && dx == 0) || std::abs(dy) > w.win_h / 2 || std::abs(dx) > w.win_w / 2)
+            return fail(LF_EINVAL, "Census offset %d (%d,%d) outside the %dx%d window or at "
+                        "the centre", n, dy, dx, w.win_h, w.win_w);
+    }
     return LF_OK;
 }
 
@@ -225,7 +234,7 @@ size_t plan_initial(Carve& c, int S, int T, int C, int H, int W, int N, const lf
     InitPlan q;
     q.census = (uint64_t*)c.take((1 + nv) * C * HW * sizeof(uint64_t));
     q.paths = c.take(lf::sgm_dense_scratch_bytes(nv, H, W, N, prm->sgm_init.npaths,
-                                                 C * (prm->census.win_h * prm->census.win_w - 1),
+                                                 C * lf::census_bits(prm->census),
                                                  prm->sgm_init.P2));
     q.maps = (int16_t*)c.take(nv * HW * sizeof(int16_t));
     q.tmp = (int16_t*)c.take(HW * sizeof(int16_t));
@@ -511,7 +520,7 @@ lf_status lf_census(const void* img, int32_t dtype, int32_t H, int32_t W, int32_
     lf::Runner r;
     r.stream = stream;
     prof::Scope _ps(lf::kStCensus, r);
-    LF_HIP(lf::census_image(r, img, dtype, H, W, pitch, win.win_h, win.win_w, out), "lf_census");
+    LF_HIP(lf::census_image(r, img, dtype, H, W, pitch, win, out), "lf_census");
     return LF_OK;
 }
 

@@ -3,7 +3,9 @@
 // A 256-thread workgroup owns a 32 x 8 pixel tile.  It stages the tile plus the
 // window halo (clamp-to-edge) into LDS once, as float, with coalesced row loads,
 // then each thread compares its centre with the win_h*win_w - 1 neighbours in
-// row-major order (centre skipped), bit n = [centre > neighbour n].
+// row-major order (centre skipped), bit n = [centre > neighbour n] -- or, for a
+// sparse window, with the listed neighbours, whose positions in the window are
+// read by every lane from the launch record.
 #include "lf_internal.h"
 
 namespace lf {
@@ -21,6 +23,9 @@ struct CensusArgs {
     int H, W, pitch, win_h, win_w;
     int bx, by;               // tiles along x and y
     gptr<uint64_t> out;            // [n][H*W]
+    int ntap;                 // sparse window: neighbours listed (0: dense window)
+    uint8_t tap[LF_MAX_CENSUS_BITS];    // neighbour n: row (dy + win_h/2) in bits 0-3,
+                                        // column (dx + win_w/2) in bits 4-7
 };
 
 // The bit string of one pixel from its window in the LDS tile (win points at the
@@ -62,6 +67,26 @@ __device__ __forceinline__ uint64_t census_fixed(const float* win) {
     return ((uint64_t)hi << 32) | lo;
 }
 
+// The bit string over a listed neighbour set: bit n = [centre > neighbour n],
+// neighbour n at window row tap & 15, column tap >> 4 (rows tw apart).  The list
+// is uniform over the launch record: the taps and their offsets are scalar work.
+template <class A>
+__device__ __forceinline__ uint64_t census_listed(const float* win, const A& a, int tw,
+                                                  int ctr) {
+    const float c = win[ctr];
+    const int n = a.ntap, n0 = n < 32 ? n : 32;
+    uint32_t lo = 0, hi = 0;
+    for (int i = 0; i < n0; ++i) {
+        const int t = a.tap[i];
+        lo |= (c > win[(t & 15) * tw + (t >> 4)] ? 1u : 0u) << i;
+    }
+    for (int i = 32; i < n; ++i) {
+        const int t = a.tap[i];
+        hi |= (c > win[(t & 15) * tw + (t >> 4)] ? 1u : 0u) << (i - 32);
+    }
+    return ((uint64_t)hi << 32) | lo;
+}
+
 template <typename T, int WH, int WW>
 __device__ __forceinline__ void census_block(const CensusArgs& a, uint32_t b, float* tile) {
     const int per = a.bx * a.by;
@@ -89,11 +114,13 @@ __device__ __forceinline__ void census_block(const CensusArgs& a, uint32_t b, fl
     const float* win = tile + ly * tw + lx;
     uint64_t bits;
     if constexpr (WH > 0) bits = census_fixed<WH, WW>(win);
+    else if constexpr (WH < 0) bits = census_listed(win, a, tw, rh * tw + rw);
     else bits = census_any(win, a.win_h, a.win_w, tw);
     dst[(size_t)v * W + u] = bits;
 }
 
-// WH = WW = 0: any window (sizes from the arguments)
+// WH = WW = 0: any dense window (sizes from the arguments); -1: a listed
+// (sparse) neighbour set inside the win_h x win_w window
 template <class Src, typename T, int WH, int WW>
 __global__ __launch_bounds__(256) void census_kernel(Src src) {
     __shared__ float tile[(kBY + 2 * kMaxCensusRadius) * (kBX + 2 * kMaxCensusRadius)];
@@ -109,15 +136,20 @@ uint32_t census_blocks(const CensusArgs& a) {
     return (uint32_t)a.bx * a.by * a.n;
 }
 
-CensusArgs census_args(const void* base, int H, int W, int pitch, int win_h, int win_w,
+CensusArgs census_args(const void* base, int H, int W, int pitch, const lf_census_window& w,
                        uint64_t* out) {
     CensusArgs a{};
     a.base = base;
     a.H = H;
     a.W = W;
     a.pitch = pitch;
-    a.win_h = win_h;
-    a.win_w = win_w;
+    a.win_h = w.win_h;
+    a.win_w = w.win_w;
+    // offsets validated by the caller: |dy| <= win_h/2, |dx| <= win_w/2
+    const int rh = w.win_h / 2, rw = w.win_w / 2;
+    a.ntap = w.n_offsets;
+    for (int n = 0; n < w.n_offsets; ++n)
+        a.tap[n] = (uint8_t)((rh + w.dy[n]) | (rw + w.dx[n]) << 4);
     a.bx = (W + kBX - 1) / kBX;
     a.by = (H + kBY - 1) / kBY;
     a.out = out;
@@ -132,13 +164,17 @@ hipError_t census_variant(Runner& r, int stage, const std::vector<CensusArgs>& a
 }
 
 // One launch per input type and window size (the 5x5 and 7x9 windows of the
-// workloads compiled for their size, any other through the general loop).
+// workloads compiled for their size, any other dense window through the general
+// loop, listed neighbour sets through the tap loop).
 template <typename T>
 hipError_t census_windows(Runner& r, int stage, const std::vector<CensusArgs>& args) {
-    std::vector<CensusArgs> by[3];
-    std::vector<uint32_t> blocks[3];
+    std::vector<CensusArgs> by[4];
+    std::vector<uint32_t> blocks[4];
     for (const CensusArgs& a : args) {
-        const int w = a.win_h == 5 && a.win_w == 5 ? 0 : a.win_h == 7 && a.win_w == 9 ? 1 : 2;
+        const int w = a.ntap > 0                       ? 3
+                      : a.win_h == 5 && a.win_w == 5 ? 0
+                      : a.win_h == 7 && a.win_w == 9 ? 1
+                                                     : 2;
         by[w].push_back(a);
         blocks[w].push_back(census_blocks(a));
     }
@@ -147,7 +183,9 @@ hipError_t census_windows(Runner& r, int stage, const std::vector<CensusArgs>& a
         return e;
     if (!by[1].empty() && (e = census_variant<T, 7, 9>(r, stage, by[1], blocks[1])) != hipSuccess)
         return e;
-    if (!by[2].empty()) e = census_variant<T, 0, 0>(r, stage, by[2], blocks[2]);
+    if (!by[2].empty() && (e = census_variant<T, 0, 0>(r, stage, by[2], blocks[2])) != hipSuccess)
+        return e;
+    if (!by[3].empty()) e = census_variant<T, -1, -1>(r, stage, by[3], blocks[3]);
     return e;
 }
 
@@ -159,8 +197,8 @@ hipError_t launch_census(Runner& r, int stage, int dtype, const std::vector<Cens
 }  // namespace
 
 hipError_t census_image(Runner& r, const void* img, int dtype, int H, int W, int pitch,
-                        int win_h, int win_w, uint64_t* out) {
-    CensusArgs a = census_args(img, H, W, pitch, win_h, win_w, out);
+                        const lf_census_window& win, uint64_t* out) {
+    CensusArgs a = census_args(img, H, W, pitch, win, out);
     a.n = 1;
     a.off[0] = 0;
     return launch_census(r, kStCensus, dtype, {a});
@@ -173,8 +211,8 @@ hipError_t stage_census(Runner& r, const Jobs& jobs, bool all_views) {
         // view z / C (reference first, then the cross views; or all views)
         const int C = j->C;
         const int64_t ps = (int64_t)j->H * j->pitch;            // plane stride
-        CensusArgs a = census_args(j->views, j->H, j->W, j->pitch, j->prm.census.win_h,
-                                   j->prm.census.win_w, all_views ? j->census_all : j->census);
+        CensusArgs a = census_args(j->views, j->H, j->W, j->pitch, j->prm.census,
+                                   all_views ? j->census_all : j->census);
         if (all_views) {
             a.n = j->S * j->T * C;
             a.stride = ps;

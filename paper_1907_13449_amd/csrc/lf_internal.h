@@ -54,6 +54,12 @@ constexpr int kMaxCensusRadius = 7;      // windows up to 15 x 15
 constexpr int kPadH = 2, kPadW = 6;      // rows / columns added to the cost stage's view copy
 constexpr int kMaxBatchImages = 16;
 
+// Bits of a Census string with this window (the listed neighbours of a sparse
+// window, else every pixel of the dense window but the centre).
+inline int census_bits(const lf_census_window& w) {
+    return w.n_offsets > 0 ? w.n_offsets : w.win_h * w.win_w - 1;
+}
+
 __device__ __forceinline__ int clampi(int x, int lo, int hi) { return min(max(x, lo), hi); }
 
 // Loads one view sample as float (8-bit values convert exactly).
@@ -247,7 +253,7 @@ size_t scan_scratch_bytes(int64_t HW);
 hipError_t stage_census(Runner& r, const Jobs& jobs, bool all_views);
 // A standalone Census transform of one image.
 hipError_t census_image(Runner& r, const void* img, int dtype, int H, int W, int pitch,
-                        int win_h, int win_w, uint64_t* out);
+                        const lf_census_window& win, uint64_t* out);
 // Census cost + SGM + WTA over the cross views -> maps.
 // part 0: the Census cost volume, 1: the path costs, 2: their sum and the WTA
 hipError_t stage_sgm_initial(Runner& r, const Jobs& jobs, int part);

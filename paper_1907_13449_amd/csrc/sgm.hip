@@ -1102,7 +1102,7 @@ hipError_t stage_sgm_initial(Runner& r, const Jobs& jobs, int part) {
         const int H = j->H, W = j->W, N = j->N, NPc = dense_cvol_np(N);
         const size_t HW = (size_t)H * W;
         const lf_sgm_params& sp = j->prm.sgm_init;
-        const int bits = j->C * (j->prm.census.win_h * j->prm.census.win_w - 1);
+        const int bits = j->C * census_bits(j->prm.census);
         const int lt = bits + sp.P2 <= 255 ? 0 : 1;
         const int NP = dense_lnp(N, 1 << lt);
         uint8_t* cvol = (uint8_t*)j->paths;

@@ -47,8 +47,25 @@ class ViewSet(C.Structure):
                 ("channels", C.c_int32)]
 
 
+MAX_CENSUS_BITS = 64
+
+
 class CensusWindow(C.Structure):
-    _fields_ = [("win_h", C.c_int32), ("win_w", C.c_int32)]
+    _fields_ = [("win_h", C.c_int32), ("win_w", C.c_int32), ("n_offsets", C.c_int32),
+                ("dy", C.c_int8 * MAX_CENSUS_BITS), ("dx", C.c_int8 * MAX_CENSUS_BITS)]
+
+
+def census_window(win_h, win_w, offsets=None) -> CensusWindow:
+    """lf_census_window: the dense win_h x win_w window, or with `offsets` (a list
+    of up to 64 (dy, dx) pairs inside it) the sparse window of those neighbours."""
+    w = CensusWindow(win_h, win_w, 0)
+    if offsets:
+        if len(offsets) > MAX_CENSUS_BITS:
+            raise ValueError(f"at most {MAX_CENSUS_BITS} Census offsets")
+        w.n_offsets = len(offsets)
+        for n, (dy, dx) in enumerate(offsets):
+            w.dy[n], w.dx[n] = int(dy), int(dx)
+    return w
 
 
 class SgmParams(C.Structure):
@@ -164,8 +181,8 @@ def _dev(t, dtype, name):
     return t
 
 
-PARAM_KEYS = frozenset(("win_h", "win_w", "P1_init", "P2_init", "P1_final", "P2_final",
-                        "npaths", "phi", "lam", "fill_passes", "edge_tau", "alpha", "cost_kind",
+PARAM_KEYS = frozenset(("win_h", "win_w", "census_offsets", "P1_init", "P2_init", "P1_final",
+                        "P2_final", "npaths", "phi", "lam", "fill_passes", "edge_tau", "alpha", "cost_kind",
                         "median", "sum_bits", "lam_far"))
 
 
@@ -176,7 +193,7 @@ def make_params(p: dict) -> Params:
     unknown = set(p) - PARAM_KEYS
     if unknown:
         raise KeyError(f"unknown method parameters: {sorted(unknown)}")
-    return Params(CensusWindow(p["win_h"], p["win_w"]),
+    return Params(census_window(p["win_h"], p["win_w"], p.get("census_offsets")),
                   SgmParams(p["P1_init"], p["P2_init"], p["npaths"]),
                   SgmParams(p["P1_final"], p["P2_final"], p["npaths"]),
                   p["phi"], p["lam"], p["fill_passes"], float(p["edge_tau"]), float(p["alpha"]),
@@ -223,7 +240,8 @@ def validate_hypotheses(hyp_host) -> None:
 
 
 # ------------------------------------------------------------- entry points
-def lf_census(img: torch.Tensor, win_h: int, win_w: int, out=None, stream=None):
+def lf_census(img: torch.Tensor, win_h: int, win_w: int, out=None, stream=None,
+              offsets=None):
     if img.dim() != 2 or not img.is_cuda or not img.is_contiguous():
         raise ValueError("img: contiguous [H][W] CUDA tensor")
     dt = LF_U8 if img.dtype == torch.uint8 else LF_F32
@@ -232,7 +250,7 @@ def lf_census(img: torch.Tensor, win_h: int, win_w: int, out=None, stream=None):
     H, W = img.shape
     if out is None:
         out = torch.empty((H, W), dtype=torch.int64, device=img.device)
-    _check(lib.lf_census(_ptr(img), dt, H, W, W, CensusWindow(win_h, win_w), _ptr(out),
+    _check(lib.lf_census(_ptr(img), dt, H, W, W, census_window(win_h, win_w, offsets), _ptr(out),
                          _stream(stream)))
     return out
 

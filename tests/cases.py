@@ -111,14 +111,33 @@ def case(name):
         # N = 64, noise 0.01: the plenoptic shape of the large workload at reduced size
         return lfsynth.workload("paper_s", seed=4001, H=56, W=80, S=15, T=15, N=64,
                                 d_min=-1.5, d_max=1.5, noise=0.01)
+    if name == "sparse_7x7":                 # a sparse 7x7 Census window (Sec. 3.2, 4.3):
+        lf = lfsynth.workload("paper_s", seed=32, H=44, W=53, S=7, T=7, N=60)   # 24 bits
+        lf.params.update(win_h=7, win_w=7,
+                         census_offsets=lfsynth.checkerboard_census_offsets(7, 7))
+        return lf
+    if name == "sparse_64_census":           # 64 listed neighbours in a 15x15 window, in a
+        lf = lfsynth.workload("paper_s", seed=33, H=35, W=42, S=5, T=5, N=30)   # random
+        lf.params.update(win_h=15, win_w=15, cost_kind=1, sum_bits=32,  # order; Eq. (15)
+                         census_offsets=random_census_offsets(15, 15, 64, seed=33))  # final
+        return lf
     if name == "stage_s":                    # 1x11 u8 moving-stage light field, d in [0, 24],
         return lfsynth.workload("stage", H=270, W=480)   # N = 96, |V| = 2, shifts to 120 px
     raise KeyError(name)
 
 
+def random_census_offsets(win_h, win_w, n, seed):
+    """n distinct neighbours of the win_h x win_w window in a seeded random order."""
+    rng = np.random.default_rng(seed)
+    cells = [(i, j) for i in range(-(win_h // 2), win_h // 2 + 1)
+             for j in range(-(win_w // 2), win_w // 2 + 1) if (i, j) != (0, 0)]
+    return [cells[k] for k in rng.permutation(len(cells))[:n]]
+
+
 CASES = ["small", "f32_ragged", "u8_n65", "n256", "stage_1x11", "col_7x1", "one_row", "one_col",
          "u16_paths", "census_cost", "paths16", "paths16_u16", "boundless", "rgb_f32",
          "rgb_u8_census", "adaptive", "u8_inf_add", "fill_4", "fill_3_sparse", "u16_tail", "k3_u8",
-         "k4_u16", "k3_u16", "half_shifts", "plenoptic_s", "stage_s"]
+         "k4_u16", "k3_u16", "half_shifts", "plenoptic_s", "stage_s", "sparse_7x7",
+         "sparse_64_census"]
 
 

@@ -35,14 +35,16 @@ def test_library_exports_every_declared_symbol(lf):
     for name in declared_functions():
         assert hasattr(lf.lib, name), name
     assert set(declared_functions()) == set(lf.EXPORTS)
-    assert lf.lib.lf_abi_version() == 4
+    assert lf.lib.lf_abi_version() == 5
 
 
 def test_struct_layouts_match_header(lf):
     # lf_view_set: pointer + 7 int32 (+ 4 bytes of tail padding);
-    # lf_params: 2 + 3 + 3 + 3 int32 + 2 float + 4 int32
+    # lf_census_window: 3 int32 + 2 x 64 int8;
+    # lf_params: the window + 3 + 3 + 3 int32 + 2 float + 4 int32
     assert C.sizeof(lf.ViewSet) == 8 + 7 * 4 + 4
-    assert C.sizeof(lf.Params) == (2 + 3 + 3 + 3) * 4 + 2 * 4 + 4 * 4
+    assert C.sizeof(lf.CensusWindow) == 3 * 4 + 2 * 64
+    assert C.sizeof(lf.Params) == C.sizeof(lf.CensusWindow) + (3 + 3 + 3) * 4 + 2 * 4 + 4 * 4
 
 
 def test_validate_hypotheses(lf):
@@ -100,6 +102,47 @@ def test_params_rejected(lf, bad):
     st = lf.lib.lf_depth(C.byref(vs), C.c_void_p(0x1000), 8, C.byref(prm), C.c_void_p(0x1000),
                          None, C.c_void_p(0x1000), 1 << 40, None)
     assert st in (lf.LF_EINVAL, lf.LF_EUNSUPPORTED)
+
+
+def _depth_status(lf, prm):
+    # a workspace too small for anything: LF_ENOSPACE once the parameters pass
+    vs = lf.ViewSet(0x1000, 5, 5, 16, 16, 16, lf.LF_U8, 1)
+    return lf.lib.lf_depth(C.byref(vs), C.c_void_p(0x1000), 8, C.byref(prm), C.c_void_p(0x1000),
+                           None, C.c_void_p(0x1000), 1024, None)
+
+
+@pytest.mark.parametrize("win,offsets", [
+    ((5, 5), [(0, 0)]),                       # the centre
+    ((5, 5), [(3, 0)]),                       # outside the bounding window (rows)
+    ((5, 5), [(1, 1), (0, -3)]),              # outside (columns)
+    ((7, 9), [(0, 5)]),
+    ((4, 5), [(1, 1)]),                       # even side
+    ((17, 3), [(1, 1)]),                      # side > 15
+])
+def test_sparse_windows_rejected(lf, win, offsets):
+    prm = _params(lf, win_h=win[0], win_w=win[1], census_offsets=offsets)
+    assert _depth_status(lf, prm) in (lf.LF_EINVAL, lf.LF_EUNSUPPORTED)
+
+
+def test_sparse_window_bit_count(lf):
+    import lfsynth
+    # 65 listed neighbours is one too many (set directly: the binding refuses it)
+    prm = _params(lf, win_h=15, win_w=15)
+    prm.census.n_offsets = 65
+    assert _depth_status(lf, prm) == lf.LF_EINVAL
+    prm.census.n_offsets = -1
+    assert _depth_status(lf, prm) == lf.LF_EINVAL
+    with pytest.raises(ValueError):
+        lf.census_window(15, 15, [(0, 1)] * 65)
+    # a 15 x 15 bounding window (224 pixels) is fine with 64 listed neighbours,
+    # and so are repeated neighbours
+    offs = lfsynth.checkerboard_census_offsets(15, 15)[:64]
+    assert _depth_status(lf, _params(lf, win_h=15, win_w=15, census_offsets=offs)) == lf.LF_ENOSPACE
+    assert _depth_status(lf, _params(lf, census_offsets=[(1, 1)] * 3)) == lf.LF_ENOSPACE
+    # entries beyond n_offsets are ignored
+    prm = _params(lf, census_offsets=[(1, 1)])
+    prm.census.dy[5] = 100
+    assert _depth_status(lf, prm) == lf.LF_ENOSPACE
 
 
 def test_workspace_too_small_is_enospace(lf):

@@ -42,7 +42,7 @@ def say(*a):
     print(*a, flush=True)
 
 
-from cases import CASES, case as _case  # noqa: E402
+from cases import CASES, case as _case, random_census_offsets  # noqa: E402
 
 
 def _to_dev(lfd):
@@ -83,6 +83,38 @@ def test_census_bit_exact(lf, lfo, dtype, win):
     got = lf.lf_census(torch.from_numpy(img).cuda(), *win).cpu().numpy().view(np.uint64)
     ref = lfo.census(img.astype(np.float32), *win)
     assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("dtype", ["u8", "f32"])
+@pytest.mark.parametrize("pattern", ["checker_7x7", "random64_15x15", "whole_7x9", "one_3x1"])
+def test_census_sparse_bit_exact(lf, lfo, dtype, pattern):
+    # a listed neighbour set (sparse window, Sec. 3.2) against the oracle, and the
+    # whole window as a list against the dense kernel
+    win = {"checker_7x7": (7, 7), "random64_15x15": (15, 15), "whole_7x9": (7, 9),
+           "one_3x1": (3, 1)}[pattern]
+    if pattern == "checker_7x7":
+        offs = lfsynth.checkerboard_census_offsets(7, 7)
+    elif pattern == "random64_15x15":
+        offs = random_census_offsets(15, 15, 64, seed=5)
+    elif pattern == "whole_7x9":
+        offs = random_census_offsets(7, 9, 62, seed=0)
+        offs = sorted(offs)                          # row-major: the dense order
+    else:
+        offs = [(1, 0)]
+    rng = np.random.default_rng(len(offs))
+    H, W = 45, 77
+    img = rng.integers(0, 256, size=(H, W)).astype(np.uint8)
+    if dtype == "f32":
+        img = (img / 255.0).astype(np.float32)
+    img[10:14, 20:30] = img[10, 20]
+    say("census sparse", dtype, pattern)
+    dev = torch.from_numpy(img).cuda()
+    got = lf.lf_census(dev, *win, offsets=offs).cpu().numpy().view(np.uint64)
+    ref = lfo.census(img.astype(np.float32), *win, offsets=offs)
+    assert np.array_equal(got, ref)
+    if pattern == "whole_7x9":
+        dense = lf.lf_census(dev, *win).cpu().numpy().view(np.uint64)
+        assert np.array_equal(got, dense)
 
 
 @pytest.fixture(scope="module")
