@@ -26,6 +26,8 @@ Also in the same line (skip them with --no-quality / --no-batch / --no-large /
   batched  64 light fields mixing 5x5x256^2, 7x7x384^2 and 9x9x512^2 float32
            scenes with 32..128 hypotheses: one autotuned, graph-captured batch
            plan against the same 64 lf_depth calls one after another;
+  batched_benchmark_shape  the same for 8 light fields of the benchmark shape
+           (the benchmark scene plus seeded noise);
   large    2 x 15x15 views of 625x434 f32 (N = 64) with 2 x 1x11 views of
            1920x1080 u8 (N = 96): per shape and as one batch;
   served   Poisson arrivals (2,000 requests, 100 warm-up) drawn uniformly from the
@@ -406,10 +408,33 @@ def request_cells(lf, r):
 
 
 def run_batched(scenes, n, dev):
+    reqs = mixed_requests(scenes, n, 3, dev, cycle=True)
+    return time_batch(reqs, dev, f"{n} light fields: 5x5x256^2 / 7x7x384^2 / 9x9x512^2 f32, "
+                                 "N in 32..128")
+
+
+def run_batched_benchmark_shape(views, hyp, params, n, dev):
+    """n light fields of the benchmark shape (9x9x512^2 f32, N = 100) as one batch
+    against n lf_depth calls: the benchmark light field plus seeded Gaussian noise
+    (sigma 0.004) drawn on the GPU, so that no two members are equal."""
+    import torch
+    g = torch.Generator(device=dev)
+    g.manual_seed(2024)
+    reqs = []
+    for i in range(n):
+        v = (views + 0.004 * torch.randn(views.shape, generator=g, device=dev)).clamp_(0.0, 1.0)
+        reqs.append(dict(kind="paper", views=v, hyp=hyp, params=params))
+    return time_batch(reqs, dev, f"{n} light fields of 9x9x512^2 f32, N = 100 "
+                                 "(the benchmark scene with seeded noise)")
+
+
+def time_batch(reqs, dev, label):
+    """Plain (one lf_depth per light field, back to back on one stream) against one
+    autotuned, graph-captured plan over the same light fields."""
     import numpy as np
     import torch
     from paper_1907_13449_amd import lf
-    reqs = mixed_requests(scenes, n, 3, dev, cycle=True)
+    n = len(reqs)
     cells = sum(request_cells(lf, r) for r in reqs)
     outs = [torch.empty(r["views"].shape[2:], dtype=torch.float32, device=dev) for r in reqs]
     # plain: one lf_depth per light field, back to back on one stream, one workspace
@@ -453,7 +478,7 @@ def run_batched(scenes, n, dev):
     e1.record(stream)
     torch.cuda.synchronize()
     batch_ms = e0.elapsed_time(e1) / reps
-    res = {"workload": f"{n} light fields: 5x5x256^2 / 7x7x384^2 / 9x9x512^2 f32, N in 32..128",
+    res = {"workload": label,
            "light_fields": n, "cells": cells,
            "batched_ms": batch_ms, "plain_ms": plain_ms,
            "batched_gcells_s": cells / (batch_ms * 1e-3) / 1e9,
@@ -463,7 +488,7 @@ def run_batched(scenes, n, dev):
            "launches_per_batch": plan.launches, "tuning": tuning,
            "plan_setup_s": setup_s, "graph": True}
     plan.close()
-    log(f"[bench] batched {n}: {batch_ms:.2f} ms vs plain {plain_ms:.2f} ms "
+    log(f"[bench] batched {label}: {batch_ms:.2f} ms vs plain {plain_ms:.2f} ms "
         f"({plain_ms / batch_ms:.2f}x), identical={same}")
     return res
 
@@ -921,6 +946,8 @@ def main():
         scenes = mixed_scenes(lfd, dev)
     if not args.no_batch and scenes is not None:
         res["batched"] = run_batched(scenes, args.batch_n, dev)
+        res["batched_benchmark_shape"] = run_batched_benchmark_shape(views, hyp, p, 8, dev)
+        torch.cuda.empty_cache()
     if not args.no_large and args.workload == "paper":
         res["large"] = run_large(dev)
         torch.cuda.empty_cache()
