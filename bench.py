@@ -341,6 +341,33 @@ def quality_vs_boundless(lf, lfd, views, hyp, out, ms_bounded, cells_bounded, st
            "time_saved": 1.0 - ms_bounded / ms_free}
     log(f"[bench] bounded: BadPix {res['bounded']['badpix_0.07']:.2f} % in {ms_bounded:.2f} ms; "
         f"boundary-less: BadPix {res['boundless']['badpix_0.07']:.2f} % in {ms_free:.2f} ms")
+
+    # one reading or parameter of the bounded method changed at a time: what each
+    # costs or buys in accuracy, cells and time on this scene
+    variants = {"lambda_6": dict(lam=6), "lambda_10": dict(lam=10), "lambda_20": dict(lam=20),
+                "no_edge_exclusion": dict(edge_tau=float("inf")), "no_fill": dict(fill_passes=0),
+                "phi_1": dict(phi=1), "phi_8": dict(phi=8), "adaptive_lambda_far_8": dict(lam_far=8)}
+    abl = {}
+    for name, change in variants.items():
+        pv = dict(lfd.params, **change)
+        ws = lf.workspace(lf.depth_workspace_bytes(lfd.S, lfd.T, H, W, N, pv), views.device)
+        m = torch.empty_like(out)
+        lf.lf_depth(views, hyp, pv, ws=ws, out=m, stream=stream)
+        e0.record(stream)
+        for _ in range(steps):
+            lf.lf_depth(views, hyp, pv, ws=ws, out=m, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        ini = lf.lf_initial_disparity(views, hyp, pv, want_maps=False)
+        w = (ini["d_hi"].to(torch.int64) - ini["d_lo"].to(torch.int64) + 1)
+        shown = {k: (v if np.isfinite(v) else str(v)) for k, v in change.items()}   # JSON
+        abl[name] = dict(q(m.cpu().numpy(), ms), change=shown, final_cells=int(w.sum().item()),
+                         full_range_fraction=float((w == N).float().mean().item()))
+        del ws, ini, w
+    res["ablation"] = abl
+    log("[bench] ablation: " + ", ".join(f"{k} {v['badpix_0.07']:.2f} % / {v['ms']:.2f} ms"
+                                          for k, v in abl.items()))
     return res
 
 
