@@ -371,6 +371,59 @@ def quality_vs_boundless(lf, lfd, views, hyp, out, ms_bounded, cells_bounded, st
     return res
 
 
+def summarize_units(sq_csv, ta_csv, td_csv, commands):
+    """Markdown of per-kernel unit utilisation from three rocprofv3 --pmc runs:
+    SQ instruction and wave counters; TA_TA_BUSY_sum with GRBM_GUI_ACTIVE; TD_TD_BUSY_sum
+    with GRBM_GUI_ACTIVE.  The median over each kernel's dispatches; GRBM_GUI_ACTIVE
+    sums the 8 XCDs, so kernel cycles = GRBM_GUI_ACTIVE / 8; VALU busy = SQ_INSTS_VALU
+    x 4 cycles (a wave64 instruction on a 16-lane SIMD) / (1,024 SIMDs x cycles);
+    TA / TD busy = TA_TA_BUSY_sum / TD_TD_BUSY_sum / (256 CUs x cycles)."""
+    import csv
+    import statistics
+
+    def per_kernel(path):
+        vals = {}
+        for r in csv.DictReader(open(path)):
+            if "lf::" not in r["Kernel_Name"]:
+                continue
+            key = (r["Dispatch_Id"], r["Kernel_Name"], r["Counter_Name"])
+            vals[key] = vals.get(key, 0.0) + float(r["Counter_Value"])
+        acc = {}
+        for (d, n, c), v in vals.items():
+            acc.setdefault(_short_kernel(n)[0], {}).setdefault(c, []).append(v)
+        return {k: {c: statistics.median(v) for c, v in cs.items()} for k, cs in acc.items()}
+
+    sq, ta, td = per_kernel(sq_csv), per_kernel(ta_csv), per_kernel(td_csv)
+    rows = []
+    for k in sq:
+        cyc_ta = ta.get(k, {}).get("GRBM_GUI_ACTIVE", 0.0) / 8.0
+        cyc_td = td.get(k, {}).get("GRBM_GUI_ACTIVE", 0.0) / 8.0
+        if cyc_ta <= 0 or cyc_td <= 0:
+            continue
+        valu = sq[k].get("SQ_INSTS_VALU", 0.0)
+        rows.append((cyc_ta / 2.4e3, k, 100.0 * valu * 4 / (1024 * cyc_ta),
+                     100.0 * ta[k].get("TA_TA_BUSY_sum", 0.0) / (256 * cyc_ta),
+                     100.0 * td[k].get("TD_TD_BUSY_sum", 0.0) / (256 * cyc_td),
+                     sq[k].get("SQ_INSTS_VMEM_RD", 0.0) / 1e6, sq[k].get("SQ_INSTS_VMEM_WR", 0.0) / 1e6,
+                     valu / 1e6, sq[k].get("SQ_INSTS_SALU", 0.0) / 1e6))
+    md = ["Commands (from the repository root, one counter set per run, on one MI355X):", ""]
+    md += [f"    {c}" for c in commands]
+    md += ["", "Sources: " + ", ".join(f"{k} {v}" for k, v in current_sources().items()) +
+           " (sha256, 16 hex).", "",
+           "Normalisation (median over each kernel's dispatches): kernel cycles = "
+           "GRBM_GUI_ACTIVE / 8 (the counter sums the 8 XCDs); VALU busy = SQ_INSTS_VALU x 4 "
+           "cycles (a wave64 instruction on a 16-lane SIMD) / (1,024 SIMDs x kernel cycles); "
+           "TA / TD busy = TA_TA_BUSY_sum / TD_TD_BUSY_sum / (256 CUs x kernel cycles).  Time "
+           "is kernel cycles at 2.4 GHz under the profiler.", "",
+           "| kernel | us | VALU busy % | TA busy % | TD busy % | vector loads (M wave instr) "
+           "| vector stores (M) | VALU (M wave instr) | SALU (M) |",
+           "|---|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    for r in sorted(rows, reverse=True):
+        md.append(f"| {r[1]} | {r[0]:.0f} | {r[2]:.0f} | {r[3]:.0f} | {r[4]:.0f} | {r[5]:.2f} | "
+                  f"{r[6]:.2f} | {r[7]:.1f} | {r[8]:.1f} |")
+    return "\n".join(md)
+
+
 # --------------------------------------------------------------- batches
 def mixed_scenes(paper_lfd, dev):
     """Device-resident scenes of the batched and served workloads: the 9x9x512^2
@@ -761,11 +814,18 @@ def main():
                     metavar=("FETCH_CSV", "WRITE_CSV", "WORKLOAD", "OUT_PREFIX"),
                     help="write OUT_PREFIX.json/.md from two rocprofv3 --pmc runs "
                          "(FETCH_SIZE, WRITE_SIZE) of a --calib-copy run, and exit")
+    ap.add_argument("--summarize-units", nargs=4, metavar=("SQ_CSV", "TA_CSV", "TD_CSV", "TITLE"),
+                    help="print a markdown table of per-kernel unit utilisation from three "
+                         "rocprofv3 --pmc runs (see summarize_units) and exit")
     ap.add_argument("--commands", nargs="*", default=[],
-                    help="the rocprofv3 commands recorded with --summarize-counters")
+                    help="the rocprofv3 commands recorded with --summarize-counters / -units")
     args = ap.parse_args()
     if args.summarize_kernels:
         print(summarize_kernel_stats(*args.summarize_kernels))
+        return
+    if args.summarize_units:
+        sq, ta, td, title = args.summarize_units
+        print(f"# {title}\n\n" + summarize_units(sq, ta, td, args.commands))
         return
     if args.summarize_counters:
         fetch, write, name, out = args.summarize_counters
