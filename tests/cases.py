@@ -121,6 +121,13 @@ def case(name):
         lf.params.update(win_h=15, win_w=15, cost_kind=1, sum_bits=32,  # order; Eq. (15)
                          census_offsets=random_census_offsets(15, 15, 64, seed=33))  # final
         return lf
+    if name == "sparse_rgb":                 # colour u8 views, a sparse 5x5 window on both
+        lf = lfsynth.workload("paper_s", seed=34, H=29, W=38, S=5, T=5, N=36,   # stages
+                              channels=3)     # (Census per channel, Eq. (15) final cost)
+        lf.views = np.clip(np.rint(lf.views * 255.0), 0, 255).astype(np.uint8)
+        lf.params.update(win_h=5, win_w=5, cost_kind=1, sum_bits=16, alpha=1.0, edge_tau=60.0,
+                         census_offsets=lfsynth.checkerboard_census_offsets(5, 5))
+        return lf
     if name == "stage_s":                    # 1x11 u8 moving-stage light field, d in [0, 24],
         return lfsynth.workload("stage", H=270, W=480)   # N = 96, |V| = 2, shifts to 120 px
     raise KeyError(name)
@@ -138,6 +145,6 @@ CASES = ["small", "f32_ragged", "u8_n65", "n256", "stage_1x11", "col_7x1", "one_
          "u16_paths", "census_cost", "paths16", "paths16_u16", "boundless", "rgb_f32",
          "rgb_u8_census", "adaptive", "u8_inf_add", "fill_4", "fill_3_sparse", "u16_tail", "k3_u8",
          "k4_u16", "k3_u16", "half_shifts", "plenoptic_s", "stage_s", "sparse_7x7",
-         "sparse_64_census"]
+         "sparse_64_census", "sparse_rgb"]
 
 
