@@ -31,6 +31,27 @@ def test_header_declares_the_six_calls_and_helpers():
         assert n in names
 
 
+def _doc_before(text, name):
+    # the comment block that precedes the declaration of `name`
+    i = text.index(name + "(")
+    j = text.rindex("/*", 0, i)
+    return " ".join(text[j:i].split())
+
+
+def test_header_states_the_bounds_contract():
+    # lf_sgm_aggregate and lf_wta_subpixel read device-side bounds and offsets that
+    # the host cannot check: their contract (and what the kernels do on a breach)
+    # is part of the interface
+    text = open(HEADER).read()
+    agg = _doc_before(text, "lf_status lf_sgm_aggregate")
+    assert "0 <= d_lo[p] <= d_hi[p] < N" in agg
+    assert "exclusive prefix sum of d_hi - d_lo + 1" in agg
+    assert "clamp the count to H*W*N" in agg
+    wta = _doc_before(text, "lf_status lf_wta_subpixel")
+    assert "Bounds contract as for lf_sgm_aggregate" in wta
+    assert "clamped" in wta
+
+
 def test_library_exports_every_declared_symbol(lf):
     for name in declared_functions():
         assert hasattr(lf.lib, name), name
