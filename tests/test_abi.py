@@ -35,7 +35,8 @@ def _doc_before(text, name):
     # the comment block that precedes the declaration of `name`
     i = text.index(name + "(")
     j = text.rindex("/*", 0, i)
-    return " ".join(text[j:i].split())
+    lines = [ln.strip().lstrip("*").strip() for ln in text[j:i].splitlines()]
+    return " ".join(" ".join(lines).split())
 
 
 def test_header_states_the_bounds_contract():
