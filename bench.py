@@ -424,6 +424,63 @@ def summarize_units(sq_csv, ta_csv, td_csv, commands):
     return "\n".join(md)
 
 
+def summarize_plan_gaps(trace_csv, command):
+    """Markdown of a rocprofv3 --kernel-trace of --replay-plan: per replay of the
+    captured plan, its liblf kernels, the span from the first start to the last
+    end, and the time within it when none of them ran."""
+    import csv
+    rows = [r for r in csv.DictReader(open(trace_csv)) if "lf::" in r["Kernel_Name"]]
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    runs, cur = [], [rows[0]]
+    for a, b in zip(rows, rows[1:]):       # replays are separated by host sleeps
+        if int(b["Start_Timestamp"]) - int(a["End_Timestamp"]) > 5_000_000:
+            runs.append(cur)
+            cur = []
+        cur.append(b)
+    runs.append(cur)
+    md = ["Command (from the repository root, on one MI355X):", "", f"    {command}", "",
+          "Sources: " + ", ".join(f"{k} {v}" for k, v in current_sources().items()) +
+          " (sha256, 16 hex).", "",
+          "| replay | kernels | span ms | kernels running ms | idle ms |", "|---:|---:|---:|---:|---:|"]
+    for i, run in enumerate(runs):
+        t0 = int(run[0]["Start_Timestamp"])
+        t1 = max(int(r["End_Timestamp"]) for r in run)
+        busy, last = 0, t0
+        for r in run:
+            s, e = int(r["Start_Timestamp"]), int(r["End_Timestamp"])
+            if e > last:
+                busy += e - max(s, last)
+                last = e
+        md.append(f"| {i} | {len(run)} | {(t1 - t0) / 1e6:.3f} | {busy / 1e6:.3f} | "
+                  f"{(t1 - t0 - busy) / 1e6:.3f} |")
+    return "\n".join(md)
+
+
+def replay_plan(dev, n=64, replays=3):
+    """The batched workload's plan (fixed tuning), captured and replayed `replays`
+    times with a host sleep between replays (for a kernel trace of the replays)."""
+    import torch
+    import lfsynth
+    from paper_1907_13449_amd import lf
+    scenes = mixed_scenes(lfsynth.workload("paper"), dev)
+    reqs = mixed_requests(scenes, n, 3, dev, cycle=True)
+    outs = [torch.empty(r["views"].shape[2:], dtype=torch.float32, device=dev) for r in reqs]
+    plan = lf.Plan([(r["views"], r["hyp"], r["params"], o, None) for r, o in zip(reqs, outs)],
+                   tuning=dict(cost_cells_per_thread=4, cost_stride=1, dense_prefetch=16,
+                               bounded_prefetch=16, bounded_lanes=32))
+    plan.capture()
+    stream = torch.cuda.current_stream()
+    for _ in range(2):
+        plan.run(stream)
+    torch.cuda.synchronize()
+    for _ in range(replays):
+        time.sleep(0.02)
+        plan.run(stream)
+        torch.cuda.synchronize()
+    log(f"[bench] replayed the {n}-light-field plan {replays} times ({plan.launches} launches)")
+    plan.close()
+
+
 # --------------------------------------------------------------- batches
 def mixed_scenes(paper_lfd, dev):
     """Device-resident scenes of the batched and served workloads: the 9x9x512^2
@@ -814,6 +871,10 @@ def main():
                     metavar=("FETCH_CSV", "WRITE_CSV", "WORKLOAD", "OUT_PREFIX"),
                     help="write OUT_PREFIX.json/.md from two rocprofv3 --pmc runs "
                          "(FETCH_SIZE, WRITE_SIZE) of a --calib-copy run, and exit")
+    ap.add_argument("--replay-plan", action="store_true",
+                    help="only build the batched workload's plan and replay it 3 times")
+    ap.add_argument("--summarize-plan-gaps", nargs=2, metavar=("TRACE_CSV", "COMMAND"),
+                    help="print a markdown summary of a kernel trace of --replay-plan and exit")
     ap.add_argument("--summarize-units", nargs=4, metavar=("SQ_CSV", "TA_CSV", "TD_CSV", "TITLE"),
                     help="print a markdown table of per-kernel unit utilisation from three "
                          "rocprofv3 --pmc runs (see summarize_units) and exit")
@@ -822,6 +883,9 @@ def main():
     args = ap.parse_args()
     if args.summarize_kernels:
         print(summarize_kernel_stats(*args.summarize_kernels))
+        return
+    if args.summarize_plan_gaps:
+        print(summarize_plan_gaps(*args.summarize_plan_gaps))
         return
     if args.summarize_units:
         sq, ta, td, title = args.summarize_units
@@ -847,6 +911,9 @@ def main():
     from paper_1907_13449_amd import lf
 
     dev = torch.device("cuda:0")
+    if args.replay_plan:
+        replay_plan(dev)
+        return
     t0 = time.perf_counter()
     lfd = lfsynth.workload(args.workload)
     log(f"[bench] scene {lfd.name} generated in {time.perf_counter() - t0:.1f}s")
