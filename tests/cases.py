@@ -128,6 +128,16 @@ def case(name):
         lf.params.update(win_h=5, win_w=5, cost_kind=1, sum_bits=16, alpha=1.0, edge_tau=60.0,
                          census_offsets=lfsynth.checkerboard_census_offsets(5, 5))
         return lf
+    if name == "n2_tiny":                    # N = 2, the fewest hypotheses; a 3x3 light
+        lf = lfsynth.workload("paper_s", seed=35, H=13, W=70, S=3, T=3, N=2,    # field
+                              d_min=-1.0, d_max=1.0)
+        lf.params.update(win_h=3, win_w=3, lam=0, phi=1)
+        return lf
+    if name == "n3_16paths":                 # N = 3 with 16 paths and 16-bit sums
+        lf = lfsynth.workload("paper_s", seed=36, H=17, W=22, S=3, T=3, N=3,
+                              d_min=-1.0, d_max=1.0)
+        lf.params.update(npaths=16, sum_bits=16, lam=1)
+        return lf
     if name == "stage_s":                    # 1x11 u8 moving-stage light field, d in [0, 24],
         return lfsynth.workload("stage", H=270, W=480)   # N = 96, |V| = 2, shifts to 120 px
     raise KeyError(name)
@@ -145,6 +155,6 @@ CASES = ["small", "f32_ragged", "u8_n65", "n256", "stage_1x11", "col_7x1", "one_
          "u16_paths", "census_cost", "paths16", "paths16_u16", "boundless", "rgb_f32",
          "rgb_u8_census", "adaptive", "u8_inf_add", "fill_4", "fill_3_sparse", "u16_tail", "k3_u8",
          "k4_u16", "k3_u16", "half_shifts", "plenoptic_s", "stage_s", "sparse_7x7",
-         "sparse_64_census", "sparse_rgb"]
+         "sparse_64_census", "sparse_rgb", "n2_tiny", "n3_16paths"]
 
 
