@@ -318,7 +318,7 @@ typedef struct {
  * slices each cost workgroup walks (persistent workgroups); dense_prefetch: 4, 8
  * or 16 (default) -- path steps of cost loads in flight per wave in the initial
  * SGM, also the steps whose path costs it stages before copying them out;
- * bounded_prefetch: 4, 8 or 16 (default) -- pixel metadata steps in flight
+ * bounded_prefetch: 4, 8 (default) or 16 -- pixel metadata steps in flight
  * per wave in the bounded SGM with 64 lanes per line (their costs run half as
  * many steps ahead); bounded_lanes: 16, 32 or 64 (default) -- lanes per path line
  * of the bounded SGM (the wavefront-to-path schedule: 64/bounded_lanes lines per

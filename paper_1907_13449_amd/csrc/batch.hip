@@ -232,6 +232,7 @@ lf_status lf_plan_autotune(lf_plan* p, hipStream_t stream, int32_t reps, lf_tuni
     double best_cost = 1e30, best_dense = 1e30, best_bounded = 1e30;
     lf::Tuning best = p->tune;
     best.cost_stride = 1;
+    best.bounded_depth = lf::Tuning{}.bounded_depth;   // the depth phase 1 runs at
     lf_status s = LF_OK;
     for (int i = 0; i < 3 && s == LF_OK; ++i) {
         lf::Tuning t;
@@ -239,7 +240,6 @@ lf_status lf_plan_autotune(lf_plan* p, hipStream_t stream, int32_t reps, lf_tuni
         t.cost_stride = 1;
         t.dense_depth = dd[i];
         t.bounded_lanes = bl[i];
-        t.bounded_depth = 16;
         double ms[lf::kNumStages];
         if ((s = measure(t, ms)) != LF_OK) break;
         if (ms[lf::kStCost] < best_cost) best_cost = ms[lf::kStCost], best.cost_cpt = cpt[i];
@@ -256,6 +256,18 @@ lf_status lf_plan_autotune(lf_plan* p, hipStream_t stream, int32_t reps, lf_tuni
         double ms[lf::kNumStages];
         if ((s = measure(t, ms)) != LF_OK) break;
         if (ms[lf::kStCost] < best_cost) best_cost = ms[lf::kStCost], best.cost_stride = stride;
+    }
+    // Phase 3: the other prefetch depths of the bounded SGM with one line per wave.
+    const int depth0 = best.bounded_depth;
+    for (int depth : {4, 8, 16}) {
+        if (s != LF_OK || best.bounded_lanes != 64) break;
+        if (depth == depth0) continue;
+        lf::Tuning t = best;
+        t.bounded_depth = depth;
+        double ms[lf::kNumStages];
+        if ((s = measure(t, ms)) != LF_OK) break;
+        if (ms[lf::kStSgmFinal] < best_bounded)
+            best_bounded = ms[lf::kStSgmFinal], best.bounded_depth = depth;
     }
     for (hipEvent_t e : ev) (void)hipEventDestroy(e);
     if (s != LF_OK) return s;

@@ -138,7 +138,7 @@ struct Tuning {
     int cost_cpt = 2;        // cells per thread of the bounded cost kernel (2, 4, 8)
     int cost_stride = 1;     // slices walked per cost workgroup (1, 2, 4)
     int dense_depth = 16;    // steps prefetched by the initial-stage SGM (4, 8, 16)
-    int bounded_depth = 16;  // steps prefetched by the bounded SGM, 64 lanes per line (4, 8, 16)
+    int bounded_depth = 8;   // steps prefetched by the bounded SGM, 64 lanes per line (4, 8, 16)
     int bounded_lanes = 64;  // lanes per path line of the bounded SGM (16, 32, 64)
 };
 

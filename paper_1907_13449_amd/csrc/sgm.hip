@@ -686,25 +686,81 @@ __global__ __launch_bounds__(256) void pix_meta_kernel(Src src) {
     }
 }
 
+// Work units of the 64-lane bounded SGM, one wave each.  Besides |W - H| + 1
+// lines of length M = min(H, W), a diagonal direction (|du| = |dv| = 1) has one
+// line of each length 1 .. M - 1 among its entry-row lines and one among its
+// entry-column lines.  Its units are the full lines alone and the pairs of
+// lengths m and M - m, run one after the other: every unit is M steps long, so
+// all the waves of the launch have the same work and none is left running
+// alone at the end.  Any other direction has one unit per line.
+__host__ __device__ inline bool paired_dir(int du, int dv) {
+    return (du == 1 || du == -1) && (dv == 1 || dv == -1);
+}
+
+__host__ __device__ inline int num_units(int H, int W, int du, int dv) {
+    return paired_dir(du, dv) ? max(H, W) : num_lines(H, W, du, dv);
+}
+
+struct Units {
+    int base[kMaxPaths + 1];       // direction r owns units [base[r], base[r+1])
+    int nunits;
+};
+
+Units make_units(const Lines& L, int H, int W) {
+    Units U{};
+    for (int r = 0; r < L.npaths; ++r)
+        U.base[r + 1] = U.base[r] + num_units(H, W, L.du[r], L.dv[r]);
+    U.nunits = U.base[L.npaths];
+    return U;
+}
+
+// The global lines of unit u (wave-uniform): line[0], and line[1] or -1.  In a
+// diagonal direction, entry-row line j is min(W - j', H) long, j' = j for du > 0
+// and W - 1 - j for du < 0, and entry-column line i (index W + i within the
+// direction) min(W, H - 1 - i).
+__device__ __forceinline__ void unit_lines(const Lines& L, const Units& U, int H, int W, int u,
+                                           int (&line)[2]) {
+    int r = 0, ub = 0, lb = 0, du = L.du[0], dv = L.dv[0];
+#pragma unroll
+    for (int i = 1; i < kMaxPaths; ++i)    // constant indices: the record stays in registers
+        if (i < L.npaths && u >= U.base[i]) {
+            r = i;
+            ub = U.base[i];
+            lb = L.base[i];
+            du = L.du[i];
+            dv = L.dv[i];
+        }
+    const int x = u - ub;
+    int first = x, second = -1;
+    if (paired_dir(du, dv)) {
+        if (x < W && du < 0) first = W - 1 - x;        // the row line of length min(W - x, H)
+        if (W >= H) {
+            if (x > W - H) second = 2 * W - 1 - x;      // lengths W - x and H - (W - x)
+        } else if (x >= 1 && x < W) {
+            second = W + H - 1 - x;                    // lengths W - x and x
+        }                                              // x >= W: a full column line
+    }
+    line[0] = lb + first;
+    line[1] = second < 0 ? -1 : lb + second;
+}
+
 struct BoundedArgs {
     gptr<const uint16_t> cost;
     gptr<const PixMeta> meta;
     gptr<uint16_t> Lbuf;           // [npaths][dir_stride]
     size_t dir_stride;
     Lines lines;
+    Units units;                   // of the 64-lane kernel
     int H, W, N;
     uint32_t P1, P2;
 };
 
 template <int K, int D>
-__device__ __forceinline__ void bounded_wave(const BoundedArgs& a, uint32_t b) {
+__device__ __forceinline__ void bounded_line(const BoundedArgs& a, const LineInfo& li) {
     constexpr int kMeta = D, kCost = D / 2;   // two-stage prefetch
     const int lane = threadIdx.x & 63;
-    const int g = __builtin_amdgcn_readfirstlane(b * kWavesPerBlock + (threadIdx.x >> 6));
-    if (g >= a.lines.nlines) return;
-    const int H = a.H, W = a.W;
+    const int W = a.W;
     const uint32_t P1 = a.P1, P2 = a.P2;
-    const LineInfo li = locate(a.lines, H, W, g);
     const uint16_t* __restrict__ cost = a.cost;
     const PixMeta* __restrict__ meta = a.meta;
     uint16_t* __restrict__ out = a.Lbuf + (size_t)li.r * a.dir_stride;
@@ -774,7 +830,14 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void sgm_bounded_paths_kernel(
     for (uint32_t vb = blockIdx.x; vb < src.total; vb += gridDim.x) {
         uint32_t b;
         const BoundedArgs& a = member(src, vb, b);
-        bounded_wave<K, D>(a, b);
+        const int u = __builtin_amdgcn_readfirstlane(b * kWavesPerBlock + (threadIdx.x >> 6));
+        if (u >= a.units.nunits) continue;            // wave-uniform
+        int line[2];
+        unit_lines(a.lines, a.units, a.H, a.W, u, line);
+        for (int part = 0; part < 2; ++part) {        // one copy of the line loop
+            if (line[part] < 0) break;
+            bounded_line<K, D>(a, locate(a.lines, a.H, a.W, line[part]));
+        }
     }
 }
 
@@ -1261,6 +1324,7 @@ hipError_t stage_sgm_final(Runner& r, const Jobs& jobs) {
         b.Lbuf = Lbuf;
         b.dir_stride = dir_stride;
         b.lines = make_lines(H, W, sp.npaths);
+        b.units = make_units(b.lines, H, W);
         b.H = H;
         b.W = W;
         b.N = N;
@@ -1271,7 +1335,7 @@ hipError_t stage_sgm_final(Runner& r, const Jobs& jobs) {
         } else {
             const int K = (N + 63) / 64 - 1;
             paths[K].push_back(b);
-            path_blocks[K].push_back(div_up(b.lines.base[b.lines.npaths], kWavesPerBlock));
+            path_blocks[K].push_back(div_up(b.units.nunits, kWavesPerBlock));
         }
 
         BsumArgs s{};
