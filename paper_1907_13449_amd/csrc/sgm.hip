@@ -127,6 +127,64 @@ __device__ __forceinline__ LineInfo locate(const Lines& L, int H, int W, int g) 
     return li;
 }
 
+// Work units of the path kernels with one line per wave.  Besides |W - H| + 1
+// lines of length M = min(H, W), a diagonal direction (|du| = |dv| = 1) has one
+// line of each length 1 .. M - 1 among its entry-row lines and one among its
+// entry-column lines.  Its units are the full lines alone and the pairs of
+// lengths m and M - m, run one after the other: every unit is M steps long, so
+// all the waves of the launch have the same work and none is left running
+// alone at the end.  Any other direction has one unit per line.
+__host__ __device__ inline bool paired_dir(int du, int dv) {
+    return (du == 1 || du == -1) && (dv == 1 || dv == -1);
+}
+
+__host__ __device__ inline int num_units(int H, int W, int du, int dv) {
+    return paired_dir(du, dv) ? max(H, W) : num_lines(H, W, du, dv);
+}
+
+struct Units {
+    int base[kMaxPaths + 1];       // direction r owns units [base[r], base[r+1])
+    int nunits;
+};
+
+Units make_units(const Lines& L, int H, int W) {
+    Units U{};
+    for (int r = 0; r < L.npaths; ++r)
+        U.base[r + 1] = U.base[r] + num_units(H, W, L.du[r], L.dv[r]);
+    U.nunits = U.base[L.npaths];
+    return U;
+}
+
+// The global lines of unit u (wave-uniform): line[0], and line[1] or -1.  In a
+// diagonal direction, entry-row line j is min(W - j', H) long, j' = j for du > 0
+// and W - 1 - j for du < 0, and entry-column line i (index W + i within the
+// direction) min(W, H - 1 - i).
+__device__ __forceinline__ void unit_lines(const Lines& L, const Units& U, int H, int W, int u,
+                                           int (&line)[2]) {
+    int r = 0, ub = 0, lb = 0, du = L.du[0], dv = L.dv[0];
+#pragma unroll
+    for (int i = 1; i < kMaxPaths; ++i)    // constant indices: the record stays in registers
+        if (i < L.npaths && u >= U.base[i]) {
+            r = i;
+            ub = U.base[i];
+            lb = L.base[i];
+            du = L.du[i];
+            dv = L.dv[i];
+        }
+    const int x = u - ub;
+    int first = x, second = -1;
+    if (paired_dir(du, dv)) {
+        if (x < W && du < 0) first = W - 1 - x;        // the row line of length min(W - x, H)
+        if (W >= H) {
+            if (x > W - H) second = 2 * W - 1 - x;      // lengths W - x and H - (W - x)
+        } else if (x >= 1 && x < W) {
+            second = W + H - 1 - x;                    // lengths W - x and x
+        }                                              // x >= W: a full column line
+    }
+    line[0] = lb + first;
+    line[1] = second < 0 ? -1 : lb + second;
+}
+
 constexpr int kWavesPerBlock = 4;
 
 size_t round256(size_t x) { return (x + 255) / 256 * 256; }
@@ -282,6 +340,7 @@ struct DenseArgs {
     gptr<const uint8_t> cvol;      // [nv][H*W][NPc]
     gptr<void> Lbuf;
     Lines lines;
+    Units units;
     int nv, H, W, N, NP, NPc;
     uint32_t P1, P2;
     uint32_t wblocks;         // blocks per view
@@ -339,17 +398,13 @@ __device__ __forceinline__ void stage_put(uint8_t* dst, const uint32_t (&L)[K]) 
 // tails: 16 rows of 100 bytes are three store instructions.  Row elements
 // k >= N hold don't-care values.
 template <int K, typename LT, int D, bool kPad>
-__device__ __forceinline__ void dense_wave(const DenseArgs& a, uint32_t b, uint8_t* wst) {
+__device__ __forceinline__ void dense_line(const DenseArgs& a, int z, const LineInfo& li,
+                                           uint8_t* wst) {
     constexpr int kRow = dense_stage_row(K, sizeof(LT));    // staged bytes per step
     constexpr int kRounds = (D * kRow / 16 + 63) / 64;      // 16-byte copies per lane
     const int lane = threadIdx.x & 63;
-    const int z = (int)(b / a.wblocks);
-    const uint32_t wb = b - (uint32_t)z * a.wblocks;
-    const int g = __builtin_amdgcn_readfirstlane(wb * kWavesPerBlock + (threadIdx.x >> 6));
-    if (g >= a.lines.nlines) return;                      // wave-uniform exit
     const int H = a.H, W = a.W, N = a.N, NPc = a.NPc;
     const uint32_t P1 = a.P1, P2 = a.P2;
-    const LineInfo li = locate(a.lines, H, W, g);
     const uint32_t HW = (uint32_t)H * W;
     const uint8_t* __restrict__ cz = a.cvol + (size_t)z * HW * NPc;
     const int rb = a.NP * (int)sizeof(LT);                  // bytes per path-cost row
@@ -505,7 +560,16 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void sgm_dense_paths_kernel(Sr
     for (uint32_t vb = blockIdx.x; vb < src.total; vb += gridDim.x) {
         uint32_t b;
         const DenseArgs& a = member(src, vb, b);
-        dense_wave<K, LT, D, kPad>(a, b, wst);
+        const int z = (int)(b / a.wblocks);               // the view
+        const uint32_t wb = b - (uint32_t)z * a.wblocks;
+        const int u = __builtin_amdgcn_readfirstlane(wb * kWavesPerBlock + (threadIdx.x >> 6));
+        if (u >= a.units.nunits) continue;                // wave-uniform
+        int line[2];
+        unit_lines(a.lines, a.units, a.H, a.W, u, line);
+        for (int part = 0; part < 2; ++part) {            // one copy of the line loop
+            if (line[part] < 0) break;
+            dense_line<K, LT, D, kPad>(a, z, locate(a.lines, a.H, a.W, line[part]), wst);
+        }
     }
 }
 
@@ -686,71 +750,13 @@ __global__ __launch_bounds__(256) void pix_meta_kernel(Src src) {
     }
 }
 
-// Work units of the 64-lane bounded SGM, one wave each.  Besides |W - H| + 1
-// lines of length M = min(H, W), a diagonal direction (|du| = |dv| = 1) has one
-// line of each length 1 .. M - 1 among its entry-row lines and one among its
-// entry-column lines.  Its units are the full lines alone and the pairs of
-// lengths m and M - m, run one after the other: every unit is M steps long, so
-// all the waves of the launch have the same work and none is left running
-// alone at the end.  Any other direction has one unit per line.
-__host__ __device__ inline bool paired_dir(int du, int dv) {
-    return (du == 1 || du == -1) && (dv == 1 || dv == -1);
-}
-
-__host__ __device__ inline int num_units(int H, int W, int du, int dv) {
-    return paired_dir(du, dv) ? max(H, W) : num_lines(H, W, du, dv);
-}
-
-struct Units {
-    int base[kMaxPaths + 1];       // direction r owns units [base[r], base[r+1])
-    int nunits;
-};
-
-Units make_units(const Lines& L, int H, int W) {
-    Units U{};
-    for (int r = 0; r < L.npaths; ++r)
-        U.base[r + 1] = U.base[r] + num_units(H, W, L.du[r], L.dv[r]);
-    U.nunits = U.base[L.npaths];
-    return U;
-}
-
-// The global lines of unit u (wave-uniform): line[0], and line[1] or -1.  In a
-// diagonal direction, entry-row line j is min(W - j', H) long, j' = j for du > 0
-// and W - 1 - j for du < 0, and entry-column line i (index W + i within the
-// direction) min(W, H - 1 - i).
-__device__ __forceinline__ void unit_lines(const Lines& L, const Units& U, int H, int W, int u,
-                                           int (&line)[2]) {
-    int r = 0, ub = 0, lb = 0, du = L.du[0], dv = L.dv[0];
-#pragma unroll
-    for (int i = 1; i < kMaxPaths; ++i)    // constant indices: the record stays in registers
-        if (i < L.npaths && u >= U.base[i]) {
-            r = i;
-            ub = U.base[i];
-            lb = L.base[i];
-            du = L.du[i];
-            dv = L.dv[i];
-        }
-    const int x = u - ub;
-    int first = x, second = -1;
-    if (paired_dir(du, dv)) {
-        if (x < W && du < 0) first = W - 1 - x;        // the row line of length min(W - x, H)
-        if (W >= H) {
-            if (x > W - H) second = 2 * W - 1 - x;      // lengths W - x and H - (W - x)
-        } else if (x >= 1 && x < W) {
-            second = W + H - 1 - x;                    // lengths W - x and x
-        }                                              // x >= W: a full column line
-    }
-    line[0] = lb + first;
-    line[1] = second < 0 ? -1 : lb + second;
-}
-
 struct BoundedArgs {
     gptr<const uint16_t> cost;
     gptr<const PixMeta> meta;
     gptr<uint16_t> Lbuf;           // [npaths][dir_stride]
     size_t dir_stride;
     Lines lines;
-    Units units;                   // of the 64-lane kernel
+    Units units;                   // of the 64-lane kernel (one line per wave)
     int H, W, N;
     uint32_t P1, P2;
 };
@@ -1203,7 +1209,8 @@ hipError_t stage_sgm_initial(Runner& r, const Jobs& jobs, int part) {
         d.NPc = NPc;
         d.P1 = (uint32_t)sp.P1;
         d.P2 = (uint32_t)sp.P2;
-        d.wblocks = div_up(d.lines.base[d.lines.npaths], kWavesPerBlock);
+        d.units = make_units(d.lines, H, W);
+        d.wblocks = div_up(d.units.nunits, kWavesPerBlock);
         const int K = (N + 63) / 64 - 1;
         const int v = lt == 0 && K <= 1 && bits + 2 * sp.P2 <= 255 + sp.P1 ? 2 : lt;
         dense[K][v].push_back(d);
