@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define LF_ABI_VERSION 5
+#define LF_ABI_VERSION 6
 #define LF_MAX_HYPOTHESES 256
 #define LF_MAX_SIDE 65536
 
@@ -318,17 +318,22 @@ typedef struct {
  * slices each cost workgroup walks (persistent workgroups); dense_prefetch: 4, 8
  * or 16 (default) -- path steps of cost loads in flight per wave in the initial
  * SGM, also the steps whose path costs it stages before copying them out;
- * bounded_prefetch: 4, 8 (default) or 16 -- pixel metadata steps in flight
+ * bounded_prefetch: 4 (default), 8 or 16 -- pixel metadata steps in flight
  * per wave in the bounded SGM with 64 lanes per line (their costs run half as
  * many steps ahead); bounded_lanes: 16, 32 or 64 (default) -- lanes per path line
  * of the bounded SGM (the wavefront-to-path schedule: 64/bounded_lanes lines per
- * wave, a line's range covered in chunks of that many hypotheses). */
+ * wave, a line's range covered in chunks of that many hypotheses);
+ * bounded_offsets: 32 (default) or 64 -- the bounded SGM with 64 lanes per line
+ * addresses its volumes with 32-bit offsets where their worst-case size is below
+ * 2^31 bytes and with 64-bit addresses otherwise; 64 takes the 64-bit form
+ * everywhere (the form of very large volumes, selectable for testing). */
 typedef struct {
     int32_t cost_cells_per_thread;
     int32_t cost_stride;
     int32_t dense_prefetch;
     int32_t bounded_prefetch;
     int32_t bounded_lanes;
+    int32_t bounded_offsets;
 } lf_tuning;
 
 typedef struct lf_plan lf_plan;

@@ -37,11 +37,13 @@ lf::Tuning to_tuning(const lf_tuning* t) {
     if (t->dense_prefetch) u.dense_depth = t->dense_prefetch;
     if (t->bounded_prefetch) u.bounded_depth = t->bounded_prefetch;
     if (t->bounded_lanes) u.bounded_lanes = t->bounded_lanes;
+    if (t->bounded_offsets) u.bounded_offsets = t->bounded_offsets;
     return u;
 }
 
 lf_tuning from_tuning(const lf::Tuning& u) {
-    return lf_tuning{u.cost_cpt, u.cost_stride, u.dense_depth, u.bounded_depth, u.bounded_lanes};
+    return lf_tuning{u.cost_cpt,      u.cost_stride,   u.dense_depth,
+                     u.bounded_depth, u.bounded_lanes, u.bounded_offsets};
 }
 
 bool valid_tuning(const lf::Tuning& u) {
@@ -50,7 +52,7 @@ bool valid_tuning(const lf::Tuning& u) {
     };
     return in(u.cost_cpt, {2, 4, 8}) && in(u.cost_stride, {1, 2, 4}) &&
            in(u.dense_depth, {4, 8, 16}) && in(u.bounded_depth, {4, 8, 16}) &&
-           in(u.bounded_lanes, {16, 32, 64});
+           in(u.bounded_lanes, {16, 32, 64}) && in(u.bounded_offsets, {32, 64});
 }
 
 }  // namespace

@@ -138,8 +138,9 @@ struct Tuning {
     int cost_cpt = 2;        // cells per thread of the bounded cost kernel (2, 4, 8)
     int cost_stride = 1;     // slices walked per cost workgroup (1, 2, 4)
     int dense_depth = 16;    // steps prefetched by the initial-stage SGM (4, 8, 16)
-    int bounded_depth = 8;   // steps prefetched by the bounded SGM, 64 lanes per line (4, 8, 16)
+    int bounded_depth = 4;   // steps prefetched by the bounded SGM, 64 lanes per line (4, 8, 16)
     int bounded_lanes = 64;  // lanes per path line of the bounded SGM (16, 32, 64)
+    int bounded_offsets = 32;  // 32: 32-bit offsets where volumes allow; 64: 64-bit always
 };
 
 // Stages of the method, in order (also the profiling buckets).

@@ -717,11 +717,19 @@ __global__ __launch_bounds__(256) void initial_export_kernel(Src src) {
 
 // ---------------------------------------------------------------------------
 // Final stage: CSR volume over per-pixel ranges [lo, hi].  Output Lbuf[r][cell].
-// meta[p] = {off[p] - lo[p] (int64), lo | hi << 16}: one 16-byte load per step.
+// meta[p] = {q = off[p] - lo[p] + N (int64, low half first), lo | hi << 16}: one
+// 16-byte load per step, or one 8-byte load of the first two words where 32-bit
+// offsets suffice.  Cell k of pixel p is q + k - N; q + k itself is positive for
+// every k >= 0 (off[p] >= 0, lo[p] < N), so it can serve as an unsigned offset
+// from N cells before the volume.
 struct alignas(16) PixMeta {
-    int64_t base;
+    uint32_t q_lo;
     int32_t lohi;
+    uint32_t q_hi;
     int32_t pad;
+    __device__ int64_t base(int N) const {   // off - lo
+        return (int64_t)(((uint64_t)q_hi << 32) | q_lo) - N;
+    }
 };
 
 struct MetaArgs {
@@ -743,8 +751,10 @@ __global__ __launch_bounds__(256) void pix_meta_kernel(Src src) {
         // only narrows a range, so its cells stay within the pixel's own
         const int lo = clampi(a.lo[p], 0, a.N - 1), hi = clampi(a.hi[p], lo, a.N - 1);
         PixMeta m;
-        m.base = a.off[p] - lo;
+        const uint64_t q = (uint64_t)(a.off[p] - lo + a.N);
+        m.q_lo = (uint32_t)q;
         m.lohi = (int32_t)((uint32_t)lo | ((uint32_t)hi << 16));
+        m.q_hi = (uint32_t)(q >> 32);
         m.pad = 0;
         a.meta[p] = m;
     }
@@ -782,7 +792,7 @@ __device__ __forceinline__ void bounded_line(const BoundedArgs& a, const LineInf
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             const int k = min(max(lane * K + j, lo), hi);
-            c[j] = cost[pm.base + k];
+            c[j] = cost[pm.base(a.N) + k];
         }
     };
     PixMeta mb[kMeta];
@@ -807,10 +817,8 @@ __device__ __forceinline__ void bounded_line(const BoundedArgs& a, const LineInf
                 const int k = lane * K + j;
                 C[j] = (k >= lo && k <= hi) ? cb[i % kCost][j] : kInf;
             }
-            // refill: costs for step + kCost (its meta arrived kMeta - kCost steps
-            // ago), then the meta slot for step + kMeta
+            // refill: costs for step + kCost (its meta arrived kMeta - kCost steps ago)
             load_cost(mb[(i + kCost) % kMeta], cb[i % kCost]);
-            mb[i] = load_meta(min(step + kMeta, li.len - 1));
             uint32_t L[K];
             if (step == 0) {
 #pragma unroll
@@ -823,15 +831,108 @@ __device__ __forceinline__ void bounded_line(const BoundedArgs& a, const LineInf
 #pragma unroll
             for (int j = 0; j < K; ++j) {
                 const int k = lane * K + j;
-                if (live && k >= lo && k <= hi) out[pm.base + k] = (uint16_t)L[j];
+                if (live && k >= lo && k <= hi) out[pm.base(a.N) + k] = (uint16_t)L[j];
             }
+            // the slot's metadata for step + kMeta, loaded after the last use of
+            // this step's (so the load can take the same registers: no copies,
+            // which would wait for every load in flight, at the loop's back edge)
+            mb[i] = load_meta(min(step + kMeta, li.len - 1));
 #pragma unroll
             for (int j = 0; j < K; ++j) Lp[j] = L[j];
         }
     }
 }
 
-template <class Src, int K, int D>
+// The same line loop with the cost volume, the pixel metadata and this
+// direction's path costs addressed through buffer descriptors, for volumes of
+// less than 2^31 bytes: 32-bit byte offsets instead of 64-bit addresses.  A
+// metadata load takes its pixel's offset as the scalar operand (no vector
+// arithmetic), a cost gather med3(k, lo, hi) and one shift-add, and a step's
+// stores one shift-add.  The descriptors start N cells before the volumes, so
+// that the offsets q + k are never negative (the store of a lane whose first
+// hypothesis lies below the range would otherwise start from a wrapped offset,
+// and the hardware drops a store whose vector offset is out of range).  A lane's
+// hypothesis k lies in [lo, hi] exactly when the clamp leaves it unchanged.
+template <int K, int D>
+__device__ __forceinline__ void bounded_line_buf(const BoundedArgs& a, const LineInfo& li) {
+    constexpr int kMeta = D, kCost = D / 2;   // two-stage prefetch
+    const int lane = threadIdx.x & 63;
+    const int W = a.W;
+    const uint32_t P1 = a.P1, P2 = a.P2;
+    const int32_t vol_bytes = (int32_t)((a.dir_stride + a.N) * 2);
+    const __amdgpu_buffer_rsrc_t rc = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)((const uint16_t*)a.cost - a.N), (short)0, vol_bytes, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rm = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(const PixMeta*)a.meta, (short)0, a.H * W * (int)sizeof(PixMeta), 0x00020000);
+    const __amdgpu_buffer_rsrc_t ro = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)((uint16_t*)a.Lbuf + (size_t)li.r * a.dir_stride - a.N), (short)0, vol_bytes,
+        0x00020000);
+    struct Meta {
+        uint32_t base, lohi;       // low 32 bits of q; lo | hi << 16
+    };
+    auto load_meta = [&](int step) -> Meta {
+        const int u = li.u0 + step * li.du, v = li.v0 + step * li.dv;
+        const auto x = __builtin_amdgcn_raw_buffer_load_b64(
+            rm, 0, (v * W + u) * (int)sizeof(PixMeta), 0);
+        return Meta{x[0], x[1]};
+    };
+    int kl[K];                                 // the lane's hypotheses
+#pragma unroll
+    for (int j = 0; j < K; ++j) kl[j] = lane * K + j;
+    // gather of the K costs of a pixel; hypotheses outside [lo, hi] read a cell
+    // of the pixel and are replaced by kInf when used
+    auto load_cost = [&](const Meta& pm, uint32_t (&c)[K]) {
+        const int lo = (int)(pm.lohi & 0xFFFF), hi = (int)(pm.lohi >> 16);
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const uint32_t k = (uint32_t)min(max(kl[j], lo), hi);
+            c[j] = __builtin_amdgcn_raw_buffer_load_b16(rc, (pm.base + k) << 1, 0, 0);
+        }
+    };
+    Meta mb[kMeta];
+    uint32_t cb[kCost][K];
+#pragma unroll
+    for (int i = 0; i < kMeta; ++i) mb[i] = load_meta(min(i, li.len - 1));
+#pragma unroll
+    for (int i = 0; i < kCost; ++i) load_cost(mb[i], cb[i]);
+
+    uint32_t Lp[K], m = 0;                     // step 0 reduces to L = C
+#pragma unroll
+    for (int j = 0; j < K; ++j) Lp[j] = 0;
+    for (int base = 0; base < li.len; base += kMeta) {
+#pragma unroll
+        for (int i = 0; i < kMeta; ++i) {
+            const int step = base + i;           // steps past the line end are computed
+            const Meta pm = mb[i];               // and not stored
+            const int lo = (int)(pm.lohi & 0xFFFF), hi = (int)(pm.lohi >> 16);
+            bool in[K];
+            uint32_t C[K];
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                in[j] = min(max(kl[j], lo), hi) == kl[j];
+                C[j] = in[j] ? cb[i % kCost][j] : kInf;
+            }
+            load_cost(mb[(i + kCost) % kMeta], cb[i % kCost]);
+            uint32_t L[K];
+            sgm_step<K>(Lp, m, P1, P2, C, L);   // with Lp = 0 and m = 0: L = C at step 0
+            m = wave_min(lane_min(L));
+            const bool live = step < li.len;
+            const uint32_t ob = (pm.base + (uint32_t)kl[0]) << 1;
+#pragma unroll
+            for (int j = 0; j < K; ++j)
+                if (live && in[j])
+                    __builtin_amdgcn_raw_buffer_store_b16((uint16_t)L[j], ro, ob, 2 * j, 0);
+            // the slot's metadata for step + kMeta, loaded after the last use of
+            // this step's (so the load can take the same registers: no copies,
+            // which would wait for every load in flight, at the loop's back edge)
+            mb[i] = load_meta(min(step + kMeta, li.len - 1));
+#pragma unroll
+            for (int j = 0; j < K; ++j) Lp[j] = L[j];
+        }
+    }
+}
+
+template <class Src, int K, int D, bool kBuf>
 __global__ __launch_bounds__(64 * kWavesPerBlock) void sgm_bounded_paths_kernel(Src src) {
     for (uint32_t vb = blockIdx.x; vb < src.total; vb += gridDim.x) {
         uint32_t b;
@@ -842,7 +943,10 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void sgm_bounded_paths_kernel(
         unit_lines(a.lines, a.units, a.H, a.W, u, line);
         for (int part = 0; part < 2; ++part) {        // one copy of the line loop
             if (line[part] < 0) break;
-            bounded_line<K, D>(a, locate(a.lines, a.H, a.W, line[part]));
+            if constexpr (kBuf)
+                bounded_line_buf<K, D>(a, locate(a.lines, a.H, a.W, line[part]));
+            else
+                bounded_line<K, D>(a, locate(a.lines, a.H, a.W, line[part]));
         }
     }
 }
@@ -917,7 +1021,7 @@ __device__ __forceinline__ void bounded_group_wave(const BoundedArgs& a, uint32_
 #pragma unroll
         for (int j = 0; j < KC; ++j) {
             const int k = lo + G * j + sub;
-            c[j] = k <= hi ? (uint32_t)cost[pm.base + k] : 0u;
+            c[j] = k <= hi ? (uint32_t)cost[pm.base(N) + k] : 0u;
         }
     };
 #pragma unroll
@@ -960,7 +1064,7 @@ __device__ __forceinline__ void bounded_group_wave(const BoundedArgs& a, uint32_
                         L = t + C[j] - m;
                     }
                     cur[k + 1] = L | ((uint32_t)step << 16);
-                    if (live) out[pm.base + k] = (uint16_t)L;
+                    if (live) out[pm.base(N) + k] = (uint16_t)L;
                     rmin = min(rmin, L);
                 }
             }
@@ -1059,20 +1163,30 @@ hipError_t dense_k(Runner& r, int K, int v, const std::vector<DenseArgs>& args,
     }
 }
 
+template <int K, int D>
+hipError_t bounded_depth_variant(Runner& r, const std::vector<BoundedArgs>& args,
+                                 const std::vector<uint32_t>& blocks, bool buf) {
+    if (buf)
+        return launch(r, kStSgmFinal, sgm_bounded_paths_kernel<Single<BoundedArgs>, K, D, true>,
+                      sgm_bounded_paths_kernel<Group<BoundedArgs>, K, D, true>, args, blocks,
+                      64 * kWavesPerBlock);
+    return launch(r, kStSgmFinal, sgm_bounded_paths_kernel<Single<BoundedArgs>, K, D, false>,
+                  sgm_bounded_paths_kernel<Group<BoundedArgs>, K, D, false>, args, blocks,
+                  64 * kWavesPerBlock);
+}
+
 template <int K>
 hipError_t bounded_variant(Runner& r, const std::vector<BoundedArgs>& args,
                            const std::vector<uint32_t>& blocks) {
-    if (r.tune.bounded_depth == 4)
-        return launch(r, kStSgmFinal, sgm_bounded_paths_kernel<Single<BoundedArgs>, K, 4>,
-                      sgm_bounded_paths_kernel<Group<BoundedArgs>, K, 4>, args, blocks,
-                      64 * kWavesPerBlock);
-    if (r.tune.bounded_depth == 8)
-        return launch(r, kStSgmFinal, sgm_bounded_paths_kernel<Single<BoundedArgs>, K, 8>,
-                      sgm_bounded_paths_kernel<Group<BoundedArgs>, K, 8>, args, blocks,
-                      64 * kWavesPerBlock);
-    return launch(r, kStSgmFinal, sgm_bounded_paths_kernel<Single<BoundedArgs>, K, 16>,
-                  sgm_bounded_paths_kernel<Group<BoundedArgs>, K, 16>, args, blocks,
-                  64 * kWavesPerBlock);
+    // 32-bit buffer offsets when every volume of the launch is below 2^31 bytes
+    bool buf = r.tune.bounded_offsets == 32;
+    for (const BoundedArgs& a : args)
+        buf = buf && (a.dir_stride + a.N) * 2 <= (size_t)INT32_MAX &&
+              (size_t)a.H * a.W * sizeof(PixMeta) <= (size_t)INT32_MAX;
+    const int d = r.tune.bounded_depth;
+    if (d == 4) return bounded_depth_variant<K, 4>(r, args, blocks, buf);
+    if (d == 8) return bounded_depth_variant<K, 8>(r, args, blocks, buf);
+    return bounded_depth_variant<K, 16>(r, args, blocks, buf);
 }
 
 template <int G, int KC>

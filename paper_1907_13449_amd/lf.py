@@ -87,7 +87,7 @@ class Request(C.Structure):
 class Tuning(C.Structure):
     _fields_ = [("cost_cells_per_thread", C.c_int32), ("cost_stride", C.c_int32),
                 ("dense_prefetch", C.c_int32), ("bounded_prefetch", C.c_int32),
-                ("bounded_lanes", C.c_int32)]
+                ("bounded_lanes", C.c_int32), ("bounded_offsets", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -420,7 +420,7 @@ def make_tuning(t: dict | None) -> Tuning | None:
         return None
     return Tuning(t.get("cost_cells_per_thread", 0), t.get("cost_stride", 0),
                   t.get("dense_prefetch", 0), t.get("bounded_prefetch", 0),
-                  t.get("bounded_lanes", 0))
+                  t.get("bounded_lanes", 0), t.get("bounded_offsets", 0))
 
 
 class Plan:

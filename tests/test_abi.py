@@ -57,7 +57,7 @@ def test_library_exports_every_declared_symbol(lf):
     for name in declared_functions():
         assert hasattr(lf.lib, name), name
     assert set(declared_functions()) == set(lf.EXPORTS)
-    assert lf.lib.lf_abi_version() == 5
+    assert lf.lib.lf_abi_version() == 6
 
 
 def test_struct_layouts_match_header(lf):
@@ -67,6 +67,8 @@ def test_struct_layouts_match_header(lf):
     assert C.sizeof(lf.ViewSet) == 8 + 7 * 4 + 4
     assert C.sizeof(lf.CensusWindow) == 3 * 4 + 2 * 64
     assert C.sizeof(lf.Params) == C.sizeof(lf.CensusWindow) + (3 + 3 + 3) * 4 + 2 * 4 + 4 * 4
+    # lf_tuning: 6 int32
+    assert C.sizeof(lf.Tuning) == 6 * 4
 
 
 def test_validate_hypotheses(lf):

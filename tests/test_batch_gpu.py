@@ -105,6 +105,7 @@ def test_batch_equals_alone(lf, items):
     dict(cost_cells_per_thread=2, dense_prefetch=4, bounded_prefetch=4, bounded_lanes=64),
     dict(cost_cells_per_thread=8, cost_stride=4, dense_prefetch=16, bounded_prefetch=8,
          bounded_lanes=64),
+    dict(bounded_prefetch=16, bounded_offsets=64),    # the 64-bit addressed bounded SGM
     dict(cost_cells_per_thread=4, cost_stride=2, dense_prefetch=8, bounded_lanes=32),
     dict(bounded_lanes=16),
 ])

@@ -63,10 +63,12 @@ def test_plan_create_rejects_bad_input(lf):
     assert st == lf.LF_EINVAL                      # unaligned workspace
     st = lf.lib.lf_plan_create(reqs, 1, C.c_void_p(FAKE), 1024, None, None, C.byref(h))
     assert st == lf.LF_ENOSPACE
-    t = lf.Tuning(3, 0, 0, 0)                      # 3 cells per thread is not offered
-    st = lf.lib.lf_plan_create(reqs, 1, C.c_void_p(FAKE), 1 << 30, C.byref(t), None, C.byref(h))
-    assert st == lf.LF_EINVAL
-    assert "tuning" in lf.lib.lf_last_error().decode()
+    for t in (lf.Tuning(3, 0, 0, 0),               # 3 cells per thread is not offered
+              lf.Tuning(0, 0, 0, 0, 0, 48)):       # nor 48-bit offsets
+        st = lf.lib.lf_plan_create(reqs, 1, C.c_void_p(FAKE), 1 << 30, C.byref(t), None,
+                                   C.byref(h))
+        assert st == lf.LF_EINVAL
+        assert "tuning" in lf.lib.lf_last_error().decode()
 
 
 def test_server_config_checks(lf):
