@@ -424,6 +424,54 @@ def summarize_units(sq_csv, ta_csv, td_csv, commands):
     return "\n".join(md)
 
 
+def summarize_stalls(sq_csv, commands):
+    """Markdown of where each kernel's waves spend their cycles, from one rocprofv3
+    --pmc run of SQ_WAVE_CYCLES SQ_WAIT_ANY SQ_WAIT_INST_ANY SQ_ACTIVE_INST_VALU
+    SQ_ACTIVE_INST_VMEM SQ_INST_LEVEL_VMEM SQ_VMEM_TA_ADDR_FIFO_FULL
+    SQ_VMEM_TA_CMD_FIFO_FULL (medians over each kernel's dispatches).  Each wave
+    counter is divided by SQ_WAVE_CYCLES: SQ_WAIT_ANY counts wave cycles spent in
+    s_waitcnt (waiting for memory), SQ_WAIT_INST_ANY wave cycles with an
+    instruction ready but not issued (its unit or the issue slot taken by another
+    wave), SQ_ACTIVE_INST_* wave cycles issuing that kind, and SQ_INST_LEVEL_VMEM /
+    SQ_WAVE_CYCLES a relative measure of its vector-memory instructions in flight."""
+    import csv
+    import statistics
+    vals = {}
+    for r in csv.DictReader(open(sq_csv)):
+        if "lf::" not in r["Kernel_Name"]:
+            continue
+        key = (r["Dispatch_Id"], r["Kernel_Name"], r["Counter_Name"])
+        vals[key] = vals.get(key, 0.0) + float(r["Counter_Value"])
+    acc = {}
+    for (d, n, c), v in vals.items():
+        acc.setdefault(_short_kernel(n)[0], {}).setdefault(c, []).append(v)
+    med = {k: {c: statistics.median(v) for c, v in cs.items()} for k, cs in acc.items()}
+    rows = []
+    for k, m in med.items():
+        wc = m.get("SQ_WAVE_CYCLES", 0.0)
+        if wc <= 0:
+            continue
+        rows.append((wc, k, *(m.get(c, 0.0) / wc for c in (
+            "SQ_WAIT_ANY", "SQ_WAIT_INST_ANY", "SQ_ACTIVE_INST_VALU", "SQ_ACTIVE_INST_VMEM",
+            "SQ_INST_LEVEL_VMEM")),
+            m.get("SQ_VMEM_TA_ADDR_FIFO_FULL", 0.0) + m.get("SQ_VMEM_TA_CMD_FIFO_FULL", 0.0)))
+    md = ["Command (from the repository root, on one MI355X):", ""]
+    md += [f"    {c}" for c in commands]
+    md += ["", "Sources: " + ", ".join(f"{k} {v}" for k, v in current_sources().items()) +
+           " (sha256, 16 hex).", "",
+           "Fractions of the kernel's wave cycles (medians over its dispatches): waiting in "
+           "s_waitcnt (SQ_WAIT_ANY), ready but not issued (SQ_WAIT_INST_ANY), issuing VALU / "
+           "vector-memory instructions (SQ_ACTIVE_INST_VALU / _VMEM); SQ_INST_LEVEL_VMEM / SQ_WAVE_CYCLES, a "
+           "relative measure of vector-memory instructions in flight (for comparing kernels); "
+           "cycles the texture address unit's FIFOs were full (ADDR + CMD).", "",
+           "| kernel | wave cycles (M) | s_waitcnt | not issued | VALU | VMEM | VMEM level "
+           "| TA FIFO full |", "|---|---:|---:|---:|---:|---:|---:|---:|"]
+    for r in sorted(rows, reverse=True):
+        md.append(f"| {r[1]} | {r[0] / 1e6:.1f} | {r[2]:.2f} | {r[3]:.2f} | {r[4]:.2f} | "
+                  f"{r[5]:.2f} | {r[6]:.2f} | {r[7]:.3g} |")
+    return "\n".join(md)
+
+
 def summarize_plan_gaps(trace_csv, command):
     """Markdown of a rocprofv3 --kernel-trace of --replay-plan: per replay of the
     captured plan, its liblf kernels, the span from the first start to the last
@@ -875,6 +923,9 @@ def main():
                     help="only build the batched workload's plan and replay it 3 times")
     ap.add_argument("--summarize-plan-gaps", nargs=2, metavar=("TRACE_CSV", "COMMAND"),
                     help="print a markdown summary of a kernel trace of --replay-plan and exit")
+    ap.add_argument("--summarize-stalls", nargs=2, metavar=("SQ_CSV", "TITLE"),
+                    help="print the markdown wave-cycle breakdown of an SQ stall counter run "
+                         "(see summarize_stalls) and exit")
     ap.add_argument("--summarize-units", nargs=4, metavar=("SQ_CSV", "TA_CSV", "TD_CSV", "TITLE"),
                     help="print a markdown table of per-kernel unit utilisation from three "
                          "rocprofv3 --pmc runs (see summarize_units) and exit")
@@ -886,6 +937,10 @@ def main():
         return
     if args.summarize_plan_gaps:
         print(summarize_plan_gaps(*args.summarize_plan_gaps))
+        return
+    if args.summarize_stalls:
+        sq, title = args.summarize_stalls
+        print(f"# {title}\n\n" + summarize_stalls(sq, args.commands))
         return
     if args.summarize_units:
         sq, ta, td, title = args.summarize_units
