@@ -205,6 +205,41 @@ def test_bounded_sgm_bit_exact_on_identical_costs(lfo, results, name):
     assert np.array_equal(csum[mask], ref[mask])
 
 
+@pytest.mark.parametrize("H,W,N,npaths,sum_bits", [
+    (13, 17, 256, 8, 32),     # four hypotheses per lane
+    (11, 19, 100, 8, 32),     # two
+    (9, 23, 150, 16, 32),     # three, knight moves
+    (17, 12, 64, 8, 16),      # one, 16-bit sums
+])
+def test_bounded_sgm_ranges_far_from_zero(lf, lfo, H, W, N, npaths, sum_bits):
+    # Ranges near the top of the hypothesis set from the first pixel on (off - lo < 0
+    # there), single hypotheses, full ranges and ranges that start or end at a
+    # lane boundary, on random costs: the bounded SGM's cell addressing against the
+    # oracle's C_s of Eq. (8)-(9) on identical costs.
+    rng = np.random.default_rng(H * W + N)
+    kind = rng.integers(0, 4, size=(H, W))
+    lo = np.where(kind == 0, rng.integers(N - 24, N, size=(H, W)),
+                  np.where(kind == 1, 0, rng.integers(0, N, size=(H, W))))
+    hi = np.where(kind == 1, N - 1, np.minimum(N - 1, lo + rng.integers(0, 24, size=(H, W))))
+    hi = np.where(kind == 3, lo, hi)                         # single hypotheses
+    lo[0, 0], hi[0, 0] = N - 7, N - 1                          # the first pixel high up
+    lo, hi = lo.astype(np.int16), hi.astype(np.int16)
+    widths = hi.astype(np.int64) - lo + 1
+    off = np.concatenate([[0], np.cumsum(widths.reshape(-1))]).astype(np.int64)
+    cap = lfo.cost_cap(8 * 6, npaths, sum_bits)
+    cost = rng.integers(0, min(cap, 90) + 1, size=int(off[-1])).astype(np.uint16)
+    say("bounded ranges", H, W, N, npaths, sum_bits)
+    dev = "cuda"
+    csum = lf.lf_sgm_aggregate(torch.from_numpy(cost.view(np.int16)).to(dev),
+                               torch.from_numpy(off).to(dev), torch.from_numpy(lo).to(dev),
+                               torch.from_numpy(hi).to(dev), N, 6, 8 * 6, npaths, sum_bits)
+    got = csum.cpu().numpy().view(np.uint16 if sum_bits == 16 else np.uint32)
+    dense, mask = _csr_to_dense(cost, off, lo, hi, N, np.int32)
+    ref = lfo.sgm(dense, 6, 8 * 6, npaths, lo=lo, hi=hi)
+    gd, _ = _csr_to_dense(got, off, lo, hi, N, np.int64)
+    assert np.array_equal(gd[mask], ref[mask])
+
+
 @pytest.mark.parametrize("name", CASES)
 def test_wta_subpixel_median_bit_exact(results, name):
     lfd, g, o = results[name]
