@@ -53,7 +53,7 @@ typedef enum {
     LF_EINVAL = -1,        /* invalid argument (nothing enqueued) */
     LF_ENOSPACE = -2,      /* a caller buffer or the workspace is too small */
     LF_EDEVICE = -3,       /* a HIP call or kernel launch failed */
-    LF_EUNSUPPORTED = -4,  /* valid, but outside what this build implements */
+    LF_EUNSUPPORTED = -4,  /* valid, but outside what the library implements */
     LF_EBUSY = -5,         /* a queue is full or the object is in use; retry later */
     LF_ETIMEOUT = -6,      /* a wait ended before the work did */
     LF_ECANCELED = -7      /* the work was dropped before it ran */

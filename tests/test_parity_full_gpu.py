@@ -49,7 +49,7 @@ def _run(name):
     print("  GPU done; oracle running", flush=True)
     o = oracle.depth(lfd.views, lfd.hyp, p, want_intermediates=True, want_initial_volumes=True)
     print("  oracle done", flush=True)
-    # compared here, and only the verdicts kept (several GB at the largest shape)
+    # compared here, and only the outcomes kept (several GB at the largest shape)
     g["init_cost_equal"] = bool(np.array_equal(ccv, o.pop("init_cost")))
     g["init_csum_equal"] = bool(np.array_equal(csum, o.pop("init_csum")))
     del ccv, csum

@@ -142,7 +142,7 @@ def results(lf, lfo):
                  d_index=wta["d_index"].cpu().numpy(), disp=wta["disparity"].cpu().numpy(),
                  depth=full.cpu().numpy())
         o = lfo.depth(lfd.views, lfd.hyp, p, want_intermediates=True, want_initial_volumes=True)
-        # the initial volumes are compared here and only the verdicts kept (they are
+        # the initial volumes are compared here and only the outcomes kept (they are
         # |V| H W N each, the largest cases' dominate the memory otherwise)
         g["init_cost_equal"] = np.array_equal(ini["census_cost"].cpu().numpy().astype(np.int32),
                                               o.pop("init_cost"))
